@@ -1,0 +1,529 @@
+/*
+ * oracle.c -- plain, slow, single-threaded FP64 CPU reference of one explicit
+ * electromagnetic particle-in-cell step (KEMPIC-3D, arXiv 2609.16575).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; it shares no header, helper, table or kernel with the
+ * HIP path.  Only the tests, the smoke check and the CPU baseline leg of the
+ * benchmark load it (through oracle/oracle.py).
+ *
+ * Everything is written as loops over the definitions, in the order the paper
+ * gives them (Sec. 2.2, Fig. "PIC algorithm"): Faraday -> temporal centring of
+ * B -> staggered CIC gather -> relativistic Boris push -> ZigZag current
+ * deposit -> Ampere-Maxwell -> boundaries.  Units: c = eps0 = mu0 = 1, which
+ * is what the bare "- dt J" term of the Ampere-Maxwell update implies.
+ *
+ * Grid layout (shared convention, not shared code): arrays are [k][j][i],
+ * x fastest, with `ext[a] = n[a] + (absorbing ? 1 : 0)` entries per axis.
+ * Component locations in cell units:
+ *   Ex(i+1/2, j, k)  Ey(i, j+1/2, k)  Ez(i, j, k+1/2)     J like E
+ *   Bx(i, j+1/2, k+1/2)  By(i+1/2, j, k+1/2)  Bz(i+1/2, j+1/2, k)
+ *   rho at nodes (i, j, k).
+ *
+ * Readings of points the paper leaves open are marked READING below.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PERIODIC 0
+#define ORC_ABSORBING 1
+
+typedef struct {
+    int32_t n[3];  /* cells per axis */
+    int32_t bc[3]; /* ORC_PERIODIC or ORC_ABSORBING, per axis */
+    double d[3];   /* cell size */
+    double dt;     /* time step */
+} orc_grid;
+
+typedef struct {
+    double a0;      /* peak field amplitude (normalised vector potential) */
+    double w0;      /* 1/e field waist */
+    double tau;     /* intensity FWHM duration */
+    double t0;      /* time of the envelope peak */
+    double omega0;  /* carrier frequency */
+    double yc, zc;  /* transverse centre of the spot */
+    int32_t i_s;    /* x node index of the current sheet */
+    int32_t pad;
+} orc_laser;
+
+/* ------------------------------------------------------------------------ */
+/* indexing helpers                                                          */
+/* ------------------------------------------------------------------------ */
+
+static int64_t ext_of(const orc_grid *g, int a) {
+    return (int64_t)g->n[a] + (g->bc[a] == ORC_ABSORBING ? 1 : 0);
+}
+
+static int64_t vol_of(const orc_grid *g) {
+    return ext_of(g, 0) * ext_of(g, 1) * ext_of(g, 2);
+}
+
+/* Linear index of (i,j,k); periodic axes wrap, absorbing axes return -1 when
+ * the point lies outside the stored array. */
+static int64_t at(const orc_grid *g, int64_t i, int64_t j, int64_t k) {
+    int64_t p[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a) {
+        int64_t e = ext_of(g, a);
+        if (g->bc[a] == ORC_PERIODIC) {
+            int64_t n = g->n[a];
+            p[a] = ((p[a] % n) + n) % n;
+        } else if (p[a] < 0 || p[a] >= e) {
+            return -1;
+        }
+    }
+    return p[0] + ext_of(g, 0) * (p[1] + ext_of(g, 1) * p[2]);
+}
+
+/* Stagger of E_c and B_c along axis a: 1 = half-integer position, 0 = node. */
+static int stag_E(int c, int a) { return a == c ? 1 : 0; }
+static int stag_B(int c, int a) { return a == c ? 0 : 1; }
+
+/* Number of stored values of a component along axis a: periodic axes hold n,
+ * absorbing axes hold n+1 node values or n half-cell values. */
+static int64_t count_along(const orc_grid *g, int a, int half) {
+    if (g->bc[a] == ORC_PERIODIC) return g->n[a];
+    return half ? g->n[a] : (int64_t)g->n[a] + 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.3, Yee FDTD.  Faraday: the B_x equation of the paper, the other two  */
+/* components by cyclic permutation of (x, y, z).                             */
+/* B^{n+1/2} = B^{n-1/2} - dt curl E^n, forward differences.                  */
+/* Also writes the time-centred field of Sec. 2.5 (Eq. "B centred"):          */
+/* Bbar^n = (B^{n-1/2} + B^{n+1/2}) / 2.                                      */
+/* READING: the paper's "half step" wording and the full-step equation agree  */
+/* in exact arithmetic once B is centred by averaging; the full step plus     */
+/* average is taken.                                                          */
+/* ------------------------------------------------------------------------ */
+void orc_faraday(const orc_grid *g, const double *E, double *B, double *Bbar) {
+    const int64_t V = vol_of(g);
+    for (int c = 0; c < 3; ++c) {
+        const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        int64_t cnt[3];
+        for (int a = 0; a < 3; ++a) cnt[a] = count_along(g, a, stag_B(c, a));
+        for (int64_t k = 0; k < cnt[2]; ++k)
+            for (int64_t j = 0; j < cnt[1]; ++j)
+                for (int64_t i = 0; i < cnt[0]; ++i) {
+                    int64_t p[3] = {i, j, k};
+                    int64_t q1[3] = {i, j, k}, q2[3] = {i, j, k};
+                    q1[a1] += 1; /* +1 along a1 */
+                    q2[a2] += 1; /* +1 along a2 */
+                    const int64_t ip = at(g, p[0], p[1], p[2]);
+                    const int64_t i1 = at(g, q1[0], q1[1], q1[2]);
+                    const int64_t i2 = at(g, q2[0], q2[1], q2[2]);
+                    /* (curl E)_c = d_{a1} E_{a2} - d_{a2} E_{a1} */
+                    const double curl = (E[a2 * V + i1] - E[a2 * V + ip]) / g->d[a1] -
+                                        (E[a1 * V + i2] - E[a1 * V + ip]) / g->d[a2];
+                    const double old = B[c * V + ip];
+                    const double nw = old - g->dt * curl;
+                    B[c * V + ip] = nw;
+                    if (Bbar) Bbar[c * V + ip] = 0.5 * (old + nw);
+                }
+    }
+}
+
+/* Is the E_c value at (i,j,k) on a face of an absorbing axis where it is a   */
+/* tangential component (its update then belongs to the boundary condition)? */
+static int e_on_absorbing_face(const orc_grid *g, int c, const int64_t p[3]) {
+    for (int a = 0; a < 3; ++a) {
+        if (a == c || g->bc[a] != ORC_ABSORBING) continue;
+        if (p[a] == 0 || p[a] == g->n[a]) return 1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.3, Ampere-Maxwell: the E_x equation of the paper and its cyclic      */
+/* permutations.  E^{n+1} = E^n + dt curl B^{n+1/2} - dt J^{n+1/2}, backward   */
+/* differences.  Tangential E on absorbing faces is left to orc_mur.          */
+/* ------------------------------------------------------------------------ */
+void orc_ampere(const orc_grid *g, double *E, const double *B, const double *J) {
+    const int64_t V = vol_of(g);
+    for (int c = 0; c < 3; ++c) {
+        const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+        int64_t cnt[3];
+        for (int a = 0; a < 3; ++a) cnt[a] = count_along(g, a, stag_E(c, a));
+        for (int64_t k = 0; k < cnt[2]; ++k)
+            for (int64_t j = 0; j < cnt[1]; ++j)
+                for (int64_t i = 0; i < cnt[0]; ++i) {
+                    int64_t p[3] = {i, j, k};
+                    if (e_on_absorbing_face(g, c, p)) continue;
+                    int64_t q1[3] = {i, j, k}, q2[3] = {i, j, k};
+                    q1[a1] -= 1;
+                    q2[a2] -= 1;
+                    const int64_t ip = at(g, p[0], p[1], p[2]);
+                    const int64_t i1 = at(g, q1[0], q1[1], q1[2]);
+                    const int64_t i2 = at(g, q2[0], q2[1], q2[2]);
+                    /* (curl B)_c = d_{a1} B_{a2} - d_{a2} B_{a1} */
+                    const double curl = (B[a2 * V + ip] - B[a2 * V + i1]) / g->d[a1] -
+                                        (B[a1 * V + ip] - B[a1 * V + i2]) / g->d[a2];
+                    E[c * V + ip] += g->dt * curl - g->dt * (J ? J[c * V + ip] : 0.0);
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boundaries (Sec. 2.2 lists a boundary module; its kind is not given).      */
+/* READING: first-order Mur absorbing condition (Mur 1981) on tangential E at */
+/* every face of an absorbing axis, c = 1:                                    */
+/*   E_0^{n+1} = E_1^n + (dt - d)/(dt + d) (E_1^{n+1} - E_0^n)                */
+/* and the mirror formula at the far face.  Axes are processed x, then y,     */
+/* then z; an edge value shared by two faces ends with the later axis.        */
+/* E_old is a copy of E^n taken before orc_ampere.                            */
+/* ------------------------------------------------------------------------ */
+void orc_mur(const orc_grid *g, double *E, const double *E_old) {
+    const int64_t V = vol_of(g);
+    for (int a = 0; a < 3; ++a) {
+        if (g->bc[a] != ORC_ABSORBING) continue;
+        const double coef = (g->dt - g->d[a]) / (g->dt + g->d[a]);
+        const int64_t n = g->n[a];
+        for (int c = 0; c < 3; ++c) {
+            if (c == a) continue;
+            int64_t cnt[3];
+            for (int b = 0; b < 3; ++b) cnt[b] = count_along(g, b, stag_E(c, b));
+            cnt[a] = 1; /* iterate the face plane only */
+            for (int64_t k = 0; k < cnt[2]; ++k)
+                for (int64_t j = 0; j < cnt[1]; ++j)
+                    for (int64_t i = 0; i < cnt[0]; ++i) {
+                        for (int side = 0; side < 2; ++side) {
+                            int64_t p0[3] = {i, j, k}, p1[3] = {i, j, k};
+                            p0[a] = side ? n : 0;
+                            p1[a] = side ? n - 1 : 1;
+                            const int64_t b0 = at(g, p0[0], p0[1], p0[2]);
+                            const int64_t b1 = at(g, p1[0], p1[1], p1[2]);
+                            E[c * V + b0] = E_old[c * V + b1] +
+                                            coef * (E[c * V + b1] - E_old[c * V + b0]);
+                        }
+                    }
+        }
+    }
+}
+
+/* READING (laser injection, configuration with a0 = 2): a soft current sheet */
+/* J_y on the x-node plane i_s radiating the incident field                   */
+/*   E_inc = a0 exp(-r^2/w0^2) exp(-2 ln2 (t-t0)^2/tau^2) sin(omega0 (t-t0))   */
+/* in both directions (K = -2 E_inc, J = K/dx); the backward half is absorbed */
+/* by the x = 0 face.  Applied to E after Ampere as -dt * J_sheet at         */
+/* t = t^{n+1/2}.                                                              */
+double orc_laser_field(const orc_laser *L, double t, double y, double z) {
+    const double r2 = (y - L->yc) * (y - L->yc) + (z - L->zc) * (z - L->zc);
+    const double tt = t - L->t0;
+    return L->a0 * exp(-r2 / (L->w0 * L->w0)) *
+           exp(-2.0 * log(2.0) * tt * tt / (L->tau * L->tau)) * sin(L->omega0 * tt);
+}
+
+void orc_laser_apply(const orc_grid *g, double *E, const orc_laser *L, double t_half) {
+    const int64_t V = vol_of(g);
+    int64_t cnt[3];
+    for (int b = 0; b < 3; ++b) cnt[b] = count_along(g, b, stag_E(1, b));
+    for (int64_t k = 0; k < cnt[2]; ++k)
+        for (int64_t j = 0; j < cnt[1]; ++j) {
+            int64_t p[3] = {L->i_s, j, k};
+            if (e_on_absorbing_face(g, 1, p)) continue;
+            const double y = ((double)j + 0.5) * g->d[1];
+            const double z = (double)k * g->d[2];
+            const double Jy = -2.0 * orc_laser_field(L, t_half, y, z) / g->d[0];
+            const int64_t ip = at(g, p[0], p[1], p[2]);
+            if (ip >= 0) E[V + ip] -= g->dt * Jy;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.5: staggered CIC (trilinear) gather.  Each component is            */
+/* interpolated from its own Yee sub-grid: per axis t = xi - s (s = 0 or 1/2), */
+/* i0 = floor(t), weight of i0+1 is t - i0.  Points outside an absorbing      */
+/* axis' array contribute zero.                                               */
+/* ------------------------------------------------------------------------ */
+static double gather_one(const orc_grid *g, const double *F, const int stag[3],
+                         const double xi[3]) {
+    int64_t i0[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        const double t = xi[a] - 0.5 * stag[a];
+        const double fl = floor(t);
+        i0[a] = (int64_t)fl;
+        f[a] = t - fl;
+    }
+    double s = 0.0;
+    for (int oz = 0; oz < 2; ++oz)
+        for (int oy = 0; oy < 2; ++oy)
+            for (int ox = 0; ox < 2; ++ox) {
+                const int64_t ip = at(g, i0[0] + ox, i0[1] + oy, i0[2] + oz);
+                if (ip < 0) continue;
+                const double w = (ox ? f[0] : 1.0 - f[0]) * (oy ? f[1] : 1.0 - f[1]) *
+                                 (oz ? f[2] : 1.0 - f[2]);
+                s += w * F[ip];
+            }
+    return s;
+}
+
+void orc_gather(const orc_grid *g, const double *E, const double *Bbar, const double pos[3],
+                double Ep[3], double Bp[3]) {
+    const int64_t V = vol_of(g);
+    double xi[3];
+    for (int a = 0; a < 3; ++a) xi[a] = pos[a] / g->d[a];
+    for (int c = 0; c < 3; ++c) {
+        int se[3], sb[3];
+        for (int a = 0; a < 3; ++a) {
+            se[a] = stag_E(c, a);
+            sb[a] = stag_B(c, a);
+        }
+        Ep[c] = gather_one(g, E + c * V, se, xi);
+        Bp[c] = gather_one(g, Bbar + c * V, sb, xi);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.4: relativistic Boris push (Boris 1970).  u = gamma v (c = 1),      */
+/* r = q dt / (2 m).  Half electric kick, magnetic rotation, half kick.       */
+/* READING: the rotation is described in words only; the standard t/s form   */
+/* is used: t = r B / gamma^-, s = 2 t / (1 + t.t).                           */
+/* ------------------------------------------------------------------------ */
+void orc_boris(double u[3], const double Ep[3], const double Bp[3], double r) {
+    double um[3], t[3], s[3], up[3], upl[3];
+    for (int a = 0; a < 3; ++a) um[a] = u[a] + r * Ep[a];
+    const double gm = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    for (int a = 0; a < 3; ++a) t[a] = r * Bp[a] / gm;
+    const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    for (int a = 0; a < 3; ++a) s[a] = 2.0 * t[a] / (1.0 + tt);
+    /* u' = u- + u- x t */
+    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+    /* u+ = u- + u' x s */
+    upl[0] = um[0] + (up[1] * s[2] - up[2] * s[1]);
+    upl[1] = um[1] + (up[2] * s[0] - up[0] * s[2]);
+    upl[2] = um[2] + (up[0] * s[1] - up[1] * s[0]);
+    for (int a = 0; a < 3; ++a) u[a] = upl[a] + r * Ep[a];
+}
+
+/* Single particle in prescribed uniform fields (Sec. 3.1 benchmarks): nsteps */
+/* Boris pushes and position updates x += dt u/gamma.  traj (nullable) gets   */
+/* the position after each step, 3 per step.                                  */
+void orc_particle_uniform(double r, const double E[3], const double B[3], double dt,
+                          int64_t nsteps, double x[3], double u[3], double *traj) {
+    for (int64_t s = 0; s < nsteps; ++s) {
+        orc_boris(u, E, B, r);
+        const double gm = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        for (int a = 0; a < 3; ++a) x[a] += dt * u[a] / gm;
+        if (traj)
+            for (int a = 0; a < 3; ++a) traj[3 * s + a] = x[a];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.5: ZigZag charge-conserving current deposit (Umeda et al. 2003).   */
+/* Per axis, in cell units: i1 = floor(xi1), i2 = floor(xi2), relay point     */
+/*   xr = min(min(i1,i2)+1, max(max(i1,i2), (xi1+xi2)/2)).                    */
+/* The move is split into segment A (xi1 -> xr) inside cell i1 and segment B  */
+/* (xr -> xi2) inside cell i2.  Each straight segment inside one cell          */
+/* deposits on the 12 edges of that cell.                                     */
+/* READING: the paper does not print the 3D weights.  The line integral of    */
+/* the bilinear CIC weights along the straight segment is used:               */
+/*   J_a(edge o_b, o_c) += q dx_a/(dt dV) * d_a * [w_b(o_b) w_c(o_c)          */
+/*                                     + sgn dxi_b dxi_c / 12]                 */
+/* with w(0) = 1 - W, w(1) = W, W the segment midpoint relative to the cell,  */
+/* sgn = +1 when o_b == o_c else -1.  midpoint_only = 1 drops the /12 term    */
+/* (the literal midpoint-product weights of the 2D derivation).               */
+/* ------------------------------------------------------------------------ */
+static void add_edge(const orc_grid *g, double *J, int c, int64_t i, int64_t j, int64_t k,
+                     double v) {
+    const int64_t ip = at(g, i, j, k);
+    if (ip < 0) return; /* absorbing axis: edge outside the array */
+    int64_t p[3] = {i, j, k};
+    /* an absorbing axis' half-cell components stop at index n-1 */
+    for (int a = 0; a < 3; ++a)
+        if (g->bc[a] == ORC_ABSORBING && stag_E(c, a) && p[a] >= g->n[a]) return;
+    J[c * vol_of(g) + ip] += v;
+}
+
+static void deposit_segment(const orc_grid *g, double *J, const int64_t cell[3],
+                            const double s[3], const double e[3], double qsp,
+                            int midpoint_only) {
+    const double dV = g->d[0] * g->d[1] * g->d[2];
+    double dxi[3], W[3];
+    for (int a = 0; a < 3; ++a) {
+        dxi[a] = e[a] - s[a];
+        W[a] = 0.5 * (s[a] + e[a]) - (double)cell[a];
+    }
+    for (int c = 0; c < 3; ++c) {
+        const int b1 = (c + 1) % 3, b2 = (c + 2) % 3;
+        const double amp = qsp * dxi[c] * g->d[c] / (g->dt * dV);
+        const double cross = midpoint_only ? 0.0 : dxi[b1] * dxi[b2] / 12.0;
+        for (int o2 = 0; o2 < 2; ++o2)
+            for (int o1 = 0; o1 < 2; ++o1) {
+                const double w1 = o1 ? W[b1] : 1.0 - W[b1];
+                const double w2 = o2 ? W[b2] : 1.0 - W[b2];
+                const double sg = (o1 == o2) ? 1.0 : -1.0;
+                int64_t p[3] = {cell[0], cell[1], cell[2]};
+                p[b1] += o1;
+                p[b2] += o2;
+                add_edge(g, J, c, p[0], p[1], p[2], amp * (w1 * w2 + sg * cross));
+            }
+    }
+}
+
+void orc_zigzag(const orc_grid *g, double *J, const double xi1[3], const double xi2[3],
+                double qsp, int midpoint_only) {
+    int64_t c1[3], c2[3];
+    double xr[3];
+    for (int a = 0; a < 3; ++a) {
+        const int64_t i1 = (int64_t)floor(xi1[a]);
+        const int64_t i2 = (int64_t)floor(xi2[a]);
+        const double lo = (double)((i1 < i2 ? i1 : i2) + 1);
+        const double hi = (double)(i1 > i2 ? i1 : i2);
+        const double mid = 0.5 * (xi1[a] + xi2[a]);
+        xr[a] = fmin(lo, fmax(hi, mid));
+        c1[a] = i1;
+        c2[a] = i2;
+    }
+    deposit_segment(g, J, c1, xi1, xr, qsp, midpoint_only);
+    deposit_segment(g, J, c2, xr, xi2, qsp, midpoint_only);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One species through gather -> Boris -> move -> ZigZag (Sec. 2.2 order).   */
+/* pos: 3*np global positions x^n (in [0, L)), u: 3*np momenta u^{n-1/2}     */
+/* (gamma v); both rewritten to x^{n+1}, u^{n+1/2}.  alive (nullable) marks   */
+/* particles removed by an absorbing face.  wpp (nullable) per-particle       */
+/* macro weight, else w.  q_sp = q w, m_sp = m w (Sec. 2.1).  dry = 1 only    */
+/* gathers and pushes a copy of u to accumulate the kinetic energy of         */
+/* u^{n+1/2} (nothing is written).  kin (nullable) += sum w m (gamma - 1) of  */
+/* the pushed momenta.                                                        */
+/* ------------------------------------------------------------------------ */
+void orc_push_deposit(const orc_grid *g, const double *E, const double *Bbar, double *J,
+                      int64_t np, double *pos, double *u, int8_t *alive, const double *wpp,
+                      double q, double m, double w, int midpoint_only, int dry, double *kin) {
+    const double r = q * g->dt / (2.0 * m);
+    double L[3];
+    for (int a = 0; a < 3; ++a) L[a] = g->n[a] * g->d[a];
+    double ksum = 0.0;
+    for (int64_t p = 0; p < np; ++p) {
+        if (alive && !alive[p]) continue;
+        const double wp = wpp ? wpp[p] : w;
+        double Ep[3], Bp[3], un[3];
+        orc_gather(g, E, Bbar, pos + 3 * p, Ep, Bp);
+        for (int a = 0; a < 3; ++a) un[a] = u[3 * p + a];
+        orc_boris(un, Ep, Bp, r);
+        const double uu = un[0] * un[0] + un[1] * un[1] + un[2] * un[2];
+        const double gm = sqrt(1.0 + uu);
+        ksum += wp * m * uu / (gm + 1.0); /* gamma - 1 = u.u / (gamma + 1) */
+        if (dry) continue;
+        double xi1[3], xi2[3];
+        for (int a = 0; a < 3; ++a) {
+            xi1[a] = pos[3 * p + a] / g->d[a];
+            xi2[a] = xi1[a] + g->dt * un[a] / (gm * g->d[a]);
+        }
+        if (J) orc_zigzag(g, J, xi1, xi2, q * wp, midpoint_only);
+        for (int a = 0; a < 3; ++a) {
+            u[3 * p + a] = un[a];
+            double x = pos[3 * p + a] + g->dt * un[a] / gm;
+            if (g->bc[a] == ORC_PERIODIC) {
+                if (x >= L[a]) x -= L[a];
+                if (x < 0.0) {
+                    x += L[a];
+                    if (x >= L[a]) x = 0.0;
+                }
+            } else if (x < 0.0 || x >= L[a]) {
+                if (alive) alive[p] = 0;
+            }
+            pos[3 * p + a] = x;
+        }
+    }
+    if (kin) *kin += ksum;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.5: CIC charge density at nodes, rho += (q_sp / dV) prod_a w_a.     */
+/* ------------------------------------------------------------------------ */
+void orc_rho(const orc_grid *g, int64_t np, const double *pos, const int8_t *alive,
+             const double *wpp, double q, double w, double *rho) {
+    const double dV = g->d[0] * g->d[1] * g->d[2];
+    for (int64_t p = 0; p < np; ++p) {
+        if (alive && !alive[p]) continue;
+        const double qsp = q * (wpp ? wpp[p] : w);
+        int64_t i0[3];
+        double f[3];
+        for (int a = 0; a < 3; ++a) {
+            const double t = pos[3 * p + a] / g->d[a];
+            const double fl = floor(t);
+            i0[a] = (int64_t)fl;
+            f[a] = t - fl;
+        }
+        for (int oz = 0; oz < 2; ++oz)
+            for (int oy = 0; oy < 2; ++oy)
+                for (int ox = 0; ox < 2; ++ox) {
+                    const int64_t ip = at(g, i0[0] + ox, i0[1] + oy, i0[2] + oz);
+                    if (ip < 0) continue;
+                    const double wt = (ox ? f[0] : 1.0 - f[0]) * (oy ? f[1] : 1.0 - f[1]) *
+                                      (oz ? f[2] : 1.0 - f[2]);
+                    rho[ip] += qsp / dV * wt;
+                }
+    }
+}
+
+/* Discrete divergence at nodes with backward differences (the operator for  */
+/* which Yee + a charge-conserving deposit keep Gauss's law, Sec. 2.3):      */
+/*   div F(i,j,k) = sum_a (F_a(p) - F_a(p - e_a)) / d_a.                      */
+void orc_div_nodes(const orc_grid *g, const double *F, double *out) {
+    const int64_t V = vol_of(g);
+    int64_t cnt[3];
+    for (int a = 0; a < 3; ++a) cnt[a] = count_along(g, a, 0);
+    for (int64_t k = 0; k < cnt[2]; ++k)
+        for (int64_t j = 0; j < cnt[1]; ++j)
+            for (int64_t i = 0; i < cnt[0]; ++i) {
+                const int64_t ip = at(g, i, j, k);
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    int64_t q[3] = {i, j, k};
+                    q[a] -= 1;
+                    const int64_t iq = at(g, q[0], q[1], q[2]);
+                    /* an absorbing axis' padding entry (index n of a half-cell
+                     * component) is never written and stays zero */
+                    const double fp = F[a * V + ip];
+                    const double fm = iq < 0 ? 0.0 : F[a * V + iq];
+                    s += (fp - fm) / g->d[a];
+                }
+                out[ip] = s;
+            }
+}
+
+/* Field energies (Sec. 3.3, energy conservation).  READING: the paper does  */
+/* not state time levels.  U_E^n = dV/2 sum |E^n|^2 and                      */
+/* U_B^n = dV/2 sum B^{n-1/2} . B^{n+1/2}, with B^{n+1/2} formed from the     */
+/* state as B^{n-1/2} - dt curl E^n; their sum is the quadratic form that the */
+/* vacuum Yee leapfrog keeps exactly.                                         */
+double orc_energy_E(const orc_grid *g, const double *E) {
+    const int64_t V = vol_of(g);
+    const double dV = g->d[0] * g->d[1] * g->d[2];
+    double s = 0.0;
+    for (int64_t i = 0; i < 3 * V; ++i) s += E[i] * E[i];
+    return 0.5 * dV * s;
+}
+
+double orc_energy_B(const orc_grid *g, const double *E, const double *B) {
+    const int64_t V = vol_of(g);
+    const double dV = g->d[0] * g->d[1] * g->d[2];
+    double *Bn = (double *)malloc(sizeof(double) * 3 * V);
+    memcpy(Bn, B, sizeof(double) * 3 * V);
+    orc_faraday(g, E, Bn, NULL);
+    double s = 0.0;
+    for (int64_t i = 0; i < 3 * V; ++i) s += B[i] * Bn[i];
+    free(Bn);
+    return 0.5 * dV * s;
+}
+
+/* Sum of w m (gamma - 1) over the momenta as stored. */
+double orc_kinetic(int64_t np, const double *u, const int8_t *alive, const double *wpp,
+                   double m, double w) {
+    double s = 0.0;
+    for (int64_t p = 0; p < np; ++p) {
+        if (alive && !alive[p]) continue;
+        const double uu = u[3 * p] * u[3 * p] + u[3 * p + 1] * u[3 * p + 1] +
+                          u[3 * p + 2] * u[3 * p + 2];
+        s += (wpp ? wpp[p] : w) * m * uu / (sqrt(1.0 + uu) + 1.0);
+    }
+    return s;
+}

@@ -1,0 +1,235 @@
+"""Seeded synthetic plasmas for the five workloads of this project.
+
+This module only draws random numbers and lays out initial conditions; it
+holds none of the PIC step's arithmetic, so both the FP64 oracle and the HIP
+path can take their inputs from it.  Every array is FP64 with *global*
+positions in [0, L) and momenta u = gamma v (c = 1); the HIP path converts to
+its own storage on the device.
+
+Units: c = eps0 = mu0 = 1.  Plasma workloads take n0 = 1, so omega_p = 1 and
+the cell size is one skin depth; electrons have q = -1, m = 1, protons q = +1,
+m = 1836.  A macro-particle of weight w carries q w and m w (Sec. 2.1 of the
+paper).  The time step is the paper's Courant number 0.5 (Sec. 3.2, 3.3).
+
+Generator: numpy PCG64 seeded with 1000 + workload number.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+PERIODIC = 0
+ABSORBING = 1
+M_PROTON = 1836.0
+
+
+@dataclass
+class SpeciesInit:
+    name: str
+    q: float
+    m: float
+    w: float
+    pos: np.ndarray            # (N, 3) float64 global positions
+    u: np.ndarray              # (N, 3) float64, u^{-1/2}
+    wpp: Optional[np.ndarray] = None   # (N,) per-particle weight, replaces w
+
+
+@dataclass
+class LaserInit:
+    a0: float
+    w0: float
+    tau: float
+    t0: float
+    omega0: float
+    yc: float
+    zc: float
+    i_s: int = 1
+
+
+@dataclass
+class Workload:
+    name: str
+    n: tuple
+    d: tuple
+    dt: float
+    bc: tuple
+    species: list = field(default_factory=list)
+    rho_bg: float = 0.0
+    laser: Optional[LaserInit] = None
+    steps: int = 1
+    sort_every: int = 10
+    E0: Optional[np.ndarray] = None   # (3, ext_z, ext_y, ext_x) or None -> zero
+    B0: Optional[np.ndarray] = None
+
+    @property
+    def n_particles(self) -> int:
+        return int(sum(s.pos.shape[0] for s in self.species))
+
+    @property
+    def n_cells(self) -> int:
+        return int(np.prod(self.n))
+
+
+def courant_dt(d, courant: float = 0.5) -> float:
+    return float(courant / np.sqrt(sum(1.0 / float(x) ** 2 for x in d)))
+
+
+def _uniform_in_cells(rng, n, d, ppc, cell_mask=None):
+    """ppc positions uniformly random inside every cell, cell-ordered (x fastest)."""
+    nx, ny, nz = n
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cells = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64)
+    if cell_mask is not None:
+        cells = cells[cell_mask.ravel()]
+    cells = np.repeat(cells, ppc, axis=0)
+    frac = rng.random(cells.shape)
+    pos = (cells + frac) * np.asarray(d, dtype=np.float64)
+    L = np.asarray(n, dtype=np.float64) * np.asarray(d, dtype=np.float64)
+    # (i + frac) * d can round up to L for the last cell: keep positions in [0, L)
+    pos = np.where(pos >= L, np.nextafter(L, 0.0), pos)
+    return pos
+
+
+def _quiet_lattice(n, d, per_axis):
+    """Regular lattice with per-axis counts at offsets (m + 1/2)/n_m in every cell."""
+    offs = [(np.arange(c) + 0.5) / c for c in per_axis]
+    oz, oy, ox = np.meshgrid(offs[2], offs[1], offs[0], indexing="ij")
+    local = np.stack([ox.ravel(), oy.ravel(), oz.ravel()], axis=1)
+    nx, ny, nz = n
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cells = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64)
+    pos = (cells[:, None, :] + local[None, :, :]).reshape(-1, 3)
+    return pos * np.asarray(d, dtype=np.float64)
+
+
+def langmuir_thermal(n=(16, 16, 16), ppc=8, vth=0.01, amp=1e-3, mode=1, steps=200, seed=1001):
+    """Workload 1: periodic thermal plasma with a Langmuir perturbation.
+
+    16^3 cells of size 1, 8 electrons per cell uniformly random in the cell,
+    u ~ N(0, vth^2) per component plus u_x += amp sin(2 pi mode x / L_x),
+    immobile neutralising background rho_bg = +1, 200 steps, FP64.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = (1.0, 1.0, 1.0)
+    pos = _uniform_in_cells(rng, n, d, ppc)
+    u = rng.normal(0.0, vth, size=pos.shape)
+    u[:, 0] += amp * np.sin(2.0 * np.pi * mode * pos[:, 0] / (n[0] * d[0]))
+    sp = SpeciesInit("electron", -1.0, 1.0, 1.0 / ppc, pos, u)
+    return Workload("langmuir_thermal_%dx%dx%d_ppc%d" % (*n, ppc), tuple(n), d, courant_dt(d),
+                    (PERIODIC,) * 3, [sp], rho_bg=1.0, steps=steps, sort_every=10)
+
+
+def thermal_two_species(n=(128, 128, 128), ppc=8, vth=0.05, steps=100, seed=1002,
+                        sort_every=10):
+    """Workload 2: periodic thermal electron-proton plasma (the benchmark).
+
+    128^3 cells of size 1, 8 electrons and 8 protons per cell; protons sit on
+    the electron positions (exact initial neutrality, E^0 = 0 satisfies
+    Gauss's law).  u_e ~ N(0, 0.05^2), u_p ~ N(0, (0.05/sqrt(1836))^2) per
+    component (equal temperatures).  Weight 1/ppc each (n0 = 1).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = (1.0, 1.0, 1.0)
+    pos = _uniform_in_cells(rng, n, d, ppc)
+    ue = rng.normal(0.0, vth, size=pos.shape)
+    up = rng.normal(0.0, vth / np.sqrt(M_PROTON), size=pos.shape)
+    e = SpeciesInit("electron", -1.0, 1.0, 1.0 / ppc, pos, ue)
+    p = SpeciesInit("proton", 1.0, M_PROTON, 1.0 / ppc, pos.copy(), up)
+    return Workload("thermal_ep_%dx%dx%d_ppc%d" % (*n, ppc), tuple(n), d, courant_dt(d),
+                    (PERIODIC,) * 3, [e, p], rho_bg=0.0, steps=steps, sort_every=sort_every)
+
+
+def lwfa_slab(n=(1024, 128, 128), d=(0.05, 0.2, 0.2), ppc=2, x_start=128, ramp=40,
+              n_plasma=0.01, a0=2.0, w0=8.0, tau=10.0, steps=2000, seed=1003,
+              sort_every=10):
+    """Workload 3: laser-wakefield-like box with absorbing faces (laser units).
+
+    c = omega0 = 1, densities in units of n_c.  Cold electron slab filling
+    x >= x_start cells with a linear up-ramp over `ramp` cells to n_plasma,
+    `ppc` particles per cell along a (ppc, 1, 1) regular lattice with
+    per-particle weight n(x) dV / ppc.  Linearly (y) polarised Gaussian pulse
+    of peak amplitude a0, waist w0, intensity FWHM tau, injected at x node 1.
+    """
+    nx, ny, nz = n
+    dV = d[0] * d[1] * d[2]
+    offs = (np.arange(ppc) + 0.5) / ppc
+    xs = np.arange(x_start, nx)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), xs, indexing="ij")
+    cells = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64)
+    cells = np.repeat(cells, ppc, axis=0)
+    local = np.zeros_like(cells)
+    local[:, 0] = np.tile(offs, cells.shape[0] // ppc)
+    local[:, 1] = 0.5
+    local[:, 2] = 0.5
+    rng = np.random.Generator(np.random.PCG64(seed))
+    # small seeded jitter in the transverse offsets breaks the exact lattice symmetry
+    local[:, 1:] += 0.25 * (rng.random((cells.shape[0], 2)) - 0.5)
+    pos = (cells + local) * np.asarray(d)
+    xc = pos[:, 0] / d[0]
+    dens = n_plasma * np.clip((xc - x_start) / ramp, 0.0, 1.0)
+    wpp = dens * dV / ppc
+    u = np.zeros_like(pos)
+    sp = SpeciesInit("electron", -1.0, 1.0, n_plasma * dV / ppc, pos, u, wpp=wpp)
+    Ly, Lz = ny * d[1], nz * d[2]
+    laser = LaserInit(a0=a0, w0=w0, tau=tau, t0=2.5 * tau, omega0=1.0, yc=0.5 * Ly,
+                      zc=0.5 * Lz, i_s=1)
+    return Workload("lwfa_%dx%dx%d_ppc%d" % (nx, ny, nz, ppc), tuple(n), tuple(d),
+                    courant_dt(d), (ABSORBING,) * 3, [sp], rho_bg=0.0, laser=laser,
+                    steps=steps, sort_every=sort_every)
+
+
+def cold_langmuir_lattice(n=(32, 32, 32), per_axis=(4, 2, 2), eps=1e-2, mode=1, steps=500):
+    """Workload 4: cold quiet-start plasma for the differentiable run.
+
+    32^3 cells, 16 particles per cell on a (4, 2, 2) lattice at offsets
+    (m + 1/2)/n_m, u_x = eps sin(2 pi mode x / L_x), background rho_bg = +1.
+    Deterministic (no random draws).
+    """
+    d = (1.0, 1.0, 1.0)
+    pos = _quiet_lattice(n, d, per_axis)
+    ppc = int(np.prod(per_axis))
+    u = np.zeros_like(pos)
+    u[:, 0] = eps * np.sin(2.0 * np.pi * mode * pos[:, 0] / (n[0] * d[0]))
+    sp = SpeciesInit("electron", -1.0, 1.0, 1.0 / ppc, pos, u)
+    return Workload("cold_langmuir_%dx%dx%d_ppc%d" % (*n, ppc), tuple(n), d, courant_dt(d),
+                    (PERIODIC,) * 3, [sp], rho_bg=1.0, steps=steps, sort_every=0)
+
+
+def weibel_bimaxwellian(n=(256, 256, 256), ppc=16, vth_x=0.25, vth_perp=0.05, steps=50,
+                        seed=1005, sort_every=10):
+    """Workload 5: anisotropic (T_x/T_perp = 25) electrons over immobile ions.
+
+    u_x ~ N(0, 0.25^2), u_y, u_z ~ N(0, 0.05^2); 16 electrons per cell
+    uniformly random in the cell; background rho_bg = +1.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = (1.0, 1.0, 1.0)
+    pos = _uniform_in_cells(rng, n, d, ppc)
+    u = np.empty_like(pos)
+    u[:, 0] = rng.normal(0.0, vth_x, size=pos.shape[0])
+    u[:, 1:] = rng.normal(0.0, vth_perp, size=(pos.shape[0], 2))
+    sp = SpeciesInit("electron", -1.0, 1.0, 1.0 / ppc, pos, u)
+    return Workload("weibel_%dx%dx%d_ppc%d" % (*n, ppc), tuple(n), d, courant_dt(d),
+                    (PERIODIC,) * 3, [sp], rho_bg=1.0, steps=steps, sort_every=sort_every)
+
+
+def random_fields(n, bc=(PERIODIC,) * 3, scale=1e-2, seed=7):
+    """Random E and B arrays (valid entries only; absorbing padding left zero)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ext = [n[a] + (1 if bc[a] == ABSORBING else 0) for a in range(3)]
+    E = scale * rng.standard_normal((3, ext[2], ext[1], ext[0]))
+    B = scale * rng.standard_normal((3, ext[2], ext[1], ext[0]))
+    for c in range(3):
+        for a in range(3):
+            if bc[a] != ABSORBING:
+                continue
+            # E_c is half-staggered along a == c; B_c along a != c: index n is padding
+            sl = [slice(None)] * 3
+            sl[2 - a] = n[a]
+            if a == c:
+                E[c][tuple(sl)] = 0.0
+            else:
+                B[c][tuple(sl)] = 0.0
+    return E, B

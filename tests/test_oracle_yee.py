@@ -1,0 +1,173 @@
+"""Pins of the oracle's Yee solver (Sec. 2.3 of the paper).
+
+- an oblique vacuum plane wave built from the closed-form Yee dispersion
+  relation is an exact discrete eigenmode: it must be reproduced to round-off
+  (any wrong sign, index or cell size in a curl breaks it);
+- the vacuum leapfrog keeps |E^n|^2 + B^{n-1/2}.B^{n+1/2} exactly;
+- div B is unchanged and div E changes by exactly -dt div J;
+- the error against the continuum solution falls at second order, the
+  property behind the paper's grid-convergence table (rate 2.136);
+- first-order Mur faces absorb a normally incident pulse; the soft current
+  sheet radiates the prescribed incident amplitude.
+"""
+import ctypes as C
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def _coords(n, d, stag):
+    """Physical coordinates of a component with per-axis stagger (0 or 1/2)."""
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    return ((x + stag[0]) * d[0], (y + stag[1]) * d[1], (z + stag[2]) * d[2])
+
+
+def _plane_wave(n, d, dt, m, amp_dir, t_E, t_B):
+    L = [n[a] * d[a] for a in range(3)]
+    k = np.array([2 * np.pi * m[a] / L[a] for a in range(3)])
+    kt = np.array([2.0 / d[a] * np.sin(k[a] * d[a] / 2.0) for a in range(3)])
+    Ehat = np.cross(kt, amp_dir)
+    Ehat /= np.linalg.norm(Ehat)
+    s = dt * np.linalg.norm(kt) / 2.0
+    omega = 2.0 / dt * np.arcsin(s)
+    omt = 2.0 / dt * np.sin(omega * dt / 2.0)
+    Bhat = np.cross(kt, Ehat) / omt
+    E = np.zeros((3, n[2], n[1], n[0]))
+    B = np.zeros_like(E)
+    for c in range(3):
+        se = [0.5 if a == c else 0.0 for a in range(3)]
+        sb = [0.0 if a == c else 0.5 for a in range(3)]
+        X = _coords(n, d, se)
+        E[c] = Ehat[c] * np.cos(k[0] * X[0] + k[1] * X[1] + k[2] * X[2] - omega * t_E)
+        X = _coords(n, d, sb)
+        B[c] = Bhat[c] * np.cos(k[0] * X[0] + k[1] * X[1] + k[2] * X[2] - omega * t_B)
+    return E, B
+
+
+def test_oblique_plane_wave_is_exact_eigenmode():
+    n, d = (16, 12, 10), (1.0, 0.8, 1.2)
+    dt = O.courant_dt(d)
+    sim = O.OracleSim(n, d, dt)
+    E, B = _plane_wave(n, d, dt, (1, 2, 1), np.array([0.3, -0.7, 1.0]), 0.0, -0.5 * dt)
+    sim.E[...] = E
+    sim.B[...] = B
+    N = 60
+    sim.step(N)
+    E2, B2 = _plane_wave(n, d, dt, (1, 2, 1), np.array([0.3, -0.7, 1.0]), N * dt, (N - 0.5) * dt)
+    assert np.max(np.abs(sim.E - E2)) < 1e-12
+    assert np.max(np.abs(sim.B - B2)) < 1e-12
+    # and the wave actually moved: the field is far from its start
+    assert np.max(np.abs(sim.E - E)) > 0.1
+
+
+def test_vacuum_yee_energy_exact():
+    n, d = (8, 6, 7), (1.0, 0.9, 1.1)
+    sim = O.OracleSim(n, d, O.courant_dt(d))
+    rng = np.random.default_rng(3)
+    sim.E[...] = rng.standard_normal(sim.E.shape)
+    sim.B[...] = rng.standard_normal(sim.B.shape)
+    U0 = sim.diagnostics()
+    sim.step(200)
+    U1 = sim.diagnostics()
+    tot0 = U0["U_E"] + U0["U_B"]
+    tot1 = U1["U_E"] + U1["U_B"]
+    assert abs(tot1 - tot0) / tot0 < 1e-12
+    assert abs(U1["U_E"] - U0["U_E"]) / tot0 > 1e-3  # energy did move between E and B
+
+
+def _divB(B, d):
+    return ((np.roll(B[0], -1, axis=2) - B[0]) / d[0] + (np.roll(B[1], -1, axis=1) - B[1]) / d[1]
+            + (np.roll(B[2], -1, axis=0) - B[2]) / d[2])
+
+
+def test_divergences():
+    n, d = (6, 5, 7), (1.0, 0.7, 1.3)
+    dt = O.courant_dt(d)
+    sim = O.OracleSim(n, d, dt)
+    rng = np.random.default_rng(5)
+    sim.E[...] = rng.standard_normal(sim.E.shape)
+    sim.B[...] = rng.standard_normal(sim.B.shape)
+    g = C.byref(sim.g)
+    L = O.lib()
+    db0 = _divB(sim.B, d)
+    for _ in range(20):
+        J = rng.standard_normal(sim.E.shape)
+        de0 = sim.div(sim.E)
+        L.orc_faraday(g, O._p(sim.E), O._p(sim.B), O._p(sim.Bbar))
+        L.orc_ampere(g, O._p(sim.E), O._p(sim.B), O._p(J))
+        de1 = sim.div(sim.E)
+        assert np.max(np.abs((de1 - de0) + dt * sim.div(J))) < 1e-12
+    assert np.max(np.abs(_divB(sim.B, d) - db0)) < 1e-12
+
+
+def test_second_order_convergence():
+    """Continuum plane wave E_y = B_z = cos(k(x - t)); error at fixed time.
+
+    The paper reports rate 2.136 (R^2 0.972) for its waveguide table; the
+    Yee scheme at fixed Courant number must show rate 2 here.
+    """
+    L = 2 * np.pi
+    T = L
+    errs, hs = [], []
+    for N in (16, 32, 64, 128):
+        h = L / N
+        d = (h, h, h)
+        dt = O.courant_dt(d)
+        nsteps = int(round(T / dt))
+        sim = O.OracleSim((N, 1, 1), d, dt)
+        x_node = np.arange(N) * h
+        x_half = (np.arange(N) + 0.5) * h
+        sim.E[1, 0, 0, :] = np.cos(x_node)
+        sim.B[2, 0, 0, :] = np.cos(x_half + 0.5 * dt)
+        sim.step(nsteps)
+        t = nsteps * dt
+        errs.append(np.max(np.abs(sim.E[1, 0, 0, :] - np.cos(x_node - t))))
+        hs.append(h)
+    rate = np.polyfit(np.log(hs), np.log(errs), 1)[0]
+    gold = GOLD["yee_convergence"]
+    assert 1.9 < rate < 2.2, rate
+    assert abs(rate - gold["rate"]) < 0.25
+
+
+def test_mur_absorbs_normal_pulse():
+    N = 400
+    h = 0.05
+    d = (h, 0.2, 0.2)
+    dt = O.courant_dt(d)
+    sim = O.OracleSim((N, 1, 1), d, dt, bc=(O.ABSORBING, O.PERIODIC, O.PERIODIC))
+    x_node = np.arange(N + 1) * h
+    x_half = (np.arange(N) + 0.5) * h
+    xc, wid = 0.5 * N * h, 1.0
+    sim.E[1, 0, 0, :] = np.exp(-((x_node - xc) / wid) ** 2)
+    sim.B[2, 0, 0, :N] = np.exp(-((x_half + 0.5 * dt - xc) / wid) ** 2)
+    U0 = sim.diagnostics()
+    tot0 = U0["U_E"] + U0["U_B"]
+    sim.step(int(round((0.5 * N * h + 6 * wid) / dt)))
+    U1 = sim.diagnostics()
+    # the half moving right has left through the face: under 1% of it remains
+    assert (U1["U_E"] + U1["U_B"]) / tot0 < 0.01
+
+
+def test_laser_sheet_radiates_incident_amplitude():
+    N = 400
+    d = (0.05, 0.2, 0.2)
+    dt = O.courant_dt(d)
+    sim = O.OracleSim((N, 1, 1), d, dt, bc=(O.ABSORBING, O.PERIODIC, O.PERIODIC))
+    a0, tau = 2.0, 10.0
+    sim.set_laser(a0=a0, w0=1e9, tau=tau, t0=2.5 * tau, omega0=1.0, yc=0.1, zc=0.0, i_s=1)
+    probe = 200
+    trace = []
+    nsteps = int(round((2.5 * tau + 2 * tau + probe * d[0]) / dt))
+    for _ in range(nsteps):
+        sim.step(1)
+        trace.append(sim.E[1, 0, 0, probe])
+    tt = np.linspace(-3 * tau, 3 * tau, 200001)
+    env = np.max(np.abs(np.exp(-2 * np.log(2) * tt ** 2 / tau ** 2) * np.sin(tt)))
+    peak = np.max(np.abs(trace))
+    assert abs(peak / (a0 * env) - 1.0) < 0.02, peak / (a0 * env)
