@@ -1,0 +1,242 @@
+/*
+ * empic.h -- C ABI of libempic, an MI355X (gfx950) implementation of the
+ * explicit 3D electromagnetic particle-in-cell step of KEMPIC-3D
+ * (arXiv 2609.16575): staggered trilinear gather of E and B, relativistic
+ * Boris push, charge-conserving ZigZag current deposit and Yee FDTD curl
+ * updates (Sec. 2.2 of the paper, Fig. "PIC algorithm").
+ *
+ * Conventions (all calls):
+ *   - Units c = eps0 = mu0 = 1 (the bare "- dt J" of the Ampere-Maxwell
+ *     update, Sec. 2.3).  Momenta are u = gamma v.
+ *   - Time levels (Sec. 2.3, 2.4): E and particle positions at t^n, B and
+ *     momenta at t^{n-1/2}.  empic_step advances all four by whole steps.
+ *   - Grid arrays are [k][j][i] (x fastest) with ext[a] = n[a] + 1 on an
+ *     absorbing axis, n[a] on a periodic one.  Component locations in cell
+ *     units: Ex(i+1/2,j,k) Ey(i,j+1/2,k) Ez(i,j,k+1/2), Bx(i,j+1/2,k+1/2)
+ *     By(i+1/2,j,k+1/2) Bz(i+1/2,j+1/2,k); J like E; rho at nodes.  On an
+ *     absorbing axis the entry n of a half-cell component is padding and
+ *     stays zero.
+ *   - All device memory is owned by the caller (fields, particle buffers,
+ *     workspace).  The library keeps raw pointers only; the caller keeps the
+ *     memory alive and unmoved while the handle lives.  empic_destroy never
+ *     frees caller memory.
+ *   - Every kernel is launched on the hipStream_t given at creation.  Calls
+ *     are asynchronous except empic_diagnostics, empic_sync,
+ *     empic_particle_count and empic_kernel_times, which synchronise it.
+ *   - Every call returns an empic_status; nothing throws across the ABI.
+ *     After EMPIC_E_ARG, EMPIC_E_CFL, EMPIC_E_CAPACITY or
+ *     EMPIC_E_UNSUPPORTED the handle is unchanged and usable.  After
+ *     EMPIC_E_HIP the handle is poisoned: only empic_destroy and
+ *     empic_last_error are allowed.  EMPIC_E_NONFINITE / EMPIC_E_STATE
+ *     report a fault word raised by the kernels (bits EMPIC_FAULT_*).
+ *   - A handle is not thread-safe; use one handle per stream.
+ */
+#ifndef EMPIC_H
+#define EMPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EMPIC_MAX_SPECIES 4
+
+typedef enum {
+    EMPIC_OK = 0,
+    EMPIC_E_ARG = 1,         /* bad argument (null, size, range, order of calls) */
+    EMPIC_E_STATE = 2,       /* kernel fault word reports corrupted particle state */
+    EMPIC_E_HIP = 3,         /* a HIP runtime call failed; handle poisoned */
+    EMPIC_E_CFL = 4,         /* dt violates the 3D CFL bound (Sec. 2.3, CFL eq.) */
+    EMPIC_E_CAPACITY = 5,    /* particle count exceeds a buffer's capacity */
+    EMPIC_E_NONFINITE = 6,   /* a non-finite momentum or field reached a particle */
+    EMPIC_E_UNSUPPORTED = 7  /* valid request this build does not implement */
+} empic_status;
+
+enum { EMPIC_BC_PERIODIC = 0, EMPIC_BC_ABSORBING = 1 };
+
+/* Arithmetic of the step. */
+enum {
+    EMPIC_FP32_CELLREL = 0, /* FP32 fields; particles as packed cell + FP32
+                               in-cell offset + FP32 u; cell-sorted, fused
+                               gather/push/deposit with LDS tiles */
+    EMPIC_FP64_PLAIN = 1    /* FP64 fields and global FP64 positions, unsorted,
+                               one thread per particle, global atomics */
+};
+
+/* Fault bits raised by kernels (empic_diag.fault_word). */
+enum {
+    EMPIC_FAULT_NONFINITE = 1u,   /* non-finite gamma after the push */
+    EMPIC_FAULT_FAST = 2u,        /* |dxi| >= 1 cell in one step (impossible under CFL) */
+    EMPIC_FAULT_OFFSET = 4u,      /* stored in-cell offset outside [0,1) */
+    EMPIC_FAULT_CELL = 8u,        /* stored cell index outside the grid */
+    EMPIC_FAULT_FALLBACK = 16u    /* info: a particle left its tile window and was
+                                     handled through global memory (not an error) */
+};
+
+/* Grid and time step (Sec. 2.3).  dt must satisfy
+ *   dt <= 1 / sqrt(1/d0^2 + 1/d1^2 + 1/d2^2)              (c = 1)
+ * FP32_CELLREL additionally limits n to <= 2047 x 2047 x 1023 cells (the
+ * packed cell index).  sort_every = S > 0 re-sorts particles by tile and cell
+ * at the start of every S-th step (FP32 path); 0 sorts only on request and
+ * once before the first step. */
+typedef struct {
+    int32_t n[3];
+    int32_t bc[3];      /* EMPIC_BC_* per axis */
+    double d[3];        /* cell sizes */
+    double dt;
+    int32_t precision;  /* EMPIC_FP32_CELLREL or EMPIC_FP64_PLAIN */
+    int32_t sort_every;
+} empic_grid_desc;
+
+/* A species (Sec. 2.1): a macro-particle of weight w stands for w physical
+ * particles with charge q w and mass m w.  per_particle_w = 1 takes the weight
+ * of each particle from its `w` buffer instead (q w_p, m w_p). */
+typedef struct {
+    double q;
+    double m;
+    double w;
+    int32_t per_particle_w;
+    int32_t pad;
+} empic_species_desc;
+
+/* Device buffers of one species.  FP32_CELLREL: cell = packed
+ * i | j << 11 | k << 22 (or -1 for a removed particle), pos = in-cell
+ * offsets in [0,1) (float), u (float), w (float, optional).  FP64_PLAIN: cell
+ * unused (may be NULL), pos = global positions in [0, L) (double), u (double),
+ * w (double, optional).  id (int32) travels with the particle through sorts. */
+typedef struct {
+    int32_t *cell;
+    void *pos[3];
+    void *u[3];
+    int32_t *id;
+    void *w;
+} empic_particle_buffers;
+
+/* Soft current-sheet laser source (READING of the paper's external-source
+ * module, Sec. 2.5 and 3.2): J_y on x-node plane i_s radiating
+ * E_inc = a0 exp(-r^2/w0^2) exp(-2 ln2 (t-t0)^2/tau^2) sin(omega0 (t-t0)),
+ * r^2 = (y-yc)^2 + (z-zc)^2, in both directions. */
+typedef struct {
+    double a0, w0, tau, t0, omega0, yc, zc;
+    int32_t i_s;
+    int32_t enabled;
+} empic_laser_desc;
+
+/* FP64 diagnostics of the current state (Sec. 3.3).  U_E = dV/2 sum |E^n|^2,
+ * U_B = dV/2 sum B^{n-1/2}.B^{n+1/2} (B^{n+1/2} formed from the state),
+ * K_minus / K_plus = sum w m (gamma - 1) at u^{n-1/2} / u^{n+1/2} (the latter
+ * from a side-effect-free push), K = their mean, U_tot = U_E + U_B + sum K.
+ * Gauss residual r = div E - rho - rho_bg at nodes (backward differences).
+ * cont_max = max |rho^n - rho^{n-1} + dt div J^{n-1/2}| when the previous
+ * call was made exactly one step earlier (cont_valid = 1), with rho_max the
+ * largest |rho^n| of the particles for scale. */
+typedef struct {
+    int64_t step;
+    double t;
+    double U_E, U_B, U_tot;
+    double K[EMPIC_MAX_SPECIES];
+    double K_minus[EMPIC_MAX_SPECIES];
+    double K_plus[EMPIC_MAX_SPECIES];
+    double gauss_max, gauss_l2;
+    double cont_max, rho_max;
+    int32_t cont_valid;
+    uint32_t fault_word;
+    int64_t n_particles[EMPIC_MAX_SPECIES];
+    int64_t fallback_particles; /* cumulative count of out-of-window particles */
+} empic_diag;
+
+typedef struct empic_sim empic_sim;
+
+/* Bytes of device workspace the handle needs for this grid, up to
+ * max_species species of at most max_capacity particles each. */
+size_t empic_workspace_bytes(const empic_grid_desc *g, int32_t max_species,
+                             int64_t max_capacity);
+
+/* Validate the grid (sizes, CFL -> EMPIC_E_CFL), keep the stream and the
+ * caller-owned workspace (>= empic_workspace_bytes, 256-byte aligned). */
+empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t max_capacity,
+                          void *hip_stream, void *workspace, size_t workspace_bytes,
+                          empic_sim **out);
+
+/* Bind the six field arrays and the current density, each ext0*ext1*ext2
+ * elements of float (FP32_CELLREL) or double (FP64_PLAIN).  E = E^n,
+ * B = B^{n-1/2}; J is written by every step (J^{n+1/2} of the last step). */
+empic_status empic_bind_fields(empic_sim *s, void *const E[3], void *const B[3],
+                               void *const J[3]);
+
+/* Register a species with `capacity` slots in buffers buf0 and, for the FP32
+ * path, a second set buf1 of the same capacity that the sort ping-pongs into
+ * (buf1 may be NULL for FP64_PLAIN).  The species starts empty; fill it with
+ * empic_load_particles_f64.  Up to EMPIC_MAX_SPECIES. */
+empic_status empic_add_species(empic_sim *s, const empic_species_desc *desc, int64_t capacity,
+                               const empic_particle_buffers *buf0,
+                               const empic_particle_buffers *buf1, int32_t *species_id_out);
+
+/* Fill species `sp` with `count` particles from device FP64 arrays: pos_xyz
+ * and u_xyz are count x 3 (interleaved x,y,z), global positions in [0, L),
+ * u = u^{-1/2}.  w (count, may be NULL) is the per-particle weight; ids
+ * (count int32, may be NULL -> 0..count-1).  Converted on the device to the
+ * species' storage (cell + FP32 offset for FP32_CELLREL). */
+empic_status empic_load_particles_f64(empic_sim *s, int32_t sp, int64_t count,
+                                      const double *pos_xyz, const double *u_xyz,
+                                      const double *w, const int32_t *ids);
+
+/* Write the live particles of `sp` as FP64 global positions and momenta
+ * (count x 3 each, device) and their ids, in storage order; *count_out (host)
+ * receives the number written.  Synchronises.  Capacity of the outputs must
+ * be >= the species' capacity. */
+empic_status empic_store_particles_f64(empic_sim *s, int32_t sp, double *pos_xyz,
+                                       double *u_xyz, int32_t *ids, int64_t *count_out);
+
+/* Which of the two buffer sets holds the species' particles now (0 or 1). */
+empic_status empic_current_buffer(empic_sim *s, int32_t sp, int32_t *which);
+
+/* Immobile neutralising background charge density (enters Gauss only). */
+empic_status empic_set_background(empic_sim *s, double rho_bg);
+
+/* External laser source (see empic_laser_desc); enabled = 0 removes it. */
+empic_status empic_set_laser(empic_sim *s, const empic_laser_desc *laser);
+
+/* Advance the state by nsteps PIC cycles (Sec. 2.2): Faraday with temporal
+ * centring of B -> gather, Boris, move, ZigZag deposit for every species ->
+ * Ampere-Maxwell -> laser source -> Mur faces.  FP32 path: counting sort
+ * every sort_every steps.  Asynchronous. */
+empic_status empic_step(empic_sim *s, int32_t nsteps);
+
+/* Sort (FP32 path) by tile and cell now, dropping removed particles. */
+empic_status empic_sort(empic_sim *s);
+
+/* CIC charge density at nodes (Sec. 2.5) of species sp (-1 = all), FP64,
+ * ext0*ext1*ext2 doubles on the device, overwritten.  No background. */
+empic_status empic_deposit_rho(empic_sim *s, int32_t sp, double *rho_out);
+
+/* Compute the FP64 diagnostics of the current state; synchronises. */
+empic_status empic_diagnostics(empic_sim *s, empic_diag *out);
+
+/* Live particles of species sp; synchronises. */
+empic_status empic_particle_count(empic_sim *s, int32_t sp, int64_t *n);
+
+/* Wait for the stream; surface asynchronous HIP errors and the fault word. */
+empic_status empic_sync(empic_sim *s);
+
+/* Kernel timing with HIP events on the handle's stream: enable = 1 starts
+ * recording every launch of the particle kernel ("push") and of the field
+ * kernels ("field"); empic_kernel_times returns the summed milliseconds and
+ * the launch counts since enabling, and synchronises. */
+empic_status empic_enable_timing(empic_sim *s, int32_t enable);
+empic_status empic_kernel_times(empic_sim *s, double *push_ms, int64_t *push_launches,
+                                double *field_ms, int64_t *field_launches,
+                                double *sort_ms, int64_t *sort_launches);
+
+/* Per-handle message for the last failed call; valid until the next call. */
+const char *empic_last_error(const empic_sim *s);
+
+void empic_destroy(empic_sim *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMPIC_H */

@@ -1,0 +1,690 @@
+// empic.hip -- host runtime of libempic: the C ABI declared in include/empic.h.
+//
+// Owns no device memory: fields, particle buffers and the workspace come from
+// the caller; this file validates arguments, carves the workspace, orders the
+// kernel launches of the PIC cycle on the caller's stream (Sec. 2.2 of
+// KEMPIC-3D) and converts kernel fault words and HIP errors into status codes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace empic;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t up_align(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    size_t Bbar, fault, table, partials, result, rho_cur, rho_prev, tile_off, counts, scan, rank,
+        fb_list, mur, total;
+    size_t tile_off_stride;
+    long long mur_stride;
+};
+
+void grid_info(const empic_grid_desc *d, GridP &g, TileInfo &ti) {
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = d->n[a];
+        g.bc[a] = d->bc[a];
+        g.ext[a] = d->n[a] + (d->bc[a] == EMPIC_BC_ABSORBING ? 1 : 0);
+        g.d[a] = d->d[a];
+        g.inv_d[a] = 1.0 / d->d[a];
+        ti.nt[a] = (d->n[a] + (a == 0 ? TX : a == 1 ? TY : TZ) - 1) / (a == 0 ? TX : a == 1 ? TY : TZ);
+    }
+    g.dt = d->dt;
+    g.V = (long long)g.ext[0] * g.ext[1] * g.ext[2];
+    ti.ntiles = ti.nt[0] * ti.nt[1] * ti.nt[2];
+    ti.NK = (long long)ti.ntiles * TC;
+}
+
+Layout layout(const empic_grid_desc *d, int max_species, long long max_capacity) {
+    GridP g;
+    TileInfo ti;
+    grid_info(d, g, ti);
+    const size_t es = d->precision == EMPIC_FP64_PLAIN ? 8 : 4;
+    Layout L;
+    size_t o = 0;
+    L.Bbar = o;
+    o += up_align(3 * (size_t)g.V * es);
+    L.fault = o;
+    o += up_align(64);
+    L.table = o;
+    o += up_align(sizeof(DevSpecies) * EMPIC_MAX_SPECIES);
+    L.partials = o;
+    o += up_align((size_t)NQ * PSTRIDE * 8);
+    L.result = o;
+    o += up_align(NQ * 8);
+    L.rho_cur = o;
+    o += up_align((size_t)g.V * 8);
+    L.rho_prev = o;
+    o += up_align((size_t)g.V * 8);
+    L.tile_off = o;
+    L.tile_off_stride = up_align(((size_t)ti.ntiles + 1) * 4 + 4);
+    o += L.tile_off_stride * (size_t)max_species;
+    L.counts = o;
+    o += up_align(((size_t)ti.NK + 1) * 4);
+    L.scan = o;
+    o += up_align(((size_t)(ti.NK + 1023) / 1024 + 2) * 4);
+    L.rank = o;
+    o += up_align((size_t)max_capacity * 4);
+    L.fb_list = o;  // out-of-window list: every slot of every species fits
+    o += up_align((size_t)max_capacity * max_species * 8);
+    long long ps = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+        const long long area = (long long)g.ext[b1] * g.ext[b2];
+        if (area > ps) ps = area;
+    }
+    L.mur_stride = ps;
+    L.mur = o;
+    const bool absorbing = d->bc[0] || d->bc[1] || d->bc[2];
+    o += absorbing ? up_align((size_t)3 * 2 * 4 * ps * es) : 0;
+    L.total = o;
+    return L;
+}
+
+struct SpeciesState {
+    empic_species_desc desc{};
+    long long capacity = 0;
+    empic_particle_buffers buf[2]{};
+    bool has_alt = false;
+    int cur = 0;
+    int32_t *tile_off = nullptr;  // ntiles + 1
+    int32_t *dcount = nullptr;    // device slot count
+    long long host_count = 0;
+};
+
+struct TimedEvent {
+    hipEvent_t a, b;
+    int kind;  // 0 push, 1 field, 2 sort
+};
+
+}  // namespace
+
+struct empic_sim {
+    empic_grid_desc desc{};
+    GridP g{};
+    TileInfo ti{};
+    Layout L{};
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    void *Bbar[3]{};
+    uint32_t *fault = nullptr;
+    unsigned long long *fallback = nullptr;
+    DevSpecies *table = nullptr;
+    double *partials = nullptr, *result = nullptr, *rho_cur = nullptr, *rho_prev = nullptr;
+    int32_t *counts = nullptr, *scan_blocks = nullptr, *rank = nullptr;
+    void *mur = nullptr;
+    int2 *fb_list = nullptr;
+    unsigned *fb_count = nullptr;
+    void *E[3]{}, *B[3]{}, *J[3]{};
+    bool bound = false;
+    SpeciesState sp[EMPIC_MAX_SPECIES];
+    int nsp = 0, max_species = 0;
+    long long max_capacity = 0;
+    double rho_bg = 0.0;
+    empic_laser_desc laser{};
+    long long nstep = 0, rho_prev_step = -1;
+    bool need_sort = true;
+    bool poisoned = false;
+    std::string err;
+    bool timing = false;
+    std::vector<TimedEvent> events;
+    double t_ms[3] = {0, 0, 0};
+    long long t_n[3] = {0, 0, 0};
+};
+
+namespace {
+
+empic_status fail(empic_sim *s, empic_status st, const std::string &msg) {
+    if (s) s->err = msg;
+    return st;
+}
+
+empic_status hip_fail(empic_sim *s, hipError_t e, const char *what) {
+    if (s) {
+        s->poisoned = true;
+        s->err = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return EMPIC_E_HIP;
+}
+
+#define EMPIC_HIP(call)                                 \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(s, e_, #call); \
+    } while (0)
+
+#define EMPIC_GUARD(s)                                                               \
+    do {                                                                             \
+        if (!(s)) return EMPIC_E_ARG;                                                \
+        if ((s)->poisoned) return fail((s), EMPIC_E_HIP, "handle poisoned by an earlier HIP error"); \
+        (s)->err.clear();                                                            \
+    } while (0)
+
+bool fp64(const empic_sim *s) { return s->desc.precision == EMPIC_FP64_PLAIN; }
+
+SpeciesP species_params(const empic_sim *s, int i, int which) {
+    const SpeciesState &S = s->sp[i];
+    const empic_particle_buffers &b = S.buf[which];
+    SpeciesP p;
+    p.cell = (uint32_t *)b.cell;
+    for (int a = 0; a < 3; ++a) {
+        p.pos[a] = b.pos[a];
+        p.u[a] = b.u[a];
+    }
+    p.id = b.id;
+    p.w = S.desc.per_particle_w ? b.w : nullptr;
+    p.tile_off = S.tile_off;
+    p.count = S.dcount;
+    p.capacity = S.capacity;
+    p.q = S.desc.q;
+    p.m = S.desc.m;
+    p.w_species = S.desc.w;
+    p.per_particle_w = S.desc.per_particle_w;
+    return p;
+}
+
+void ev_begin(empic_sim *s, TimedEvent &t, int kind) {
+    t.kind = kind;
+    t.a = t.b = nullptr;
+    if (!s->timing) return;
+    (void)hipEventCreate(&t.a);
+    (void)hipEventCreate(&t.b);
+    (void)hipEventRecord(t.a, s->stream);
+}
+void ev_end(empic_sim *s, TimedEvent &t) {
+    if (!s->timing || !t.a) return;
+    (void)hipEventRecord(t.b, s->stream);
+    s->events.push_back(t);
+}
+
+template <typename T>
+void field_ptrs(empic_sim *s, T *E[3], T *B[3], T *J[3], T *Bb[3]) {
+    for (int a = 0; a < 3; ++a) {
+        E[a] = (T *)s->E[a];
+        B[a] = (T *)s->B[a];
+        J[a] = (T *)s->J[a];
+        Bb[a] = (T *)s->Bbar[a];
+    }
+}
+
+void do_sort(empic_sim *s) {
+    TimedEvent t;
+    ev_begin(s, t, 2);
+    for (int i = 0; i < s->nsp; ++i) {
+        SpeciesState &S = s->sp[i];
+        const SpeciesP cur = species_params(s, i, S.cur);
+        const SpeciesP alt = species_params(s, i, 1 - S.cur);
+        launch_sort(s->g, s->ti, cur, alt, s->counts, s->scan_blocks, s->rank, S.tile_off,
+                    s->fault, s->stream);
+        S.cur = 1 - S.cur;
+    }
+    ev_end(s, t);
+    s->need_sort = false;
+}
+
+template <typename T>
+void one_step(empic_sim *s) {
+    T *E[3], *B[3], *J[3], *Bb[3];
+    field_ptrs<T>(s, E, B, J, Bb);
+    const bool absorbing = s->g.bc[0] || s->g.bc[1] || s->g.bc[2];
+    TimedEvent t;
+    ev_begin(s, t, 1);
+    // 1. Faraday + temporal centring of B; J zeroed for this step's deposit
+    launch_faraday<T>(s->g, E, B, Bb, J, true, s->stream);
+    ev_end(s, t);
+    // 2. gather, Boris, move, ZigZag for every species
+    ev_begin(s, t, 0);
+    if constexpr (sizeof(T) == 4) {
+        unsigned mask = 0;
+        for (int i = 0; i < s->nsp; ++i) mask |= (unsigned)s->sp[i].cur << i;
+        launch_push_fused(s->g, s->ti, (float *const *)E, (float *const *)Bb, (float *const *)J,
+                          s->table, s->nsp, mask, s->fault, s->fallback, s->fb_list, s->fb_count,
+                          (long long)s->max_capacity * s->max_species, s->stream);
+    } else {
+        for (int i = 0; i < s->nsp; ++i)
+            launch_push_f64(s->g, (double *const *)E, (double *const *)Bb, (double *const *)J,
+                            species_params(s, i, 0), s->sp[i].host_count, s->fault, s->stream);
+    }
+    ev_end(s, t);
+    // 3. Ampere-Maxwell, external source, absorbing faces
+    ev_begin(s, t, 1);
+    if (absorbing) launch_mur_save<T>(s->g, E, (T *)s->mur, s->L.mur_stride, s->stream);
+    launch_ampere<T>(s->g, E, B, J, s->stream);
+    if (s->laser.enabled) launch_laser<T>(s->g, E, s->laser, (s->nstep + 0.5) * s->g.dt, s->stream);
+    if (absorbing) launch_mur_apply<T>(s->g, E, (const T *)s->mur, s->L.mur_stride, s->stream);
+    ev_end(s, t);
+    s->nstep += 1;
+}
+
+empic_status check_launch(empic_sim *s, const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(s, e, what);
+    return EMPIC_OK;
+}
+
+empic_status read_fault(empic_sim *s, uint32_t *word) {
+    EMPIC_HIP(hipMemcpyAsync(word, s->fault, 4, hipMemcpyDeviceToHost, s->stream));
+    EMPIC_HIP(hipStreamSynchronize(s->stream));
+    return EMPIC_OK;
+}
+
+empic_status fault_status(empic_sim *s, uint32_t w) {
+    if (w & EMPIC_FAULT_NONFINITE)
+        return fail(s, EMPIC_E_NONFINITE, "non-finite momentum after the push");
+    if (w & (EMPIC_FAULT_FAST | EMPIC_FAULT_OFFSET | EMPIC_FAULT_CELL)) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "corrupted particle state (fault word 0x%x)", w);
+        return fail(s, EMPIC_E_STATE, buf);
+    }
+    return EMPIC_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+size_t empic_workspace_bytes(const empic_grid_desc *g, int32_t max_species, int64_t max_capacity) {
+    if (!g || max_species < 1 || max_species > EMPIC_MAX_SPECIES || max_capacity < 0) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (g->n[a] < 1) return 0;
+    return layout(g, max_species, max_capacity).total;
+}
+
+empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t max_capacity,
+                          void *hip_stream, void *workspace, size_t workspace_bytes,
+                          empic_sim **out) {
+    if (!g || !out || !workspace) return EMPIC_E_ARG;
+    *out = nullptr;
+    if (max_species < 1 || max_species > EMPIC_MAX_SPECIES || max_capacity < 0) return EMPIC_E_ARG;
+    if (g->precision != EMPIC_FP32_CELLREL && g->precision != EMPIC_FP64_PLAIN) return EMPIC_E_ARG;
+    double inv2 = 0.0;
+    long long V = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] < 1 || !(g->d[a] > 0.0) || !std::isfinite(g->d[a])) return EMPIC_E_ARG;
+        if (g->bc[a] != EMPIC_BC_PERIODIC && g->bc[a] != EMPIC_BC_ABSORBING) return EMPIC_E_ARG;
+        if (g->bc[a] == EMPIC_BC_ABSORBING && g->n[a] < 2) return EMPIC_E_ARG;
+        inv2 += 1.0 / (g->d[a] * g->d[a]);
+        V *= g->n[a] + (g->bc[a] == EMPIC_BC_ABSORBING ? 1 : 0);
+    }
+    if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return EMPIC_E_ARG;
+    if (g->dt > (1.0 + 1e-12) / std::sqrt(inv2)) return EMPIC_E_CFL;  // 3D CFL, c = 1
+    if (g->sort_every < 0) return EMPIC_E_ARG;
+    if (V >= (1LL << 31)) return EMPIC_E_UNSUPPORTED;
+    for (int a = 0; a < 3; ++a)  // launch grids put one axis in a grid dimension
+        if (g->n[a] + 1 > 65535) return EMPIC_E_UNSUPPORTED;
+    if (g->precision == EMPIC_FP32_CELLREL && (g->n[0] > 2047 || g->n[1] > 2047 || g->n[2] > 1023))
+        return EMPIC_E_UNSUPPORTED;
+    if (g->precision == EMPIC_FP64_PLAIN && (g->bc[0] || g->bc[1] || g->bc[2]))
+        return EMPIC_E_UNSUPPORTED;
+    if (max_capacity >= (1LL << 31)) return EMPIC_E_UNSUPPORTED;
+    if (((uintptr_t)workspace & (ALIGN - 1)) != 0) return EMPIC_E_ARG;
+    const Layout L = layout(g, max_species, max_capacity);
+    if (workspace_bytes < L.total) return EMPIC_E_ARG;
+
+    empic_sim *s = new empic_sim();
+    s->desc = *g;
+    grid_info(g, s->g, s->ti);
+    s->L = L;
+    s->stream = (hipStream_t)hip_stream;
+    s->ws = (char *)workspace;
+    const size_t es = g->precision == EMPIC_FP64_PLAIN ? 8 : 4;
+    for (int a = 0; a < 3; ++a) s->Bbar[a] = s->ws + L.Bbar + (size_t)a * s->g.V * es;
+    s->fault = (uint32_t *)(s->ws + L.fault);
+    s->fallback = (unsigned long long *)(s->ws + L.fault + 8);
+    s->table = (DevSpecies *)(s->ws + L.table);
+    s->partials = (double *)(s->ws + L.partials);
+    s->result = (double *)(s->ws + L.result);
+    s->rho_cur = (double *)(s->ws + L.rho_cur);
+    s->rho_prev = (double *)(s->ws + L.rho_prev);
+    s->counts = (int32_t *)(s->ws + L.counts);
+    s->scan_blocks = (int32_t *)(s->ws + L.scan);
+    s->rank = (int32_t *)(s->ws + L.rank);
+    s->mur = s->ws + L.mur;
+    s->fb_list = (int2 *)(s->ws + L.fb_list);
+    s->fb_count = (unsigned *)(s->ws + L.fault + 16);
+    s->max_species = max_species;
+    s->max_capacity = max_capacity;
+    for (int i = 0; i < max_species; ++i) {
+        s->sp[i].tile_off = (int32_t *)(s->ws + L.tile_off + (size_t)i * L.tile_off_stride);
+        s->sp[i].dcount = s->sp[i].tile_off + (s->ti.ntiles + 1);
+    }
+    // zero the fault word, counters and the Bbar array (a fill kernel; no memset nodes)
+    launch_fill_i32((int32_t *)(s->ws + L.fault), 16, 0, s->stream);
+    launch_fill_i32((int32_t *)(s->ws + L.Bbar), (long long)(3 * s->g.V * es / 4), 0, s->stream);
+    if (hipGetLastError() != hipSuccess) {
+        delete s;
+        return EMPIC_E_HIP;
+    }
+    *out = s;
+    return EMPIC_OK;
+}
+
+empic_status empic_bind_fields(empic_sim *s, void *const E[3], void *const B[3], void *const J[3]) {
+    EMPIC_GUARD(s);
+    if (!E || !B || !J) return fail(s, EMPIC_E_ARG, "null field array list");
+    for (int a = 0; a < 3; ++a)
+        if (!E[a] || !B[a] || !J[a]) return fail(s, EMPIC_E_ARG, "null field array");
+    for (int a = 0; a < 3; ++a) {
+        s->E[a] = E[a];
+        s->B[a] = B[a];
+        s->J[a] = J[a];
+    }
+    s->bound = true;
+    return EMPIC_OK;
+}
+
+empic_status empic_add_species(empic_sim *s, const empic_species_desc *desc, int64_t capacity,
+                               const empic_particle_buffers *buf0,
+                               const empic_particle_buffers *buf1, int32_t *species_id_out) {
+    EMPIC_GUARD(s);
+    if (!desc || !buf0) return fail(s, EMPIC_E_ARG, "null species descriptor or buffers");
+    if (s->nsp >= s->max_species) return fail(s, EMPIC_E_ARG, "species limit of the handle reached");
+    if (!(desc->m > 0.0) || !std::isfinite(desc->q) || !std::isfinite(desc->w))
+        return fail(s, EMPIC_E_ARG, "species needs m > 0 and finite q, w");
+    if (capacity < 0 || capacity > s->max_capacity)
+        return fail(s, EMPIC_E_CAPACITY, "species capacity exceeds the handle's max_capacity");
+    if (capacity % 8 != 0) return fail(s, EMPIC_E_ARG, "capacity must be a multiple of 8");
+    const bool f32 = !fp64(s);
+    const empic_particle_buffers *bufs[2] = {buf0, buf1};
+    for (int k = 0; k < 2; ++k) {
+        const empic_particle_buffers *b = bufs[k];
+        if (!b) continue;
+        bool ok = b->pos[0] && b->pos[1] && b->pos[2] && b->u[0] && b->u[1] && b->u[2] && b->id;
+        if (f32) ok = ok && b->cell;
+        if (desc->per_particle_w) ok = ok && b->w;
+        if (!ok) return fail(s, EMPIC_E_ARG, "missing particle buffer");
+        if (f32) {
+            bool al = aligned16(b->cell);
+            for (int a = 0; a < 3; ++a) al = al && aligned16(b->pos[a]) && aligned16(b->u[a]);
+            if (desc->per_particle_w) al = al && aligned16(b->w);
+            if (!al) return fail(s, EMPIC_E_ARG, "FP32 particle buffers must be 16-byte aligned");
+        }
+    }
+    if (f32 && !buf1) return fail(s, EMPIC_E_ARG, "the FP32 path needs a second buffer set for sorting");
+    SpeciesState &S = s->sp[s->nsp];
+    S.desc = *desc;
+    S.capacity = capacity;
+    S.buf[0] = *buf0;
+    S.has_alt = buf1 != nullptr;
+    if (buf1) S.buf[1] = *buf1;
+    S.cur = 0;
+    S.host_count = 0;
+    launch_fill_i32(S.tile_off, s->ti.ntiles + 2, 0, s->stream);  // offsets and count
+    const int id = s->nsp;
+    s->nsp += 1;
+    DevSpecies D;
+    D.p[0] = species_params(s, id, 0);
+    D.p[1] = species_params(s, id, S.has_alt ? 1 : 0);
+    D.r = (float)(desc->q * s->g.dt / (2.0 * desc->m));
+    const double dV = s->g.d[0] * s->g.d[1] * s->g.d[2];
+    const double wsp = desc->per_particle_w ? 1.0 : desc->w;
+    for (int a = 0; a < 3; ++a) D.qc[a] = (float)(desc->q * wsp * s->g.d[a] / (s->g.dt * dV));
+    launch_write_species(s->table + id, D, s->stream);
+    if (species_id_out) *species_id_out = id;
+    s->need_sort = true;
+    return check_launch(s, "add_species");
+}
+
+empic_status empic_load_particles_f64(empic_sim *s, int32_t sp, int64_t count,
+                                      const double *pos_xyz, const double *u_xyz, const double *w,
+                                      const int32_t *ids) {
+    EMPIC_GUARD(s);
+    if (sp < 0 || sp >= s->nsp) return fail(s, EMPIC_E_ARG, "no such species");
+    SpeciesState &S = s->sp[sp];
+    if (count < 0 || count > S.capacity) return fail(s, EMPIC_E_CAPACITY, "count exceeds capacity");
+    if (count > 0 && (!pos_xyz || !u_xyz)) return fail(s, EMPIC_E_ARG, "null position or momentum");
+    if (S.desc.per_particle_w && count > 0 && !w)
+        return fail(s, EMPIC_E_ARG, "species takes per-particle weights");
+    S.cur = 0;
+    const SpeciesP p = species_params(s, sp, 0);
+    if (fp64(s)) {
+        launch_load_f64(s->g, p, count, pos_xyz, u_xyz, w, ids, s->fault, s->stream);
+        launch_fill_i32(S.dcount, 1, (int32_t)count, s->stream);
+    } else {
+        launch_load_f32(s->g, p, count, pos_xyz, u_xyz, w, ids, s->fault, s->stream);
+    }
+    S.host_count = count;
+    s->need_sort = true;
+    s->rho_prev_step = -1;
+    return check_launch(s, "load_particles");
+}
+
+empic_status empic_store_particles_f64(empic_sim *s, int32_t sp, double *pos_xyz, double *u_xyz,
+                                       int32_t *ids, int64_t *count_out) {
+    EMPIC_GUARD(s);
+    if (sp < 0 || sp >= s->nsp || !pos_xyz || !u_xyz || !count_out)
+        return fail(s, EMPIC_E_ARG, "bad store arguments");
+    SpeciesState &S = s->sp[sp];
+    const SpeciesP p = species_params(s, sp, S.cur);
+    if (fp64(s)) {
+        launch_store_f64(p, S.host_count, pos_xyz, u_xyz, ids, s->stream);
+        EMPIC_HIP(hipGetLastError());
+        EMPIC_HIP(hipStreamSynchronize(s->stream));
+        *count_out = S.host_count;
+    } else {
+        launch_store_f32(s->g, p, pos_xyz, u_xyz, ids, s->stream);
+        EMPIC_HIP(hipGetLastError());
+        int32_t c = 0;
+        EMPIC_HIP(hipMemcpyAsync(&c, S.dcount, 4, hipMemcpyDeviceToHost, s->stream));
+        EMPIC_HIP(hipStreamSynchronize(s->stream));
+        *count_out = c;
+    }
+    return EMPIC_OK;
+}
+
+empic_status empic_current_buffer(empic_sim *s, int32_t sp, int32_t *which) {
+    EMPIC_GUARD(s);
+    if (sp < 0 || sp >= s->nsp || !which) return fail(s, EMPIC_E_ARG, "bad arguments");
+    *which = s->sp[sp].cur;
+    return EMPIC_OK;
+}
+
+empic_status empic_set_background(empic_sim *s, double rho_bg) {
+    EMPIC_GUARD(s);
+    if (!std::isfinite(rho_bg)) return fail(s, EMPIC_E_ARG, "non-finite background");
+    s->rho_bg = rho_bg;
+    return EMPIC_OK;
+}
+
+empic_status empic_set_laser(empic_sim *s, const empic_laser_desc *laser) {
+    EMPIC_GUARD(s);
+    if (!laser) return fail(s, EMPIC_E_ARG, "null laser");
+    if (laser->enabled) {
+        if (laser->i_s < 0 || laser->i_s > s->g.n[0]) return fail(s, EMPIC_E_ARG, "laser plane outside the grid");
+        if (!(laser->tau > 0.0) || !(laser->w0 > 0.0)) return fail(s, EMPIC_E_ARG, "laser needs tau, w0 > 0");
+    }
+    s->laser = *laser;
+    return EMPIC_OK;
+}
+
+empic_status empic_sort(empic_sim *s) {
+    EMPIC_GUARD(s);
+    if (fp64(s)) return EMPIC_OK;  // the plain path keeps its order
+    if (s->nsp == 0) return EMPIC_OK;
+    do_sort(s);
+    return check_launch(s, "sort");
+}
+
+empic_status empic_step(empic_sim *s, int32_t nsteps) {
+    EMPIC_GUARD(s);
+    if (!s->bound) return fail(s, EMPIC_E_ARG, "fields not bound");
+    if (nsteps < 0) return fail(s, EMPIC_E_ARG, "negative step count");
+    for (int k = 0; k < nsteps; ++k) {
+        if (fp64(s)) {
+            one_step<double>(s);
+        } else {
+            const int S = s->desc.sort_every;
+            if (s->nsp > 0 && (s->need_sort || (S > 0 && s->nstep % S == 0))) do_sort(s);
+            one_step<float>(s);
+        }
+    }
+    return check_launch(s, "step");
+}
+
+empic_status empic_deposit_rho(empic_sim *s, int32_t sp, double *rho_out) {
+    EMPIC_GUARD(s);
+    if (!rho_out || sp < -1 || sp >= s->nsp) return fail(s, EMPIC_E_ARG, "bad rho arguments");
+    launch_zero_f64(rho_out, s->g.V, s->stream);
+    for (int i = 0; i < s->nsp; ++i) {
+        if (sp >= 0 && i != sp) continue;
+        const SpeciesP p = species_params(s, i, s->sp[i].cur);
+        if (fp64(s))
+            launch_rho_f64(s->g, p, s->sp[i].host_count, rho_out, s->stream);
+        else
+            launch_rho_f32(s->g, p, rho_out, s->stream);
+    }
+    return check_launch(s, "deposit_rho");
+}
+
+empic_status empic_diagnostics(empic_sim *s, empic_diag *out) {
+    EMPIC_GUARD(s);
+    if (!out) return fail(s, EMPIC_E_ARG, "null diag");
+    if (!s->bound) return fail(s, EMPIC_E_ARG, "fields not bound");
+    std::memset(out, 0, sizeof(*out));
+    launch_zero_f64(s->partials, (long long)NQ * PSTRIDE, s->stream);
+    empic_status st = empic_deposit_rho(s, -1, s->rho_cur);
+    if (st != EMPIC_OK) return st;
+    const bool cont = s->rho_prev_step >= 0 && s->rho_prev_step == s->nstep - 1;
+    if (fp64(s)) {
+        double *E[3], *B[3], *J[3], *Bb[3];
+        field_ptrs<double>(s, E, B, J, Bb);
+        launch_gauss<double>(s->g, E, s->rho_cur, s->rho_bg, s->partials, s->stream);
+        if (cont) launch_continuity<double>(s->g, J, s->rho_cur, s->rho_prev, s->partials, s->stream);
+        launch_field_energy<double>(s->g, E, B, s->partials, s->stream);
+        launch_faraday<double>(s->g, E, B, Bb, nullptr, false, s->stream);
+        for (int i = 0; i < s->nsp; ++i) {
+            const SpeciesP p = species_params(s, i, 0);
+            launch_kinetic_f64(p, s->sp[i].host_count, s->partials + (Q_KM + i) * PSTRIDE, s->stream);
+            launch_dry_push_f64(s->g, E, Bb, p, s->sp[i].host_count,
+                                s->partials + (Q_KP + i) * PSTRIDE, s->fault, s->stream);
+        }
+    } else {
+        float *E[3], *B[3], *J[3], *Bb[3];
+        field_ptrs<float>(s, E, B, J, Bb);
+        launch_gauss<float>(s->g, E, s->rho_cur, s->rho_bg, s->partials, s->stream);
+        if (cont) launch_continuity<float>(s->g, J, s->rho_cur, s->rho_prev, s->partials, s->stream);
+        launch_field_energy<float>(s->g, E, B, s->partials, s->stream);
+        launch_faraday<float>(s->g, E, B, Bb, nullptr, false, s->stream);
+        for (int i = 0; i < s->nsp; ++i) {
+            const SpeciesP p = species_params(s, i, s->sp[i].cur);
+            launch_kinetic_f32(p, s->partials + (Q_KM + i) * PSTRIDE, s->stream);
+            launch_dry_push_f32(s->g, E, Bb, p, s->partials + (Q_KP + i) * PSTRIDE, s->fault,
+                                s->stream);
+        }
+    }
+    launch_final_reduce(s->partials, s->result, s->stream);
+    st = check_launch(s, "diagnostics");
+    if (st != EMPIC_OK) return st;
+    double res[NQ];
+    uint32_t fw[4] = {0, 0, 0, 0};
+    EMPIC_HIP(hipMemcpyAsync(res, s->result, sizeof res, hipMemcpyDeviceToHost, s->stream));
+    EMPIC_HIP(hipMemcpyAsync(fw, s->fault, 16, hipMemcpyDeviceToHost, s->stream));
+    int32_t counts[EMPIC_MAX_SPECIES] = {0, 0, 0, 0};
+    for (int i = 0; i < s->nsp; ++i)
+        EMPIC_HIP(hipMemcpyAsync(&counts[i], s->sp[i].dcount, 4, hipMemcpyDeviceToHost, s->stream));
+    EMPIC_HIP(hipStreamSynchronize(s->stream));
+    std::swap(s->rho_cur, s->rho_prev);
+    s->rho_prev_step = s->nstep;
+    const double dV = s->g.d[0] * s->g.d[1] * s->g.d[2];
+    out->step = s->nstep;
+    out->t = s->nstep * s->g.dt;
+    out->U_E = 0.5 * dV * res[Q_EE];
+    out->U_B = 0.5 * dV * res[Q_BB];
+    double ksum = 0.0;
+    for (int i = 0; i < s->nsp; ++i) {
+        out->K_minus[i] = res[Q_KM + i];
+        out->K_plus[i] = res[Q_KP + i];
+        out->K[i] = 0.5 * (out->K_minus[i] + out->K_plus[i]);
+        ksum += out->K[i];
+        out->n_particles[i] = fp64(s) ? s->sp[i].host_count : counts[i];
+    }
+    out->U_tot = out->U_E + out->U_B + ksum;
+    long long nodes = s->g.V;
+    out->gauss_max = res[Q_GMAX];
+    out->gauss_l2 = std::sqrt(res[Q_G2] / (double)nodes);
+    out->cont_valid = cont ? 1 : 0;
+    out->cont_max = cont ? res[Q_CMAX] : 0.0;
+    out->rho_max = cont ? res[Q_RMAX] : 0.0;
+    out->fault_word = fw[0];
+    out->fallback_particles = (int64_t)(((unsigned long long)fw[3] << 32) | fw[2]);
+    return fault_status(s, fw[0]);
+}
+
+empic_status empic_particle_count(empic_sim *s, int32_t sp, int64_t *n) {
+    EMPIC_GUARD(s);
+    if (sp < 0 || sp >= s->nsp || !n) return fail(s, EMPIC_E_ARG, "bad arguments");
+    if (fp64(s)) {
+        *n = s->sp[sp].host_count;
+        return EMPIC_OK;
+    }
+    int32_t c = 0;
+    EMPIC_HIP(hipMemcpyAsync(&c, s->sp[sp].dcount, 4, hipMemcpyDeviceToHost, s->stream));
+    EMPIC_HIP(hipStreamSynchronize(s->stream));
+    *n = c;
+    return EMPIC_OK;
+}
+
+empic_status empic_sync(empic_sim *s) {
+    EMPIC_GUARD(s);
+    EMPIC_HIP(hipGetLastError());
+    uint32_t w = 0;
+    const empic_status st = read_fault(s, &w);
+    if (st != EMPIC_OK) return st;
+    return fault_status(s, w);
+}
+
+empic_status empic_enable_timing(empic_sim *s, int32_t enable) {
+    EMPIC_GUARD(s);
+    s->timing = enable != 0;
+    return EMPIC_OK;
+}
+
+empic_status empic_kernel_times(empic_sim *s, double *push_ms, int64_t *push_launches,
+                                double *field_ms, int64_t *field_launches, double *sort_ms,
+                                int64_t *sort_launches) {
+    EMPIC_GUARD(s);
+    EMPIC_HIP(hipStreamSynchronize(s->stream));
+    for (TimedEvent &t : s->events) {
+        float ms = 0.f;
+        EMPIC_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+        s->t_ms[t.kind] += ms;
+        s->t_n[t.kind] += 1;
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    s->events.clear();
+    if (push_ms) *push_ms = s->t_ms[0];
+    if (push_launches) *push_launches = s->t_n[0];
+    if (field_ms) *field_ms = s->t_ms[1];
+    if (field_launches) *field_launches = s->t_n[1];
+    if (sort_ms) *sort_ms = s->t_ms[2];
+    if (sort_launches) *sort_launches = s->t_n[2];
+    for (int k = 0; k < 3; ++k) {
+        s->t_ms[k] = 0;
+        s->t_n[k] = 0;
+    }
+    return EMPIC_OK;
+}
+
+const char *empic_last_error(const empic_sim *s) { return s ? s->err.c_str() : "null handle"; }
+
+void empic_destroy(empic_sim *s) {
+    if (!s) return;
+    for (TimedEvent &t : s->events) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,331 @@
+// fields.hip -- Yee FDTD kernels for gfx950 (Sec. 2.3 of KEMPIC-3D).
+//
+// One thread per grid point, x fastest across a wavefront so that every
+// component load and store is coalesced; a thread updates all three
+// components at its point.  Periodic neighbours wrap; on an absorbing axis
+// the validity rules below keep every neighbour inside the stored array.
+//
+// Bytes per cell (FP32): Faraday reads E, B (24) and writes B, Bbar (24) and
+// zeroes J (12); Ampere reads E, B, J (36) and writes E (12).
+#include "internal.hpp"
+
+namespace empic {
+
+namespace {
+
+struct Pt {
+    int idx[3];
+    long long p;
+    long long st[3];  // strides
+};
+
+__device__ inline bool make_point(const GridP &g, Pt &q) {
+    q.idx[0] = blockIdx.x * blockDim.x + threadIdx.x;
+    q.idx[1] = blockIdx.y * blockDim.y + threadIdx.y;
+    q.idx[2] = blockIdx.z;
+    if (q.idx[0] >= g.ext[0] || q.idx[1] >= g.ext[1]) return false;
+    q.st[0] = 1;
+    q.st[1] = g.ext[0];
+    q.st[2] = (long long)g.ext[0] * g.ext[1];
+    q.p = q.idx[0] + q.st[1] * q.idx[1] + q.st[2] * q.idx[2];
+    return true;
+}
+
+// offset of the +1 / -1 neighbour along axis a (periodic wrap)
+__device__ inline long long up(const GridP &g, const Pt &q, int a) {
+    return (g.bc[a] == EMPIC_BC_PERIODIC && q.idx[a] == g.n[a] - 1) ? -(long long)(g.n[a] - 1) * q.st[a]
+                                                                   : q.st[a];
+}
+__device__ inline long long dn(const GridP &g, const Pt &q, int a) {
+    return (g.bc[a] == EMPIC_BC_PERIODIC && q.idx[a] == 0) ? (long long)(g.n[a] - 1) * q.st[a]
+                                                           : -q.st[a];
+}
+
+// A component half-staggered along absorbing axis a has n values: entry n is padding.
+__device__ inline bool valid_B(const GridP &g, const Pt &q, int c) {
+    for (int a = 0; a < 3; ++a)
+        if (g.bc[a] == EMPIC_BC_ABSORBING && a != c && q.idx[a] == g.n[a]) return false;
+    return true;
+}
+// E_c updated by Ampere: valid and not tangential on an absorbing face.
+__device__ inline bool ampere_E(const GridP &g, const Pt &q, int c) {
+    for (int a = 0; a < 3; ++a) {
+        if (g.bc[a] != EMPIC_BC_ABSORBING) continue;
+        if (a == c && q.idx[a] == g.n[a]) return false;
+        if (a != c && (q.idx[a] == 0 || q.idx[a] == g.n[a])) return false;
+    }
+    return true;
+}
+
+template <typename T>
+__global__ void k_faraday(GridP g, const T *__restrict__ Ex, const T *__restrict__ Ey,
+                          const T *__restrict__ Ez, T *__restrict__ Bx, T *__restrict__ By,
+                          T *__restrict__ Bz, T *__restrict__ Bbx, T *__restrict__ Bby,
+                          T *__restrict__ Bbz, T *__restrict__ Jx, T *__restrict__ Jy,
+                          T *__restrict__ Jz, int write_B) {
+    Pt q;
+    if (!make_point(g, q)) return;
+    const long long p = q.p;
+    if (Jx) {
+        Jx[p] = T(0);
+        Jy[p] = T(0);
+        Jz[p] = T(0);
+    }
+    const T dt = (T)g.dt;
+    const T ix = (T)g.inv_d[0], iy = (T)g.inv_d[1], iz = (T)g.inv_d[2];
+    // B^{n+1/2} = B^{n-1/2} - dt curl E^n (forward differences); Bbar = average
+    if (valid_B(g, q, 0)) {
+        const T curl = (Ez[p + up(g, q, 1)] - Ez[p]) * iy - (Ey[p + up(g, q, 2)] - Ey[p]) * iz;
+        const T old = Bx[p], nw = old - dt * curl;
+        if (write_B) Bx[p] = nw;
+        Bbx[p] = T(0.5) * (old + nw);
+    } else {
+        Bbx[p] = T(0);
+    }
+    if (valid_B(g, q, 1)) {
+        const T curl = (Ex[p + up(g, q, 2)] - Ex[p]) * iz - (Ez[p + up(g, q, 0)] - Ez[p]) * ix;
+        const T old = By[p], nw = old - dt * curl;
+        if (write_B) By[p] = nw;
+        Bby[p] = T(0.5) * (old + nw);
+    } else {
+        Bby[p] = T(0);
+    }
+    if (valid_B(g, q, 2)) {
+        const T curl = (Ey[p + up(g, q, 0)] - Ey[p]) * ix - (Ex[p + up(g, q, 1)] - Ex[p]) * iy;
+        const T old = Bz[p], nw = old - dt * curl;
+        if (write_B) Bz[p] = nw;
+        Bbz[p] = T(0.5) * (old + nw);
+    } else {
+        Bbz[p] = T(0);
+    }
+}
+
+template <typename T>
+__global__ void k_ampere(GridP g, T *__restrict__ Ex, T *__restrict__ Ey, T *__restrict__ Ez,
+                         const T *__restrict__ Bx, const T *__restrict__ By,
+                         const T *__restrict__ Bz, const T *__restrict__ Jx,
+                         const T *__restrict__ Jy, const T *__restrict__ Jz) {
+    Pt q;
+    if (!make_point(g, q)) return;
+    const long long p = q.p;
+    const T dt = (T)g.dt;
+    const T ix = (T)g.inv_d[0], iy = (T)g.inv_d[1], iz = (T)g.inv_d[2];
+    // E^{n+1} = E^n + dt curl B^{n+1/2} - dt J^{n+1/2} (backward differences)
+    if (ampere_E(g, q, 0)) {
+        const T curl = (Bz[p] - Bz[p + dn(g, q, 1)]) * iy - (By[p] - By[p + dn(g, q, 2)]) * iz;
+        Ex[p] = Ex[p] + (dt * curl - dt * Jx[p]);
+    }
+    if (ampere_E(g, q, 1)) {
+        const T curl = (Bx[p] - Bx[p + dn(g, q, 2)]) * iz - (Bz[p] - Bz[p + dn(g, q, 0)]) * ix;
+        Ey[p] = Ey[p] + (dt * curl - dt * Jy[p]);
+    }
+    if (ampere_E(g, q, 2)) {
+        const T curl = (By[p] - By[p + dn(g, q, 0)]) * ix - (Bx[p] - Bx[p + dn(g, q, 1)]) * iy;
+        Ez[p] = Ez[p] + (dt * curl - dt * Jz[p]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// First-order Mur faces (READING of the boundary module: tangential E on the
+// faces of an absorbing axis).  planes[a][c'][q][point], q = index 0, 1, n-1,
+// n along a, point = i_b1 + ext[b1] * i_b2 over the other two axes.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_mur_save(GridP g, int a, T *Ex, T *Ey, T *Ez, T *planes, long long pstride) {
+    const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    const long long npt = (long long)g.ext[b1] * g.ext[b2];
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= npt) return;
+    const int i1 = (int)(t % g.ext[b1]), i2 = (int)(t / g.ext[b1]);
+    T *E[3] = {Ex, Ey, Ez};
+    long long st[3] = {1, g.ext[0], (long long)g.ext[0] * g.ext[1]};
+    const int qidx[4] = {0, 1, g.n[a] - 1, g.n[a]};
+    int ci = 0;
+    for (int c = 0; c < 3; ++c) {
+        if (c == a) continue;
+        for (int qq = 0; qq < 4; ++qq) {
+            const long long p = st[b1] * i1 + st[b2] * i2 + st[a] * qidx[qq];
+            planes[(((long long)a * 2 + ci) * 4 + qq) * pstride + t] = E[c][p];
+        }
+        ++ci;
+    }
+}
+
+template <typename T>
+__global__ void k_mur_apply(GridP g, int a, T *Ex, T *Ey, T *Ez, const T *planes,
+                            long long pstride) {
+    const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    const long long npt = (long long)g.ext[b1] * g.ext[b2];
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= npt) return;
+    const int i1 = (int)(t % g.ext[b1]), i2 = (int)(t / g.ext[b1]);
+    T *E[3] = {Ex, Ey, Ez};
+    long long st[3] = {1, g.ext[0], (long long)g.ext[0] * g.ext[1]};
+    const T coef = (T)((g.dt - g.d[a]) / (g.dt + g.d[a]));
+    int ci = 0;
+    for (int c = 0; c < 3; ++c) {
+        if (c == a) continue;
+        const T *pl = planes + ((long long)a * 2 + ci) * 4 * pstride;
+        const long long base = st[b1] * i1 + st[b2] * i2;
+        // face at index 0: E_0^{n+1} = E_1^n + coef (E_1^{n+1} - E_0^n)
+        E[c][base] = pl[1 * pstride + t] + coef * (E[c][base + st[a]] - pl[0 * pstride + t]);
+        // face at index n: E_n^{n+1} = E_{n-1}^n + coef (E_{n-1}^{n+1} - E_n^n)
+        const long long pn = base + st[a] * g.n[a];
+        E[c][pn] = pl[2 * pstride + t] + coef * (E[c][pn - st[a]] - pl[3 * pstride + t]);
+        ++ci;
+    }
+}
+
+// Soft current sheet J_y on x-node plane i_s (READING of the external-source
+// module), applied to E after Ampere: E_y -= dt J_sheet(t^{n+1/2}).
+template <typename T>
+__global__ void k_laser(GridP g, T *Ey, empic_laser_desc L, double t_half) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    const int cy = g.n[1];                                              // E_y half along y
+    const int cz = g.bc[2] == EMPIC_BC_ABSORBING ? g.n[2] + 1 : g.n[2];  // node along z
+    if (j >= cy || k >= cz) return;
+    if (g.bc[0] == EMPIC_BC_ABSORBING && (L.i_s == 0 || L.i_s == g.n[0])) return;
+    if (g.bc[2] == EMPIC_BC_ABSORBING && (k == 0 || k == g.n[2])) return;
+    const double y = ((double)j + 0.5) * g.d[1];
+    const double z = (double)k * g.d[2];
+    const double r2 = (y - L.yc) * (y - L.yc) + (z - L.zc) * (z - L.zc);
+    const double tt = t_half - L.t0;
+    const double einc = L.a0 * exp(-r2 / (L.w0 * L.w0)) *
+                        exp(-2.0 * log(2.0) * tt * tt / (L.tau * L.tau)) * sin(L.omega0 * tt);
+    const double Jy = -2.0 * einc / g.d[0];
+    const long long p = L.i_s + (long long)g.ext[0] * (j + (long long)g.ext[1] * k);
+    Ey[p] -= (T)(g.dt * Jy);
+}
+
+// FP64 partial sums of |E|^2 and B^{n-1/2}.B^{n+1/2} (B^{n+1/2} formed on the fly)
+template <typename T>
+__global__ void k_field_energy(GridP g, const T *__restrict__ Ex, const T *__restrict__ Ey,
+                               const T *__restrict__ Ez, const T *__restrict__ Bx,
+                               const T *__restrict__ By, const T *__restrict__ Bz,
+                               double *partials) {
+    __shared__ double sm[16];
+    double ee = 0.0, bb = 0.0;
+    const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const T dt = (T)g.dt;
+    const T ix = (T)g.inv_d[0], iy = (T)g.inv_d[1], iz = (T)g.inv_d[2];
+    for (int k = blockIdx.z; k < g.ext[2]; k += gridDim.z)
+        for (int j = blockIdx.y * blockDim.y + threadIdx.y; j < g.ext[1]; j += gridDim.y * blockDim.y)
+            for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.ext[0];
+                 i += gridDim.x * blockDim.x) {
+                Pt q;
+                q.idx[0] = i;
+                q.idx[1] = j;
+                q.idx[2] = k;
+                q.st[0] = 1;
+                q.st[1] = g.ext[0];
+                q.st[2] = (long long)g.ext[0] * g.ext[1];
+                const long long p = i + q.st[1] * j + q.st[2] * k;
+                ee += (double)Ex[p] * Ex[p] + (double)Ey[p] * Ey[p] + (double)Ez[p] * Ez[p];
+                if (valid_B(g, q, 0)) {
+                    const T c = (Ez[p + up(g, q, 1)] - Ez[p]) * iy - (Ey[p + up(g, q, 2)] - Ey[p]) * iz;
+                    bb += (double)Bx[p] * (double)(Bx[p] - dt * c);
+                }
+                if (valid_B(g, q, 1)) {
+                    const T c = (Ex[p + up(g, q, 2)] - Ex[p]) * iz - (Ez[p + up(g, q, 0)] - Ez[p]) * ix;
+                    bb += (double)By[p] * (double)(By[p] - dt * c);
+                }
+                if (valid_B(g, q, 2)) {
+                    const T c = (Ey[p + up(g, q, 0)] - Ey[p]) * ix - (Ex[p + up(g, q, 1)] - Ex[p]) * iy;
+                    bb += (double)Bz[p] * (double)(Bz[p] - dt * c);
+                }
+            }
+    const double se = block_reduce<false>(ee, sm);
+    const double sb = block_reduce<false>(bb, sm);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        partials[Q_EE * PSTRIDE + bid] = se;
+        partials[Q_BB * PSTRIDE + bid] = sb;
+    }
+}
+
+dim3 point_grid(const GridP &g) { return dim3((g.ext[0] + 63) / 64, (g.ext[1] + 3) / 4, g.ext[2]); }
+
+}  // namespace
+
+// Grid of the (64, 4) point reductions: every kernel strides over all three
+// axes, and gx * gy * gz <= PSTRIDE keeps one partial slot per workgroup.
+dim3 reduction_grid(const GridP &g) {
+    int gx = (g.ext[0] + 63) / 64;
+    if (gx > 64) gx = 64;
+    int gy = (g.ext[1] + 3) / 4;
+    if (gy > PSTRIDE / gx) gy = PSTRIDE / gx;
+    int gz = PSTRIDE / (gx * gy);
+    if (gz > g.ext[2]) gz = g.ext[2];
+    if (gz < 1) gz = 1;
+    return dim3(gx, gy, gz);
+}
+
+template <typename T>
+void launch_faraday(const GridP &g, T *const E[3], T *const B[3], T *const Bbar[3],
+                    T *const J[3], bool write_B, hipStream_t s) {
+    hipLaunchKernelGGL(k_faraday<T>, point_grid(g), dim3(64, 4), 0, s, g, E[0], E[1], E[2], B[0],
+                       B[1], B[2], Bbar[0], Bbar[1], Bbar[2], J ? J[0] : nullptr,
+                       J ? J[1] : nullptr, J ? J[2] : nullptr, write_B ? 1 : 0);
+}
+
+template <typename T>
+void launch_ampere(const GridP &g, T *const E[3], T *const B[3], T *const J[3], hipStream_t s) {
+    hipLaunchKernelGGL(k_ampere<T>, point_grid(g), dim3(64, 4), 0, s, g, E[0], E[1], E[2], B[0],
+                       B[1], B[2], J[0], J[1], J[2]);
+}
+
+template <typename T>
+void launch_mur_save(const GridP &g, T *const E[3], T *planes, long long pstride, hipStream_t s) {
+    for (int a = 0; a < 3; ++a) {
+        if (g.bc[a] != EMPIC_BC_ABSORBING) continue;
+        const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+        const long long npt = (long long)g.ext[b1] * g.ext[b2];
+        hipLaunchKernelGGL(k_mur_save<T>, dim3((unsigned)((npt + 255) / 256)), dim3(256), 0, s, g,
+                           a, E[0], E[1], E[2], planes, pstride);
+    }
+}
+
+template <typename T>
+void launch_mur_apply(const GridP &g, T *const E[3], const T *planes, long long pstride,
+                      hipStream_t s) {
+    for (int a = 0; a < 3; ++a) {
+        if (g.bc[a] != EMPIC_BC_ABSORBING) continue;
+        const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+        const long long npt = (long long)g.ext[b1] * g.ext[b2];
+        hipLaunchKernelGGL(k_mur_apply<T>, dim3((unsigned)((npt + 255) / 256)), dim3(256), 0, s,
+                           g, a, E[0], E[1], E[2], planes, pstride);
+    }
+}
+
+template <typename T>
+void launch_laser(const GridP &g, T *const E[3], const empic_laser_desc &L, double t_half,
+                  hipStream_t s) {
+    const int cz = g.bc[2] == EMPIC_BC_ABSORBING ? g.n[2] + 1 : g.n[2];
+    hipLaunchKernelGGL(k_laser<T>, dim3((g.n[1] + 63) / 64, cz), dim3(64), 0, s, g, E[1], L,
+                       t_half);
+}
+
+template <typename T>
+void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *partials,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_field_energy<T>, reduction_grid(g), dim3(64, 4), 0, s, g, E[0], E[1],
+                       E[2], B[0], B[1], B[2], partials);
+}
+
+#define EMPIC_INST(T)                                                                          \
+    template void launch_faraday<T>(const GridP &, T *const[3], T *const[3], T *const[3],      \
+                                    T *const[3], bool, hipStream_t);                           \
+    template void launch_ampere<T>(const GridP &, T *const[3], T *const[3], T *const[3],       \
+                                   hipStream_t);                                               \
+    template void launch_mur_save<T>(const GridP &, T *const[3], T *, long long, hipStream_t); \
+    template void launch_mur_apply<T>(const GridP &, T *const[3], const T *, long long,        \
+                                      hipStream_t);                                            \
+    template void launch_laser<T>(const GridP &, T *const[3], const empic_laser_desc &, double, \
+                                  hipStream_t);                                                \
+    template void launch_field_energy<T>(const GridP &, T *const[3], T *const[3], double *,    \
+                                         hipStream_t);
+EMPIC_INST(float)
+EMPIC_INST(double)
+#undef EMPIC_INST
+
+}  // namespace empic

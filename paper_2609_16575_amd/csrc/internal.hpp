@@ -1,0 +1,199 @@
+// internal.hpp -- device-side types and helpers shared by the libempic
+// translation units (kernels + runtime).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "empic.h"
+
+namespace empic {
+
+// ---------------------------------------------------------------------------
+// Grid parameters passed by value to every kernel.
+// ---------------------------------------------------------------------------
+struct GridP {
+    int n[3];     // cells per axis
+    int ext[3];   // stored entries per axis (n + 1 on an absorbing axis)
+    int bc[3];    // EMPIC_BC_*
+    double d[3];  // cell sizes
+    double inv_d[3];
+    double dt;
+    long long V;  // ext0 * ext1 * ext2
+};
+
+// Tile of cells owned by one workgroup of the fused FP32 particle kernel.
+constexpr int TX = 8, TY = 8, TZ = 8;
+constexpr int TC = TX * TY * TZ;
+// Drift margin: particles up to MARGIN cells outside their tile (moved since
+// the last sort) are still served from the tile's LDS windows.
+constexpr int MARGIN = 1;
+// LDS field window (gather stencil: cells -1..+1 around a particle cell).
+constexpr int FWX = TX + 2 * MARGIN + 2, FWY = TY + 2 * MARGIN + 2, FWZ = TZ + 2 * MARGIN + 2;
+// LDS current window (second ZigZag segment may sit one cell further, edges +1).
+constexpr int JWX = TX + 2 * MARGIN + 3, JWY = TY + 2 * MARGIN + 3, JWZ = TZ + 2 * MARGIN + 3;
+constexpr int FW3 = FWX * FWY * FWZ;
+constexpr int JW3 = JWX * JWY * JWZ;
+constexpr int PUSH_THREADS = 256;
+constexpr int PPT = 8;  // consecutive particles per thread
+static_assert(JWX <= 16 && JWY <= 16 && JWZ <= 16, "window index tables hold 16 rows");
+
+// Packed cell index of the FP32 path: i | j << 11 | k << 22; all ones = removed.
+constexpr uint32_t DEAD = 0xFFFFFFFFu;
+__host__ __device__ inline uint32_t pack_cell(int i, int j, int k) {
+    return (uint32_t)i | ((uint32_t)j << 11) | ((uint32_t)k << 22);
+}
+__host__ __device__ inline int cell_i(uint32_t c) { return (int)(c & 0x7FFu); }
+__host__ __device__ inline int cell_j(uint32_t c) { return (int)((c >> 11) & 0x7FFu); }
+__host__ __device__ inline int cell_k(uint32_t c) { return (int)(c >> 22); }
+
+struct TileInfo {
+    int nt[3];      // tiles per axis
+    int ntiles;
+    long long NK;   // ntiles * TC sort keys
+};
+
+__host__ __device__ inline long long sort_key(const TileInfo &t, int i, int j, int k) {
+    const int tx = i / TX, ty = j / TY, tz = k / TZ;
+    const int lx = i - tx * TX, ly = j - ty * TY, lz = k - tz * TZ;
+    const long long tile = tx + (long long)t.nt[0] * (ty + (long long)t.nt[1] * tz);
+    return tile * TC + (lx + TX * (ly + TY * lz));
+}
+
+// Per-species launch parameters of the particle kernels.
+struct SpeciesP {
+    uint32_t *cell;
+    void *pos[3];
+    void *u[3];
+    int32_t *id;
+    void *w;          // per-particle weight or nullptr
+    const int32_t *tile_off;  // FP32: ntiles + 1 particle offsets after the last sort
+    int32_t *count;   // device slot count
+    long long capacity;
+    double q, m, w_species;
+    int per_particle_w;
+};
+
+// Device-side table of a species' parameters for both buffer sets, written
+// once when the species is registered; the fused kernel picks the current set
+// with a bit of `cur_mask` (kernel arguments are never indexed dynamically).
+struct DevSpecies {
+    SpeciesP p[2];
+    float r;      // q dt / (2 m)
+    float qc[3];  // q w d_a / (dt dV)  (w = 1 when per-particle)
+};
+void launch_write_species(DevSpecies *dst, const DevSpecies &v, hipStream_t s);
+
+constexpr int NQ = 16;       // reduction slots
+constexpr int RED_BLOCKS = 1024;  // grid-stride particle reductions
+enum Slot {
+    Q_EE = 0, Q_BB = 1, Q_KM = 2, Q_KP = 6, Q_GMAX = 10, Q_G2 = 11, Q_CMAX = 12, Q_RMAX = 13
+};
+
+__host__ __device__ inline bool slot_is_max(int q) {
+    return q == Q_GMAX || q == Q_CMAX || q == Q_RMAX;
+}
+
+// periodic wrap (an index at most one period away)
+__device__ inline int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// wave64 + block reductions in double
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+template <bool IS_MAX>
+__device__ inline double block_reduce(double v, double *smem /* >= 16 */) {
+    v = IS_MAX ? wave_max(v) : wave_sum(v);
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthr = blockDim.x * blockDim.y * blockDim.z;
+    const int lane = tid & 63, wid = tid >> 6;
+    __syncthreads();
+    if (lane == 0) smem[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (tid == 0) {
+        const int nw = (nthr + 63) >> 6;
+        r = smem[0];
+        for (int i = 1; i < nw; ++i) r = IS_MAX ? fmax(r, smem[i]) : r + smem[i];
+    }
+    return r;  // valid in thread 0 of the block
+}
+
+// Reduction partials: NQ slots of PSTRIDE per-block values each.
+constexpr int PSTRIDE = 16384;
+dim3 reduction_grid(const GridP &g);
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the kernel translation units).
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_faraday(const GridP &g, T *const E[3], T *const B[3], T *const Bbar[3],
+                    T *const J[3], bool write_B, hipStream_t s);
+template <typename T>
+void launch_ampere(const GridP &g, T *const E[3], T *const B[3], T *const J[3], hipStream_t s);
+template <typename T>
+void launch_mur_save(const GridP &g, T *const E[3], T *planes, long long plane_stride,
+                     hipStream_t s);
+template <typename T>
+void launch_mur_apply(const GridP &g, T *const E[3], const T *planes, long long plane_stride,
+                      hipStream_t s);
+template <typename T>
+void launch_laser(const GridP &g, T *const E[3], const empic_laser_desc &L, double t_half,
+                  hipStream_t s);
+template <typename T>
+void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *partials,
+                         hipStream_t s);
+
+// FP32 cell-relative path
+void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
+                       float *const Bbar[3], float *const J[3], const DevSpecies *tbl, int nsp,
+                       unsigned cur_mask, uint32_t *fault, unsigned long long *fallback,
+                       int2 *fb_list, unsigned *fb_count, long long fb_cap, hipStream_t s);
+void launch_dry_push_f32(const GridP &g, float *const E[3], float *const Bbar[3],
+                         const SpeciesP &sp, double *partial_slot, uint32_t *fault,
+                         hipStream_t s);
+void launch_kinetic_f32(const SpeciesP &sp, double *partial_slot, hipStream_t s);
+void launch_rho_f32(const GridP &g, const SpeciesP &sp, double *rho, hipStream_t s);
+void launch_load_f32(const GridP &g, const SpeciesP &sp, long long count, const double *pos,
+                     const double *u, const double *w, const int32_t *ids, uint32_t *fault,
+                     hipStream_t s);
+void launch_store_f32(const GridP &g, const SpeciesP &sp, double *pos, double *u, int32_t *ids,
+                      hipStream_t s);
+void launch_sort(const GridP &g, const TileInfo &ti, const SpeciesP &cur, const SpeciesP &alt,
+                 int32_t *counts, int32_t *scan_blocks, int32_t *rank, int32_t *tile_off,
+                 uint32_t *fault, hipStream_t s);
+
+// FP64 plain path
+void launch_push_f64(const GridP &g, double *const E[3], double *const Bbar[3],
+                     double *const J[3], const SpeciesP &sp, long long count, uint32_t *fault,
+                     hipStream_t s);
+void launch_dry_push_f64(const GridP &g, double *const E[3], double *const Bbar[3],
+                         const SpeciesP &sp, long long count, double *partial_slot,
+                         uint32_t *fault, hipStream_t s);
+void launch_kinetic_f64(const SpeciesP &sp, long long count, double *partial_slot,
+                        hipStream_t s);
+void launch_rho_f64(const GridP &g, const SpeciesP &sp, long long count, double *rho,
+                    hipStream_t s);
+void launch_load_f64(const GridP &g, const SpeciesP &sp, long long count, const double *pos,
+                     const double *u, const double *w, const int32_t *ids, uint32_t *fault,
+                     hipStream_t s);
+void launch_store_f64(const SpeciesP &sp, long long count, double *pos, double *u, int32_t *ids,
+                      hipStream_t s);
+
+// diagnostics
+void launch_zero_f64(double *p, long long n, hipStream_t s);
+template <typename T>
+void launch_gauss(const GridP &g, T *const E[3], const double *rho, double rho_bg,
+                  double *partials, hipStream_t s);
+template <typename T>
+void launch_continuity(const GridP &g, T *const J[3], const double *rho_now,
+                       const double *rho_prev, double *partials, hipStream_t s);
+void launch_final_reduce(const double *partials, double *result, hipStream_t s);
+void launch_fill_i32(int32_t *p, long long n, int32_t v, hipStream_t s);
+
+}  // namespace empic

@@ -1,0 +1,911 @@
+// push_f32.hip -- FP32 cell-relative particle path for gfx950.
+//
+// Storage: per particle a packed cell index (i | j<<11 | k<<22), an FP32
+// in-cell offset in [0,1) per axis and FP32 u = gamma v; 28 bytes (+4 for a
+// per-particle weight).  Offsets relative to the cell keep the rounding of a
+// position at 2^-24 of a cell wherever the particle is in the grid.
+//
+// k_push_fused: one workgroup per 8x8x8 tile of cells (particles counting-
+// sorted by tile, then cell).  The workgroup
+//   1. stages E^n and the centred B^n of the tile plus a halo into LDS
+//      (12^3 cells x 6 components),
+//   2. zeroes an LDS current window (13^3 x 3),
+//   3. streams its particles: each thread owns PPT = 8 consecutive particles,
+//      loaded/stored with 16-byte vector accesses, and for each particle does
+//      the staggered CIC gather from LDS (Sec. 2.5), the relativistic Boris
+//      push (Sec. 2.4), the move, and the ZigZag deposit (Sec. 2.5).  Current
+//      of consecutive particles that stay in the same cell is summed in
+//      registers and added to LDS once per run of the cell (12 LDS atomics
+//      per run instead of 12 per particle); the second ZigZag segment of a
+//      cell-crossing particle is added to LDS directly,
+//   4. adds the non-zero LDS current to global J with float atomics.
+// Particles that drifted more than MARGIN cells out of their tile since the
+// last sort are handled entirely through global memory (rare, counted).
+//
+// Algorithmic bytes per particle: 28 read + 28 written.
+#include "internal.hpp"
+
+namespace empic {
+
+namespace {
+
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+struct FusedArgs {
+    GridP g;
+    TileInfo ti;
+    const float *E[3];
+    const float *Bb[3];
+    float *J[3];
+    const DevSpecies *tbl;  // species parameters (device memory)
+    int nsp;
+    unsigned cur_mask;      // bit s: buffer set of species s
+    float dtd[3];           // dt / d_a
+    uint32_t *fault;
+    unsigned long long *fallback;  // cumulative count of out-of-window particles
+    int2 *fb_list;                 // (species, slot) of this step's out-of-window particles
+    unsigned *fb_count;            // [0] entries in fb_list, [1] block ticket of k_push_fallback
+    long long fb_cap;
+};
+
+// global index of cell-axis coordinate x on axis a: periodic wrap (any x),
+// -1 outside an absorbing axis' array
+__device__ __forceinline__ int gaxis(const GridP &g, int a, int x) {
+    if (g.bc[a] == EMPIC_BC_PERIODIC) {
+        int m = x % g.n[a];
+        return m < 0 ? m + g.n[a] : m;
+    }
+    return (x < 0 || x >= g.ext[a]) ? -1 : x;
+}
+
+// ---- global-memory versions (out-of-window particles, diagnostics) --------
+__device__ float tri_global(const GridP &g, const float *F, int i0, int j0, int k0, float fx,
+                            float fy, float fz) {
+    float v[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const int gx = gaxis(g, 0, i0 + (o & 1)), gy = gaxis(g, 1, j0 + ((o >> 1) & 1)),
+                  gz = gaxis(g, 2, k0 + (o >> 2));
+        v[o] = (gx < 0 || gy < 0 || gz < 0)
+                   ? 0.f
+                   : F[gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz)];
+    }
+    const float c00 = lerpf(v[0], v[1], fx), c10 = lerpf(v[2], v[3], fx);
+    const float c01 = lerpf(v[4], v[5], fx), c11 = lerpf(v[6], v[7], fx);
+    return lerpf(lerpf(c00, c10, fy), lerpf(c01, c11, fy), fz);
+}
+
+__device__ __forceinline__ void half_axis(float o, int l, int &h, float &fh) {
+    if (o < 0.5f) {
+        h = l - 1;
+        fh = o + 0.5f;
+    } else {
+        h = l;
+        fh = o - 0.5f;
+    }
+}
+
+__device__ void gather_global(const GridP &g, const float *const E[3], const float *const Bb[3],
+                              int ci, int cj, int ck, float ox, float oy, float oz, float Ep[3],
+                              float Bp[3]) {
+    int hx, hy, hz;
+    float fx, fy, fz;
+    half_axis(ox, ci, hx, fx);
+    half_axis(oy, cj, hy, fy);
+    half_axis(oz, ck, hz, fz);
+    Ep[0] = tri_global(g, E[0], hx, cj, ck, fx, oy, oz);
+    Ep[1] = tri_global(g, E[1], ci, hy, ck, ox, fy, oz);
+    Ep[2] = tri_global(g, E[2], ci, cj, hz, ox, oy, fz);
+    Bp[0] = tri_global(g, Bb[0], ci, hy, hz, ox, fy, fz);
+    Bp[1] = tri_global(g, Bb[1], hx, cj, hz, fx, oy, fz);
+    Bp[2] = tri_global(g, Bb[2], hx, hy, ck, fx, fy, oz);
+}
+
+// relativistic Boris push in FP32 (standard t/s rotation); returns 1/gamma of u+
+__device__ __forceinline__ float boris_f32(float &ux, float &uy, float &uz, const float E[3],
+                                           const float B[3], float r, float &gam) {
+    const float umx = fmaf(r, E[0], ux), umy = fmaf(r, E[1], uy), umz = fmaf(r, E[2], uz);
+    const float gm = sqrtf(fmaf(umx, umx, fmaf(umy, umy, fmaf(umz, umz, 1.f))));
+    const float ig = rcpf(gm);
+    const float tx = r * B[0] * ig, ty = r * B[1] * ig, tz = r * B[2] * ig;
+    const float sf = 2.f * rcpf(fmaf(tx, tx, fmaf(ty, ty, fmaf(tz, tz, 1.f))));
+    const float sx = sf * tx, sy = sf * ty, sz = sf * tz;
+    const float upx = umx + (umy * tz - umz * ty);
+    const float upy = umy + (umz * tx - umx * tz);
+    const float upz = umz + (umx * ty - umy * tx);
+    const float plx = umx + (upy * sz - upz * sy);
+    const float ply = umy + (upz * sx - upx * sz);
+    const float plz = umz + (upx * sy - upy * sx);
+    ux = fmaf(r, E[0], plx);
+    uy = fmaf(r, E[1], ply);
+    uz = fmaf(r, E[2], plz);
+    gam = sqrtf(fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.f))));
+    return rcpf(gam);
+}
+
+// Line integral of the bilinear CIC edge weights along a straight segment
+// inside one cell, given per axis the segment midpoint W (relative to that
+// cell) and its displacement D (cell units):
+// out[0..3] J_x edges (oy,oz) = (0,0),(1,0),(0,1),(1,1); out[4..7] J_y edges
+// (oz,ox); out[8..11] J_z edges (ox,oy).
+__device__ __forceinline__ void segment_weights(const float W[3], const float D[3],
+                                                const float amp_c[3], float out[12]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int b1 = (c + 1) % 3, b2 = (c + 2) % 3;
+        const float amp = amp_c[c] * D[c];
+        const float cr = D[b1] * D[b2] * (1.f / 12.f);
+        const float w1 = W[b1], w2 = W[b2];
+        out[4 * c + 0] = amp * ((1.f - w1) * (1.f - w2) + cr);
+        out[4 * c + 1] = amp * (w1 * (1.f - w2) - cr);
+        out[4 * c + 2] = amp * ((1.f - w1) * w2 - cr);
+        out[4 * c + 3] = amp * (w1 * w2 + cr);
+    }
+}
+
+// Midpoints and displacements of the ZigZag segments of a move from offset o
+// by dxi (end e = o + dxi as rounded, cell step dc per axis).  The
+// displacement is taken from dxi itself wherever the segment does not end on
+// a cell face, so that a small move keeps its full FP32 precision instead of
+// the difference of two rounded offsets.
+//   no crossing: one segment, W = o + dxi/2, D = dxi
+//   crossing:    relay xr = 1 (dc = +1), 0 (dc = -1), mid-point (dc = 0);
+//                segment A in the particle's cell, B in the cell + dc
+__device__ __forceinline__ void zigzag_split(const float o[3], const float dxi[3],
+                                             const float e[3], const int dc[3], float WA[3],
+                                             float DA[3], float WB[3], float DB[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (dc[a] == 0) {
+            DA[a] = DB[a] = 0.5f * dxi[a];
+            WA[a] = fmaf(0.25f, dxi[a], o[a]);
+            WB[a] = fmaf(0.75f, dxi[a], o[a]);
+        } else {
+            const float xr = dc[a] > 0 ? 1.f : 0.f;
+            DA[a] = xr - o[a];
+            WA[a] = 0.5f * (o[a] + xr);
+            DB[a] = e[a] - xr;
+            WB[a] = 0.5f * (xr + e[a]) - (float)dc[a];
+        }
+    }
+}
+
+// global atomic deposit of one segment's 12 values at cell (ci,cj,ck)
+__device__ void deposit_global(const GridP &g, float *const J[3], int ci, int cj, int ck,
+                               const float v[12]) {
+    const int cell[3] = {ci, cj, ck};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int b1 = (c + 1) % 3, b2 = (c + 2) % 3;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int p[3] = {cell[0], cell[1], cell[2]};
+            p[b1] += q & 1;
+            p[b2] += q >> 1;
+            const int gx = gaxis(g, 0, p[0]), gy = gaxis(g, 1, p[1]), gz = gaxis(g, 2, p[2]);
+            if (gx < 0 || gy < 0 || gz < 0) continue;
+            const int gc = c == 0 ? gx : (c == 1 ? gy : gz);
+            if (g.bc[c] == EMPIC_BC_ABSORBING && gc >= g.n[c]) continue;  // padding
+            atomicAdd(J[c] + gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz),
+                      v[4 * c + q]);
+        }
+    }
+}
+
+// Per-axis move of a particle: new end point e (relative to its cell), cell
+// step dc in {-1,0,1} and canonical new offset in [0,1).  When e + 1 rounds
+// to 1 the particle is put at offset 0 of its own cell and e is set to 0,
+// so that deposit and stored state agree.
+__device__ __forceinline__ void move_axis(float o, float dxi, float &e, int &dc, float &no) {
+    e = o + dxi;
+    dc = 0;
+    if (e >= 1.f) {
+        dc = 1;
+        no = e - 1.f;
+    } else if (e < 0.f) {
+        const float t = e + 1.f;
+        if (t >= 1.f) {
+            e = 0.f;
+            no = 0.f;
+        } else {
+            dc = -1;
+            no = t;
+        }
+    } else {
+        no = e;
+    }
+}
+
+__device__ __forceinline__ bool new_cell(const GridP &g, int a, int c, int dc, int &out) {
+    int x = c + dc;
+    if (g.bc[a] == EMPIC_BC_PERIODIC) {
+        x = x < 0 ? x + g.n[a] : (x >= g.n[a] ? x - g.n[a] : x);
+    } else if (x < 0 || x >= g.n[a]) {
+        return false;
+    }
+    out = x;
+    return true;
+}
+
+// Whole particle through global memory (drifted out of the LDS window).
+__device__ void particle_global(const FusedArgs &A, const DevSpecies &D, uint32_t &c, float &ox,
+                                             float &oy, float &oz, float &ux, float &uy,
+                                             float &uz, float wq, uint32_t &fbits) {
+    const GridP &g = A.g;
+    const int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
+    float Ep[3], Bp[3];
+    gather_global(g, A.E, A.Bb, ci, cj, ck, ox, oy, oz, Ep, Bp);
+    float gam;
+    const float ig = boris_f32(ux, uy, uz, Ep, Bp, D.r, gam);
+    if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
+    const float o[3] = {ox, oy, oz};
+    const float uu[3] = {ux, uy, uz};
+    float e[3], no[3], dx[3];
+    int dc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        dx[a] = uu[a] * ig * A.dtd[a];
+        if (!(fabsf(dx[a]) < 1.f)) fbits |= EMPIC_FAULT_FAST;
+        move_axis(o[a], dx[a], e[a], dc[a], no[a]);
+    }
+    const float amp[3] = {D.qc[0] * wq, D.qc[1] * wq, D.qc[2] * wq};
+    float v[12];
+    if ((dc[0] | dc[1] | dc[2]) == 0) {
+        const float W[3] = {fmaf(0.5f, dx[0], o[0]), fmaf(0.5f, dx[1], o[1]),
+                            fmaf(0.5f, dx[2], o[2])};
+        segment_weights(W, dx, amp, v);  // one straight segment in this cell
+        deposit_global(g, A.J, ci, cj, ck, v);
+    } else {
+        float WA[3], DA[3], WB[3], DB[3];
+        zigzag_split(o, dx, e, dc, WA, DA, WB, DB);
+        segment_weights(WA, DA, amp, v);
+        deposit_global(g, A.J, ci, cj, ck, v);
+        segment_weights(WB, DB, amp, v);
+        deposit_global(g, A.J, ci + dc[0], cj + dc[1], ck + dc[2], v);
+    }
+    int ni, nj, nk;
+    const int ok = (int)new_cell(g, 0, ci, dc[0], ni) & (int)new_cell(g, 1, cj, dc[1], nj) &
+                   (int)new_cell(g, 2, ck, dc[2], nk);
+    c = ok ? pack_cell(ni, nj, nk) : DEAD;
+    ox = no[0];
+    oy = no[1];
+    oz = no[2];
+}
+
+// ---- LDS versions -----------------------------------------------------------
+__device__ __forceinline__ float tri_lds(const float *F, int i, int j, int k, float fx, float fy,
+                                         float fz) {
+    const float *p = F + i + FWX * (j + FWY * k);
+    const float c00 = lerpf(p[0], p[1], fx);
+    const float c10 = lerpf(p[FWX], p[FWX + 1], fx);
+    const float c01 = lerpf(p[FWX * FWY], p[FWX * FWY + 1], fx);
+    const float c11 = lerpf(p[FWX * FWY + FWX], p[FWX * FWY + FWX + 1], fx);
+    return lerpf(lerpf(c00, c10, fy), lerpf(c01, c11, fy), fz);
+}
+
+// J window offsets of the 12 edges of a cell, in segment_weights order
+__device__ __forceinline__ int edge_off(int q) {
+    // J_x (oy,oz); J_y (oz,ox); J_z (ox,oy)
+    const int c = q >> 2, b = q & 3, o1 = b & 1, o2 = b >> 1;
+    if (c == 0) return JW3 * 0 + o1 * JWX + o2 * JWX * JWY;
+    if (c == 1) return JW3 * 1 + o1 * JWX * JWY + o2;
+    return JW3 * 2 + o1 + o2 * JWX;
+}
+
+__device__ __forceinline__ void lds_add12(float *sJ, int base, const float v[12]) {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) atomicAdd(sJ + base + edge_off(q), v[q]);
+}
+
+__device__ __forceinline__ int local_axis(const GridP &g, int a, int c, int wo) {
+    if (g.bc[a] == EMPIC_BC_PERIODIC) {
+        int m = c - wo - 1;
+        m = m < 0 ? m + g.n[a] : (m >= g.n[a] ? m - g.n[a] : m);
+        return m + 1;
+    }
+    return c - wo;
+}
+
+__global__ __launch_bounds__(PUSH_THREADS) void k_push_fused(FusedArgs A) {
+    __shared__ float sF[6 * FW3];
+    __shared__ float sJ[3 * JW3];
+    __shared__ int sG[3][JWX > JWY ? (JWX > JWZ ? JWX : JWZ) : (JWY > JWZ ? JWY : JWZ)];
+    __shared__ int sPad[3][JWX > JWY ? (JWX > JWZ ? JWX : JWZ) : (JWY > JWZ ? JWY : JWZ)];
+
+    const GridP &g = A.g;
+    const int nb8 = gridDim.x >> 3;
+    const int tile = (blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);  // XCD-contiguous tiles
+    if (tile >= A.ti.ntiles) return;
+    int total = 0;
+    for (int s = 0; s < A.nsp; ++s)
+        total += A.tbl[s].p[0].tile_off[tile + 1] - A.tbl[s].p[0].tile_off[tile];
+    if (total == 0) return;
+
+    const int tx = tile % A.ti.nt[0];
+    const int tyz = tile / A.ti.nt[0];
+    const int ty = tyz % A.ti.nt[1], tz = tyz / A.ti.nt[1];
+    const int wo[3] = {tx * TX - MARGIN - 1, ty * TY - MARGIN - 1, tz * TZ - MARGIN - 1};
+    const int tid = threadIdx.x;
+
+    // global index tables of the window rows: x index, y*ext0, z*ext0*ext1
+    if (tid < 3 * 16) {
+        const int a = tid / 16, l = tid % 16;
+        const int wl = a == 0 ? JWX : (a == 1 ? JWY : JWZ);
+        if (l < wl) {
+            const int gi = gaxis(g, a, wo[a] + l);
+            const int mul = a == 0 ? 1 : (a == 1 ? g.ext[0] : g.ext[0] * g.ext[1]);
+            sG[a][l] = gi < 0 ? -1 : gi * mul;
+            sPad[a][l] = (gi >= 0 && g.bc[a] == EMPIC_BC_ABSORBING && gi >= g.n[a]) ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 6 * FW3; e += PUSH_THREADS) {
+        const int comp = e / FW3;
+        const int r = e - comp * FW3;
+        const int lz = r / (FWX * FWY);
+        const int r2 = r - lz * (FWX * FWY);
+        const int ly = r2 / FWX, lx = r2 - ly * FWX;
+        const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
+        const float *src = comp < 3 ? A.E[comp] : A.Bb[comp - 3];
+        sF[e] = (gx < 0 || gy < 0 || gz < 0) ? 0.f : src[gx + gy + gz];
+    }
+    for (int e = tid; e < 3 * JW3; e += PUSH_THREADS) sJ[e] = 0.f;
+    __syncthreads();
+
+    uint32_t fbits = 0;
+    unsigned nfb = 0;
+    constexpr int LHI_X = TX + 2 * MARGIN, LHI_Y = TY + 2 * MARGIN, LHI_Z = TZ + 2 * MARGIN;
+
+    for (int s = 0; s < A.nsp; ++s) {
+        const DevSpecies &D = A.tbl[s];
+        const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
+        const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
+        if (beg >= end) continue;
+        const float r = D.r;
+        const float *WP = S.per_particle_w ? (const float *)S.w : nullptr;
+        uint32_t *CP = S.cell;
+        float *OXP = (float *)S.pos[0], *OYP = (float *)S.pos[1], *OZP = (float *)S.pos[2];
+        float *UXP = (float *)S.u[0], *UYP = (float *)S.u[1], *UZP = (float *)S.u[2];
+        const int base0 = beg & ~(PPT - 1);
+        for (int base = base0 + tid * PPT; base < end; base += PUSH_THREADS * PPT) {
+            uint32_t cc[PPT];
+            float ox[PPT], oy[PPT], oz[PPT], vx[PPT], vy[PPT], vz[PPT], wq[PPT];
+            {
+                const vu4 *c4 = (const vu4 *)(CP + base);
+                const vu4 a = __builtin_nontemporal_load(c4), b = __builtin_nontemporal_load(c4 + 1);
+                cc[0] = a.x; cc[1] = a.y; cc[2] = a.z; cc[3] = a.w;
+                cc[4] = b.x; cc[5] = b.y; cc[6] = b.z; cc[7] = b.w;
+            }
+#define EMPIC_LD8(P, DST)                                                              \
+    {                                                                                  \
+        const vf4 *p4 = (const vf4 *)((P) + base);                                     \
+        const vf4 a = __builtin_nontemporal_load(p4), b = __builtin_nontemporal_load(p4 + 1); \
+        DST[0] = a.x; DST[1] = a.y; DST[2] = a.z; DST[3] = a.w;                        \
+        DST[4] = b.x; DST[5] = b.y; DST[6] = b.z; DST[7] = b.w;                        \
+    }
+            EMPIC_LD8(OXP, ox)
+            EMPIC_LD8(OYP, oy)
+            EMPIC_LD8(OZP, oz)
+            EMPIC_LD8(UXP, vx)
+            EMPIC_LD8(UYP, vy)
+            EMPIC_LD8(UZP, vz)
+            if (WP) {
+                EMPIC_LD8(WP, wq)
+            } else {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) wq[k] = 1.f;
+            }
+#undef EMPIC_LD8
+            float acc[12];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) acc[q] = 0.f;
+            int run = -1;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int p = base + k;
+                if (p < beg || p >= end || cc[k] == DEAD) continue;
+                const uint32_t c = cc[k];
+                const int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
+                if (!(ox[k] >= 0.f && ox[k] < 1.f && oy[k] >= 0.f && oy[k] < 1.f && oz[k] >= 0.f &&
+                      oz[k] < 1.f))
+                    fbits |= EMPIC_FAULT_OFFSET;
+                const int lx = local_axis(g, 0, ci, wo[0]);
+                const int ly = local_axis(g, 1, cj, wo[1]);
+                const int lz = local_axis(g, 2, ck, wo[2]);
+                const bool inwin = lx >= 1 && lx <= LHI_X && ly >= 1 && ly <= LHI_Y && lz >= 1 &&
+                                   lz <= LHI_Z;
+                if (!inwin) {
+                    // drifted out of the tile window since the last sort: left unchanged
+                    // here and pushed through global memory by k_push_fallback
+                    ++nfb;
+                    const unsigned slot = atomicAdd(A.fb_count, 1u);
+                    if (slot < (unsigned long long)A.fb_cap) A.fb_list[slot] = make_int2(s, p);
+                    else fbits |= EMPIC_FAULT_CELL;
+                    continue;
+                }
+                // staggered CIC gather from the LDS tile (Sec. 2.5)
+                int hx, hy, hz;
+                float fx, fy, fz;
+                half_axis(ox[k], lx, hx, fx);
+                half_axis(oy[k], ly, hy, fy);
+                half_axis(oz[k], lz, hz, fz);
+                float Ep[3], Bp[3];
+                Ep[0] = tri_lds(sF + 0 * FW3, hx, ly, lz, fx, oy[k], oz[k]);
+                Ep[1] = tri_lds(sF + 1 * FW3, lx, hy, lz, ox[k], fy, oz[k]);
+                Ep[2] = tri_lds(sF + 2 * FW3, lx, ly, hz, ox[k], oy[k], fz);
+                Bp[0] = tri_lds(sF + 3 * FW3, lx, hy, hz, ox[k], fy, fz);
+                Bp[1] = tri_lds(sF + 4 * FW3, hx, ly, hz, fx, oy[k], fz);
+                Bp[2] = tri_lds(sF + 5 * FW3, hx, hy, lz, fx, fy, oz[k]);
+                // Boris push (Sec. 2.4)
+                float gam;
+                const float ig = boris_f32(vx[k], vy[k], vz[k], Ep, Bp, r, gam);
+                if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
+                // move + ZigZag (Sec. 2.5)
+                const float o[3] = {ox[k], oy[k], oz[k]};
+                const float uu[3] = {vx[k], vy[k], vz[k]};
+                float e[3], no[3], dx[3];
+                int dc[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    dx[a] = uu[a] * ig * A.dtd[a];
+                    if (!(fabsf(dx[a]) < 1.f)) fbits |= EMPIC_FAULT_FAST;
+                    move_axis(o[a], dx[a], e[a], dc[a], no[a]);
+                }
+                const float amp[3] = {D.qc[0] * wq[k], D.qc[1] * wq[k], D.qc[2] * wq[k]};
+                const int jb = lx + JWX * (ly + JWY * lz);
+                if (jb != run) {
+                    if (run >= 0) lds_add12(sJ, run, acc);
+#pragma unroll
+                    for (int q = 0; q < 12; ++q) acc[q] = 0.f;
+                    run = jb;
+                }
+                float v[12];
+                if ((dc[0] | dc[1] | dc[2]) == 0) {
+                    // one straight segment in this cell
+                    const float W[3] = {fmaf(0.5f, dx[0], o[0]), fmaf(0.5f, dx[1], o[1]),
+                                        fmaf(0.5f, dx[2], o[2])};
+                    segment_weights(W, dx, amp, v);
+#pragma unroll
+                    for (int q = 0; q < 12; ++q) acc[q] += v[q];
+                } else {
+                    float WA[3], DA[3], WB[3], DB[3];
+                    zigzag_split(o, dx, e, dc, WA, DA, WB, DB);
+                    segment_weights(WA, DA, amp, v);
+#pragma unroll
+                    for (int q = 0; q < 12; ++q) acc[q] += v[q];
+                    segment_weights(WB, DB, amp, v);
+                    lds_add12(sJ, jb + dc[0] + JWX * (dc[1] + JWY * dc[2]), v);
+                }
+                int ni, nj, nk;
+                const int ok = (int)new_cell(g, 0, ci, dc[0], ni) &
+                               (int)new_cell(g, 1, cj, dc[1], nj) &
+                               (int)new_cell(g, 2, ck, dc[2], nk);
+                cc[k] = ok ? pack_cell(ni, nj, nk) : DEAD;
+                ox[k] = no[0];
+                oy[k] = no[1];
+                oz[k] = no[2];
+            }
+            if (run >= 0) lds_add12(sJ, run, acc);
+            if (base >= beg && base + PPT <= end) {
+                vu4 *c4 = (vu4 *)(CP + base);
+                __builtin_nontemporal_store((vu4){cc[0], cc[1], cc[2], cc[3]}, c4);
+                __builtin_nontemporal_store((vu4){cc[4], cc[5], cc[6], cc[7]}, c4 + 1);
+#define EMPIC_ST8(P, SRC)                                                                 \
+    {                                                                                     \
+        vf4 *p4 = (vf4 *)((P) + base);                                                    \
+        __builtin_nontemporal_store((vf4){SRC[0], SRC[1], SRC[2], SRC[3]}, p4);           \
+        __builtin_nontemporal_store((vf4){SRC[4], SRC[5], SRC[6], SRC[7]}, p4 + 1);       \
+    }
+                EMPIC_ST8(OXP, ox)
+                EMPIC_ST8(OYP, oy)
+                EMPIC_ST8(OZP, oz)
+                EMPIC_ST8(UXP, vx)
+                EMPIC_ST8(UYP, vy)
+                EMPIC_ST8(UZP, vz)
+#undef EMPIC_ST8
+            } else {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const int p = base + k;
+                    if (p < beg || p >= end) continue;
+                    CP[p] = cc[k];
+                    OXP[p] = ox[k];
+                    OYP[p] = oy[k];
+                    OZP[p] = oz[k];
+                    UXP[p] = vx[k];
+                    UYP[p] = vy[k];
+                    UZP[p] = vz[k];
+                }
+            }
+        }
+    }
+    if (fbits) atomicOr(A.fault, fbits | (nfb ? EMPIC_FAULT_FALLBACK : 0u));
+    else if (nfb) atomicOr(A.fault, (uint32_t)EMPIC_FAULT_FALLBACK);
+    if (nfb) atomicAdd(A.fallback, (unsigned long long)nfb);
+    __syncthreads();
+    // add the tile's current to global J (non-zero entries only)
+    for (int e = tid; e < 3 * JW3; e += PUSH_THREADS) {
+        const float v = sJ[e];
+        if (v == 0.f) continue;
+        const int comp = e / JW3;
+        const int r = e - comp * JW3;
+        const int lz = r / (JWX * JWY);
+        const int r2 = r - lz * (JWX * JWY);
+        const int ly = r2 / JWX, lx = r2 - ly * JWX;
+        const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
+        if (gx < 0 || gy < 0 || gz < 0) continue;
+        const int lc = comp == 0 ? lx : (comp == 1 ? ly : lz);
+        if (sPad[comp][lc]) continue;
+        atomicAdd(A.J[comp] + gx + gy + gz, v);
+    }
+}
+
+// Out-of-window particles of this step, whole particle through global memory
+// (gather from E and Bbar, global atomic deposit).  The last workgroup to
+// finish resets the list for the next step.
+__global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
+    const unsigned n = *(volatile unsigned *)A.fb_count;
+    const unsigned m = n < (unsigned long long)A.fb_cap ? n : (unsigned)A.fb_cap;
+    uint32_t fbits = 0;
+    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        const int2 e = A.fb_list[t];
+        const DevSpecies &D = A.tbl[e.x];
+        const SpeciesP &S = D.p[(A.cur_mask >> e.x) & 1u];
+        const int p = e.y;
+        uint32_t c = S.cell[p];
+        float ox = ((float *)S.pos[0])[p], oy = ((float *)S.pos[1])[p], oz = ((float *)S.pos[2])[p];
+        float ux = ((float *)S.u[0])[p], uy = ((float *)S.u[1])[p], uz = ((float *)S.u[2])[p];
+        const float wq = (S.per_particle_w && S.w) ? ((const float *)S.w)[p] : 1.f;
+        particle_global(A, D, c, ox, oy, oz, ux, uy, uz, wq, fbits);
+        S.cell[p] = c;
+        ((float *)S.pos[0])[p] = ox;
+        ((float *)S.pos[1])[p] = oy;
+        ((float *)S.pos[2])[p] = oz;
+        ((float *)S.u[0])[p] = ux;
+        ((float *)S.u[1])[p] = uy;
+        ((float *)S.u[2])[p] = uz;
+    }
+    if (fbits) atomicOr(A.fault, fbits);
+    // reset the list once every workgroup has read the count
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned ticket = atomicAdd(A.fb_count + 1, 1u);
+        if (ticket == gridDim.x - 1) {
+            atomicExch(A.fb_count, 0u);
+            atomicExch(A.fb_count + 1, 0u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics and conversions (one thread per particle slot)
+// ---------------------------------------------------------------------------
+__global__ void k_dry_push_f32(GridP g, const float *Ex, const float *Ey, const float *Ez,
+                               const float *Bx, const float *By, const float *Bz, SpeciesP sp,
+                               float r, double *partial, uint32_t *fault) {
+    __shared__ double sm[16];
+    const float *E[3] = {Ex, Ey, Ez};
+    const float *Bb[3] = {Bx, By, Bz};
+    const long long count = *sp.count;
+    const float *WP = (sp.per_particle_w && sp.w) ? (const float *)sp.w : nullptr;
+    double ks = 0.0;
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < count;
+         p += (long long)gridDim.x * blockDim.x) {
+        const uint32_t c = sp.cell[p];
+        if (c == DEAD) continue;
+        const float ox = ((const float *)sp.pos[0])[p], oy = ((const float *)sp.pos[1])[p],
+                    oz = ((const float *)sp.pos[2])[p];
+        float ux = ((const float *)sp.u[0])[p], uy = ((const float *)sp.u[1])[p],
+              uz = ((const float *)sp.u[2])[p];
+        float Ep[3], Bp[3];
+        gather_global(g, E, Bb, cell_i(c), cell_j(c), cell_k(c), ox, oy, oz, Ep, Bp);
+        float gam;
+        boris_f32(ux, uy, uz, Ep, Bp, r, gam);
+        if (!isfinite(gam)) atomicOr(fault, (uint32_t)EMPIC_FAULT_NONFINITE);
+        const double uu = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+        const double wp = WP ? (double)WP[p] : sp.w_species;
+        ks += wp * sp.m * uu / (sqrt(1.0 + uu) + 1.0);
+    }
+    const double t = block_reduce<false>(ks, sm);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void k_kinetic_f32(SpeciesP sp, double *partial) {
+    __shared__ double sm[16];
+    const long long count = *sp.count;
+    const float *WP = (sp.per_particle_w && sp.w) ? (const float *)sp.w : nullptr;
+    double ks = 0.0;
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < count;
+         p += (long long)gridDim.x * blockDim.x) {
+        if (sp.cell[p] == DEAD) continue;
+        const double ux = ((const float *)sp.u[0])[p], uy = ((const float *)sp.u[1])[p],
+                     uz = ((const float *)sp.u[2])[p];
+        const double uu = ux * ux + uy * uy + uz * uz;
+        const double wp = WP ? (double)WP[p] : sp.w_species;
+        ks += wp * sp.m * uu / (sqrt(1.0 + uu) + 1.0);
+    }
+    const double t = block_reduce<false>(ks, sm);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ void k_rho_f32(GridP g, SpeciesP sp, double *rho) {
+    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (p >= *sp.count) return;
+    const uint32_t c = sp.cell[p];
+    if (c == DEAD) return;
+    const float *WP = (sp.per_particle_w && sp.w) ? (const float *)sp.w : nullptr;
+    const double dV = g.d[0] * g.d[1] * g.d[2];
+    const double qsp = sp.q * (WP ? (double)WP[p] : sp.w_species);
+    const int ci[3] = {cell_i(c), cell_j(c), cell_k(c)};
+    const double f[3] = {((const float *)sp.pos[0])[p], ((const float *)sp.pos[1])[p],
+                         ((const float *)sp.pos[2])[p]};
+    for (int o = 0; o < 8; ++o) {
+        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+        const int gx = gaxis(g, 0, ci[0] + ox), gy = gaxis(g, 1, ci[1] + oy),
+                  gz = gaxis(g, 2, ci[2] + oz);
+        if (gx < 0 || gy < 0 || gz < 0) continue;
+        const double wt = (ox ? f[0] : 1.0 - f[0]) * (oy ? f[1] : 1.0 - f[1]) *
+                          (oz ? f[2] : 1.0 - f[2]);
+        atomicAdd(rho + gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz), qsp / dV * wt);
+    }
+}
+
+// FP64 global positions -> packed cell + FP32 offset (on the device)
+__global__ void k_load_f32(GridP g, SpeciesP sp, long long count, const double *pos,
+                           const double *u, const double *w, const int32_t *ids, uint32_t *fault) {
+    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (p == 0) *sp.count = (int32_t)count;
+    if (p >= count) return;
+    int ci[3];
+    float off[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        const double xi = pos[3 * p + a] / g.d[a];
+        const double fl = floor(xi);
+        int i = (int)fl;
+        float o = (float)(xi - fl);
+        if (o >= 1.f) {
+            o = 0.f;
+            i += 1;
+            if (g.bc[a] == EMPIC_BC_PERIODIC && i == g.n[a]) i = 0;
+        }
+        if (!(xi >= 0.0) || i < 0 || i >= g.n[a]) ok = false;
+        ci[a] = i;
+        off[a] = o;
+    }
+    if (!ok) atomicOr(fault, (uint32_t)EMPIC_FAULT_CELL);
+    sp.cell[p] = ok ? pack_cell(ci[0], ci[1], ci[2]) : DEAD;
+    for (int a = 0; a < 3; ++a) {
+        ((float *)sp.pos[a])[p] = off[a];
+        ((float *)sp.u[a])[p] = (float)u[3 * p + a];
+    }
+    sp.id[p] = ids ? ids[p] : (int32_t)p;
+    if (sp.w && w) ((float *)sp.w)[p] = (float)w[p];
+}
+
+__global__ void k_store_f32(GridP g, SpeciesP sp, double *pos, double *u, int32_t *ids) {
+    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (p >= *sp.count) return;
+    const uint32_t c = sp.cell[p];
+    const int ci[3] = {cell_i(c), cell_j(c), cell_k(c)};
+    for (int a = 0; a < 3; ++a) {
+        pos[3 * p + a] = c == DEAD ? __builtin_nan("")
+                                   : ((double)ci[a] + (double)((const float *)sp.pos[a])[p]) * g.d[a];
+        u[3 * p + a] = (double)((const float *)sp.u[a])[p];
+    }
+    if (ids) ids[p] = c == DEAD ? -1 : sp.id[p];
+}
+
+// ---------------------------------------------------------------------------
+// Counting sort by (tile, cell): rank within key from the histogram atomics,
+// exclusive scan of the key counts, scatter into the other buffer set.
+// ---------------------------------------------------------------------------
+__global__ void k_sort_count(TileInfo ti, GridP g, SpeciesP sp, int32_t *counts, int32_t *rank,
+                             uint32_t *fault) {
+    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (p >= *sp.count) return;
+    const uint32_t c = sp.cell[p];
+    if (c == DEAD) {
+        rank[p] = -1;
+        return;
+    }
+    const int i = cell_i(c), j = cell_j(c), k = cell_k(c);
+    if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) {
+        atomicOr(fault, (uint32_t)EMPIC_FAULT_CELL);
+        rank[p] = -1;
+        return;
+    }
+    rank[p] = atomicAdd(counts + sort_key(ti, i, j, k), 1);
+}
+
+constexpr int SCAN_T = 256, SCAN_PER = 4, SCAN_B = SCAN_T * SCAN_PER;
+
+__device__ inline int block_exclusive_scan(int v, int *sm, int &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sm[wid] = x;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        if (w < wid) off += sm[w];
+        total += sm[w];
+    }
+    __syncthreads();
+    return off + x - v;
+}
+
+__global__ void k_scan_reduce(const int32_t *counts, long long NK, int32_t *bsum) {
+    __shared__ int sm[16];
+    const long long base = (long long)blockIdx.x * SCAN_B;
+    int s = 0;
+    for (int q = 0; q < SCAN_PER; ++q) {
+        const long long i = base + threadIdx.x * SCAN_PER + q;
+        if (i < NK) s += counts[i];
+    }
+    int total;
+    block_exclusive_scan(s, sm, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void k_scan_blocks(int32_t *bsum, int nb, int32_t *counts, long long NK) {
+    __shared__ int sm[16];
+    int carry = 0;
+    for (int base = 0; base < nb; base += SCAN_T) {
+        const int i = base + threadIdx.x;
+        const int v = i < nb ? bsum[i] : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, sm, total);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) counts[NK] = carry;  // total number of live particles
+}
+
+__global__ void k_scan_down(int32_t *counts, long long NK, const int32_t *bsum) {
+    __shared__ int sm[16];
+    const long long base = (long long)blockIdx.x * SCAN_B + threadIdx.x * SCAN_PER;
+    int v[SCAN_PER], s = 0;
+    for (int q = 0; q < SCAN_PER; ++q) {
+        v[q] = base + q < NK ? counts[base + q] : 0;
+        s += v[q];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, sm, total) + bsum[blockIdx.x];
+    for (int q = 0; q < SCAN_PER; ++q) {
+        if (base + q < NK) counts[base + q] = ex;
+        ex += v[q];
+    }
+}
+
+__global__ void k_sort_scatter(TileInfo ti, SpeciesP cur, SpeciesP alt, const int32_t *offs,
+                               const int32_t *rank) {
+    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (p >= *cur.count) return;
+    const int rk = rank[p];
+    if (rk < 0) return;
+    const uint32_t c = cur.cell[p];
+    const long long dst = offs[sort_key(ti, cell_i(c), cell_j(c), cell_k(c))] + rk;
+    alt.cell[dst] = c;
+    for (int a = 0; a < 3; ++a) {
+        ((float *)alt.pos[a])[dst] = ((const float *)cur.pos[a])[p];
+        ((float *)alt.u[a])[dst] = ((const float *)cur.u[a])[p];
+    }
+    alt.id[dst] = cur.id[p];
+    if (cur.w && alt.w) ((float *)alt.w)[dst] = ((const float *)cur.w)[p];
+}
+
+__global__ void k_tile_offsets(const int32_t *offs, long long NK, int ntiles, int32_t *tile_off,
+                               int32_t *count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    tile_off[t] = t == ntiles ? offs[NK] : offs[(long long)t * TC];
+    if (t == ntiles) *count = offs[NK];
+}
+
+__global__ void k_fill_i32(int32_t *p, long long n, int32_t v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+__global__ void k_write_species(DevSpecies *dst, DevSpecies v) { *dst = v; }
+
+}  // namespace
+
+void launch_fill_i32(int32_t *p, long long n, int32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, s, p, n, v);
+}
+
+void launch_write_species(DevSpecies *dst, const DevSpecies &v, hipStream_t s) {
+    hipLaunchKernelGGL(k_write_species, dim3(1), dim3(1), 0, s, dst, v);
+}
+
+void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
+                       float *const Bbar[3], float *const J[3], const DevSpecies *tbl, int nsp,
+                       unsigned cur_mask, uint32_t *fault, unsigned long long *fallback,
+                       int2 *fb_list, unsigned *fb_count, long long fb_cap, hipStream_t s) {
+    FusedArgs A;
+    A.g = g;
+    A.ti = ti;
+    for (int a = 0; a < 3; ++a) {
+        A.E[a] = E[a];
+        A.Bb[a] = Bbar[a];
+        A.J[a] = J[a];
+        A.dtd[a] = (float)(g.dt / g.d[a]);
+    }
+    A.tbl = tbl;
+    A.nsp = nsp;
+    A.cur_mask = cur_mask;
+    A.fault = fault;
+    A.fallback = fallback;
+    A.fb_list = fb_list;
+    A.fb_count = fb_count;
+    A.fb_cap = fb_cap;
+    const int nb = 8 * ((ti.ntiles + 7) / 8);
+    hipLaunchKernelGGL(k_push_fused, dim3(nb), dim3(PUSH_THREADS), 0, s, A);
+    hipLaunchKernelGGL(k_push_fallback, dim3(64), dim3(256), 0, s, A);
+}
+
+void launch_dry_push_f32(const GridP &g, float *const E[3], float *const Bbar[3],
+                         const SpeciesP &sp, double *partial_slot, uint32_t *fault,
+                         hipStream_t s) {
+    const float r = (float)(sp.q * g.dt / (2.0 * sp.m));
+    hipLaunchKernelGGL(k_dry_push_f32, dim3(RED_BLOCKS), dim3(256), 0, s, g, E[0], E[1], E[2],
+                       Bbar[0], Bbar[1], Bbar[2], sp, r, partial_slot, fault);
+}
+
+void launch_kinetic_f32(const SpeciesP &sp, double *partial_slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_kinetic_f32, dim3(RED_BLOCKS), dim3(256), 0, s, sp, partial_slot);
+}
+
+void launch_rho_f32(const GridP &g, const SpeciesP &sp, double *rho, hipStream_t s) {
+    if (sp.capacity <= 0) return;
+    hipLaunchKernelGGL(k_rho_f32, dim3(nblk(sp.capacity, 256)), dim3(256), 0, s, g, sp, rho);
+}
+
+void launch_load_f32(const GridP &g, const SpeciesP &sp, long long count, const double *pos,
+                     const double *u, const double *w, const int32_t *ids, uint32_t *fault,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_load_f32, dim3(nblk(count > 0 ? count : 1, 256)), dim3(256), 0, s, g, sp,
+                       count, pos, u, w, ids, fault);
+}
+
+void launch_store_f32(const GridP &g, const SpeciesP &sp, double *pos, double *u, int32_t *ids,
+                      hipStream_t s) {
+    if (sp.capacity <= 0) return;
+    hipLaunchKernelGGL(k_store_f32, dim3(nblk(sp.capacity, 256)), dim3(256), 0, s, g, sp, pos, u,
+                       ids);
+}
+
+void launch_sort(const GridP &g, const TileInfo &ti, const SpeciesP &cur, const SpeciesP &alt,
+                 int32_t *counts, int32_t *scan_blocks, int32_t *rank, int32_t *tile_off,
+                 uint32_t *fault, hipStream_t s) {
+    const long long NK = ti.NK;
+    launch_fill_i32(counts, NK + 1, 0, s);
+    if (cur.capacity > 0)
+        hipLaunchKernelGGL(k_sort_count, dim3(nblk(cur.capacity, 256)), dim3(256), 0, s, ti, g,
+                           cur, counts, rank, fault);
+    const int nb = (int)((NK + SCAN_B - 1) / SCAN_B);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_T), 0, s, counts, NK, scan_blocks);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_T), 0, s, scan_blocks, nb, counts, NK);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(SCAN_T), 0, s, counts, NK, scan_blocks);
+    if (cur.capacity > 0)
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nblk(cur.capacity, 256)), dim3(256), 0, s, ti,
+                           cur, alt, counts, rank);
+    hipLaunchKernelGGL(k_tile_offsets, dim3(nblk(ti.ntiles + 1, 256)), dim3(256), 0, s, counts,
+                       NK, ti.ntiles, tile_off, cur.count);
+}
+
+}  // namespace empic

@@ -1,0 +1,221 @@
+"""Python face of libempic: a simulation whose device memory is torch tensors.
+
+Every step of the PIC cycle runs in the library's HIP kernels; this class
+only allocates tensors, passes their pointers and torch's current HIP stream
+through the C ABI, and converts results to numpy for inspection.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as LB
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _round_up(x, m):
+    return (int(x) + m - 1) // m * m
+
+
+class Sim:
+    """One EM-PIC simulation on one GPU.
+
+    precision: "fp32" (cell-relative FP32, sorted, fused kernel) or "fp64"
+    (plain FP64 global positions).  `workload` is a
+    paper_2609_16575_amd.workloads.Workload.
+    """
+
+    def __init__(self, workload, precision: str = "fp32", device: Optional[str] = None,
+                 sort_every: Optional[int] = None, capacity_slack: float = 0.0):
+        import torch
+        self.torch = torch
+        self.L = LB.lib()
+        self.dev = torch.device(device or "cuda")
+        if self.dev.type != "cuda":
+            raise ValueError("libempic runs on a GPU device")
+        self.w = workload
+        self.fp64 = precision == "fp64"
+        if precision not in ("fp32", "fp64"):
+            raise ValueError(precision)
+        self.dtype = torch.float64 if self.fp64 else torch.float32
+        n, bc = workload.n, workload.bc
+        self.ext = tuple(n[a] + (1 if bc[a] == LB.BC_ABSORBING else 0) for a in range(3))
+        shape = (3, self.ext[2], self.ext[1], self.ext[0])
+        self.E = torch.zeros(shape, dtype=self.dtype, device=self.dev)
+        self.B = torch.zeros(shape, dtype=self.dtype, device=self.dev)
+        self.J = torch.zeros(shape, dtype=self.dtype, device=self.dev)
+        if workload.E0 is not None:
+            self.E.copy_(torch.from_numpy(np.asarray(workload.E0)).to(self.dev, self.dtype))
+        if workload.B0 is not None:
+            self.B.copy_(torch.from_numpy(np.asarray(workload.B0)).to(self.dev, self.dtype))
+
+        nsp = len(workload.species)
+        self.caps = [_round_up(max(8, int(s.pos.shape[0] * (1.0 + capacity_slack))), 64)
+                     for s in workload.species]
+        max_cap = max(self.caps) if self.caps else 64
+        d = LB.GridDesc()
+        for a in range(3):
+            d.n[a], d.bc[a], d.d[a] = int(n[a]), int(bc[a]), float(workload.d[a])
+        d.dt = float(workload.dt)
+        d.precision = LB.FP64_PLAIN if self.fp64 else LB.FP32_CELLREL
+        d.sort_every = int(workload.sort_every if sort_every is None else sort_every)
+        self.desc = d
+        wsb = self.L.empic_workspace_bytes(C.byref(d), max(nsp, 1), max_cap)
+        if wsb == 0:
+            raise LB.EmpicError(1, "bad grid for the workspace size")
+        self.ws = torch.empty(int(wsb), dtype=torch.uint8, device=self.dev)
+        self.stream = torch.cuda.current_stream(self.dev)
+        h = C.c_void_p()
+        st = self.L.empic_create(C.byref(d), max(nsp, 1), max_cap, C.c_void_p(self.stream.cuda_stream),
+                                 C.c_void_p(_ptr(self.ws)), int(wsb), C.byref(h))
+        if st != 0:
+            raise LB.EmpicError(st, "empic_create failed")
+        self.h = h
+        arr = C.c_void_p * 3
+        LB.check(h, self.L.empic_bind_fields(h, arr(*[_ptr(self.E[a]) for a in range(3)]),
+                                             arr(*[_ptr(self.B[a]) for a in range(3)]),
+                                             arr(*[_ptr(self.J[a]) for a in range(3)])))
+        self.bufs = []
+        for i, s in enumerate(workload.species):
+            self._add_species(s, self.caps[i])
+        LB.check(h, self.L.empic_set_background(h, float(workload.rho_bg)))
+        if workload.laser is not None:
+            Ls = workload.laser
+            ld = LB.LaserDesc(Ls.a0, Ls.w0, Ls.tau, Ls.t0, Ls.omega0, Ls.yc, Ls.zc, int(Ls.i_s), 1)
+            LB.check(h, self.L.empic_set_laser(h, C.byref(ld)))
+        torch.cuda.synchronize(self.dev)
+
+    # -- set-up -----------------------------------------------------------------
+    def _alloc_set(self, cap, wpp):
+        t = self.torch
+        fd = self.dtype
+        cell = t.zeros(cap, dtype=t.int32, device=self.dev)
+        pos = t.zeros((3, cap), dtype=fd, device=self.dev)
+        u = t.zeros((3, cap), dtype=fd, device=self.dev)
+        ids = t.zeros(cap, dtype=t.int32, device=self.dev)
+        w = t.zeros(cap, dtype=fd, device=self.dev) if wpp else None
+        pb = LB.ParticleBuffers()
+        pb.cell = _ptr(cell)
+        for a in range(3):
+            pb.pos[a] = _ptr(pos[a])
+            pb.u[a] = _ptr(u[a])
+        pb.id = _ptr(ids)
+        pb.w = _ptr(w) if w is not None else None
+        return {"cell": cell, "pos": pos, "u": u, "id": ids, "w": w, "pb": pb}
+
+    def _add_species(self, s, cap):
+        t = self.torch
+        wpp = s.wpp is not None
+        b0 = self._alloc_set(cap, wpp)
+        b1 = None if self.fp64 else self._alloc_set(cap, wpp)
+        sd = LB.SpeciesDesc(float(s.q), float(s.m), float(s.w), 1 if wpp else 0, 0)
+        sid = C.c_int32()
+        LB.check(self.h, self.L.empic_add_species(self.h, C.byref(sd), cap, C.byref(b0["pb"]),
+                                                  C.byref(b1["pb"]) if b1 else None, C.byref(sid)))
+        self.bufs.append((b0, b1))
+        self.load_particles(sid.value, s.pos, s.u, s.wpp)
+
+    def load_particles(self, sp, pos, u, wpp=None, ids=None):
+        t = self.torch
+        pos_d = t.from_numpy(np.ascontiguousarray(pos, dtype=np.float64)).to(self.dev)
+        u_d = t.from_numpy(np.ascontiguousarray(u, dtype=np.float64)).to(self.dev)
+        w_d = None if wpp is None else t.from_numpy(np.ascontiguousarray(wpp, dtype=np.float64)).to(self.dev)
+        id_d = None if ids is None else t.from_numpy(np.ascontiguousarray(ids, dtype=np.int32)).to(self.dev)
+        LB.check(self.h, self.L.empic_load_particles_f64(
+            self.h, sp, int(pos_d.shape[0]), _ptr(pos_d), _ptr(u_d),
+            _ptr(w_d) if w_d is not None else None, _ptr(id_d) if id_d is not None else None))
+        self.torch.cuda.synchronize(self.dev)
+
+    def set_fields(self, E=None, B=None):
+        t = self.torch
+        if E is not None:
+            self.E.copy_(t.from_numpy(np.asarray(E, dtype=np.float64)).to(self.dev, self.dtype))
+        if B is not None:
+            self.B.copy_(t.from_numpy(np.asarray(B, dtype=np.float64)).to(self.dev, self.dtype))
+        t.cuda.synchronize(self.dev)
+
+    # -- the PIC cycle ------------------------------------------------------------
+    def step(self, nsteps: int = 1):
+        LB.check(self.h, self.L.empic_step(self.h, int(nsteps)))
+
+    def sort(self):
+        LB.check(self.h, self.L.empic_sort(self.h))
+
+    def sync(self):
+        LB.check(self.h, self.L.empic_sync(self.h))
+
+    # -- results -------------------------------------------------------------------
+    def diagnostics(self) -> dict:
+        dg = LB.Diag()
+        LB.check(self.h, self.L.empic_diagnostics(self.h, C.byref(dg)))
+        nsp = len(self.w.species)
+        return {"step": dg.step, "t": dg.t, "U_E": dg.U_E, "U_B": dg.U_B, "U_tot": dg.U_tot,
+                "K": list(dg.K)[:nsp], "K_minus": list(dg.K_minus)[:nsp],
+                "K_plus": list(dg.K_plus)[:nsp], "gauss_max": dg.gauss_max,
+                "gauss_l2": dg.gauss_l2, "cont_max": dg.cont_max, "rho_max": dg.rho_max,
+                "cont_valid": bool(dg.cont_valid), "fault_word": dg.fault_word,
+                "n_particles": list(dg.n_particles)[:nsp],
+                "fallback_particles": dg.fallback_particles}
+
+    def particles(self, sp: int):
+        """(positions (N,3) f64, momenta (N,3) f64, ids (N,)) of live particles, storage order."""
+        t = self.torch
+        cap = self.caps[sp]
+        pos = t.empty((cap, 3), dtype=t.float64, device=self.dev)
+        u = t.empty((cap, 3), dtype=t.float64, device=self.dev)
+        ids = t.empty(cap, dtype=t.int32, device=self.dev)
+        cnt = C.c_int64()
+        LB.check(self.h, self.L.empic_store_particles_f64(self.h, sp, _ptr(pos), _ptr(u), _ptr(ids),
+                                                          C.byref(cnt)))
+        n = cnt.value
+        P, U, I = pos[:n].cpu().numpy(), u[:n].cpu().numpy(), ids[:n].cpu().numpy()
+        keep = I >= 0
+        return P[keep], U[keep], I[keep]
+
+    def particles_by_id(self, sp: int):
+        P, U, I = self.particles(sp)
+        order = np.argsort(I, kind="stable")
+        return P[order], U[order], I[order]
+
+    def fields(self):
+        self.torch.cuda.synchronize(self.dev)
+        f = lambda x: x.double().cpu().numpy()
+        return f(self.E), f(self.B), f(self.J)
+
+    def rho(self, sp: int = -1):
+        t = self.torch
+        out = t.empty(tuple(reversed(self.ext)), dtype=t.float64, device=self.dev)
+        LB.check(self.h, self.L.empic_deposit_rho(self.h, int(sp), _ptr(out)))
+        t.cuda.synchronize(self.dev)
+        return out.cpu().numpy()
+
+    def count(self, sp: int) -> int:
+        n = C.c_int64()
+        LB.check(self.h, self.L.empic_particle_count(self.h, sp, C.byref(n)))
+        return n.value
+
+    def enable_timing(self, on=True):
+        LB.check(self.h, self.L.empic_enable_timing(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        v = [C.c_double(), C.c_int64(), C.c_double(), C.c_int64(), C.c_double(), C.c_int64()]
+        LB.check(self.h, self.L.empic_kernel_times(self.h, *[C.byref(x) for x in v]))
+        return {"push_ms": v[0].value, "push_n": v[1].value, "field_ms": v[2].value,
+                "field_n": v[3].value, "sort_ms": v[4].value, "sort_n": v[5].value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.torch.cuda.synchronize(self.dev)
+            self.L.empic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,53 @@
+"""Shared helpers of the GPU parity tests (not collected by pytest)."""
+import numpy as np
+
+from oracle import oracle as O
+
+
+def oracle_from(w, E0=None, B0=None):
+    sim = O.OracleSim(w.n, w.d, w.dt, w.bc)
+    if E0 is not None:
+        sim.E[...] = E0
+    if B0 is not None:
+        sim.B[...] = B0
+    for s in w.species:
+        sim.add_species(s.q, s.m, s.w, s.pos, s.u, s.wpp)
+    sim.rho_bg = w.rho_bg
+    if w.laser is not None:
+        L = w.laser
+        sim.set_laser(L.a0, L.w0, L.tau, L.t0, L.omega0, L.yc, L.zc, L.i_s)
+    return sim
+
+
+def rel(a, b):
+    """||a - b||_inf / ||b||_inf."""
+    den = float(np.max(np.abs(b)))
+    return float(np.max(np.abs(a - b))) / (den if den > 0 else 1.0)
+
+
+def pos_err_cells(P, Pref, w):
+    """Largest position difference in cells, minimal image on periodic axes."""
+    d = np.asarray(w.d)
+    L = np.asarray(w.n, dtype=float) * d
+    dx = P - Pref
+    for a in range(3):
+        if w.bc[a] == 0:
+            dx[:, a] -= L[a] * np.round(dx[:, a] / L[a])
+    return float(np.max(np.abs(dx) / d)) if len(dx) else 0.0
+
+
+def compare_state(gpu, orc, w, sp_tol, f_tol, label=""):
+    """Compare fields and every species by id; returns the error dict."""
+    E, B, J = gpu.fields()
+    errs = {"E": rel(E, orc.E), "B": rel(B, orc.B), "J": rel(J, orc.J)}
+    for i, s in enumerate(orc.species):
+        P, U, I = gpu.particles_by_id(i)
+        alive = np.ones(s.np, bool) if s.alive is None else s.alive.astype(bool)
+        ref_ids = np.nonzero(alive)[0]
+        assert np.array_equal(I, ref_ids), (label, i, len(I), len(ref_ids))
+        errs["x%d" % i] = pos_err_cells(P, s.pos[ref_ids], w)
+        errs["u%d" % i] = rel(U, s.u[ref_ids])
+    for k, v in errs.items():
+        tol = f_tol if k in ("E", "B", "J") else sp_tol
+        assert v <= tol, (label, k, v, tol, errs)
+    return errs
