@@ -1,0 +1,182 @@
+"""Benchmark of the EM-PIC step on one MI355X.
+
+Workload (the benchmark configuration): periodic 128^3 grid, dx = 1 (c/omega_p),
+dt at Courant 0.5, 8 electrons + 8 protons per cell (33.55M particles),
+thermal v_th = 0.05c, equal temperatures, sort every 10 steps.  One step is
+the whole PIC cycle: Faraday + centring of B, gather + Boris + move + ZigZag
+for both species, Ampere-Maxwell (and the periodic counting sort every 10th
+step).  Inputs are generated once (seeded) and resident in HBM before timing.
+
+Prints one JSON line.  value = FP32 cell-relative particle-pushes/s; the plain
+FP64 step on the same workload is reported beside it.  The dominant kernel is
+the fused FP32 particle kernel; its roofline entry uses the algorithmic bytes
+56 per particle (28 read + 28 written) + 36 per cell (E and centred B read,
+J written) per launch over its HIP-event-timed average duration.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-pushes/s (gather+push+deposit+Yee) FP32 vs FP64; adjoint step ms"
+COUNTERS = os.path.join(ROOT, "profiles", "push_fused_thermal_ep_128_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2609_16575_amd", "csrc", "push_f32.hip")
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def time_steps(sim, steps, warmup, torch):
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.kernel_times()  # discard warm-up timing
+    sim.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = sim.kernel_times()
+    sim.enable_timing(False)
+    sim.sync()
+    return (t1 - t0), kt
+
+
+def traffic_from_counters(nbytes_alg):
+    """HBM bytes per launch of the fused kernel from committed rocprofv3 PMC
+    summaries, or None when they are missing or older than the kernel."""
+    if not os.path.exists(COUNTERS):
+        return None
+    c = json.load(open(COUNTERS))
+    if c.get("kernel_source_sha") != kernel_sha():
+        return None
+    return (c["fetch_kib_per_dispatch"] * c["copy_scale_fetch"] +
+            c["write_kib_per_dispatch"] * c["copy_scale_write"]) * 1024.0
+
+
+def cpu_baseline(n=(64, 64, 64), steps=2):
+    """The FP64 oracle (single thread) on a 64^3 box of the same workload."""
+    from oracle import oracle as O
+    from paper_2609_16575_amd import workloads as W
+    w = W.thermal_two_species(n=n)
+    o = O.OracleSim(w.n, w.d, w.dt)
+    for s in w.species:
+        o.add_species(s.q, s.m, s.w, s.pos, s.u)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": w.n_particles * steps / dt, "unit": "particle-pushes/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d steps of the same workload on a %dx%dx%d box (%d particles), "
+                      "single-threaded FP64 C, %.1f s" % (steps, *n, w.n_particles, dt)}
+
+
+def copy_calibration(torch, nbytes=1 << 30):
+    """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the step would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_16575_amd import workloads as W
+    from paper_2609_16575_amd.sim import Sim
+
+    if args.calibrate_copy:
+        copy_calibration(torch)
+    n = (args.n,) * 3
+    t0 = time.perf_counter()
+    w = W.thermal_two_species(n=n)
+    _log("generated %d particles in %.1f s" % (w.n_particles, time.perf_counter() - t0))
+    npart, ncell = w.n_particles, w.n_cells
+    out = {"metric": METRIC, "value": None, "unit": "particle-pushes/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "thermal e+p plasma, periodic %dx%dx%d, dx=1, Courant 0.5, "
+                                  "8 e- + 8 p+ per cell (%d particles), v_th=0.05c, sort every 10"
+                                  % (*n, npart),
+                      "particles": npart, "cells": ncell, "sort_every": 10}}
+
+    if args.only != "fp64":
+        sim = Sim(w, precision="fp32")
+        _log("fp32 sim ready")
+        wall, kt = time_steps(sim, args.steps, args.warmup, torch)
+        d = sim.diagnostics()
+        ms = 1e3 * wall / args.steps
+        out["value"] = npart * args.steps / wall
+        out["ms_per_step"] = ms
+        out["cell_updates_per_s"] = ncell * args.steps / wall
+        push_ms = kt["push_ms"] / max(kt["push_n"], 1)
+        nbytes = 56.0 * npart + 36.0 * ncell
+        achieved = nbytes / (push_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": traffic_from_counters(nbytes),
+                           "kernel": "k_push_fused", "avg_ms": push_ms,
+                           "algorithmic_bytes_per_launch": nbytes}
+        out["breakdown_ms_per_step"] = {
+            "push_fused": kt["push_ms"] / args.steps, "fields": kt["field_ms"] / args.steps,
+            "sort": kt["sort_ms"] / args.steps}
+        out["fp32_checks"] = {"fault_word": d["fault_word"],
+                              "fallback_particles": d["fallback_particles"],
+                              "U_tot": d["U_tot"]}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+
+    if not args.no_fp64 and args.only != "fp32":
+        sim = Sim(w, precision="fp64")
+        _log("fp64 sim ready")
+        wall, kt = time_steps(sim, args.steps, args.warmup, torch)
+        out["fp64_plain"] = {"value": npart * args.steps / wall, "unit": "particle-pushes/s",
+                             "ms_per_step": 1e3 * wall / args.steps,
+                             "push_ms_per_step": kt["push_ms"] / args.steps,
+                             "field_ms_per_step": kt["field_ms"] / args.steps}
+        if out["value"]:
+            out["speedup_fp32_vs_fp64"] = out["value"] / out["fp64_plain"]["value"]
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+
+    out["adjoint"] = None
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -230,6 +230,11 @@ empic_status empic_kernel_times(empic_sim *s, double *push_ms, int64_t *push_lau
                                 double *field_ms, int64_t *field_launches,
                                 double *sort_ms, int64_t *sort_launches);
 
+/* Cells per tile of the FP32 path's sort order and fused kernel (x, y, z):
+ * particles are stored tile by tile (tiles x-fastest), cell by cell inside a
+ * tile (x-fastest).  Host-only; needs no handle. */
+void empic_tile_shape(int32_t out[3]);
+
 /* Per-handle message for the last failed call; valid until the next call. */
 const char *empic_last_error(const empic_sim *s);
 

@@ -81,6 +81,7 @@ SIGNATURES = {
     "empic_kernel_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "empic_tile_shape": (None, [C.POINTER(C.c_int32)]),
     "empic_last_error": (C.c_char_p, [_P]),
     "empic_destroy": (None, [_P]),
 }
@@ -102,6 +103,12 @@ def lib():
         f.argtypes = args
     _lib = L
     return L
+
+
+def tile_shape():
+    out = (C.c_int32 * 3)()
+    lib().empic_tile_shape(out)
+    return tuple(out)
 
 
 def check(handle, status):

@@ -91,6 +91,14 @@ __global__ void k_final_reduce(const double *partials, double *result) {
     if (threadIdx.x == 0) result[q] = r;
 }
 
+__global__ void k_absmax_f64(const double *x, long long n, double *out) {
+    __shared__ double sm[16];
+    double m = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(x[i]));
+    const double r = block_reduce<true>(m, sm);
+    if (threadIdx.x == 0) *out = r;
+}
+
 __global__ void k_zero_f64(double *p, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
@@ -115,6 +123,10 @@ void launch_continuity(const GridP &g, T *const J[3], const double *rho_now,
                        const double *rho_prev, double *partials, hipStream_t s) {
     hipLaunchKernelGGL(k_continuity<T>, reduction_grid(g), dim3(64, 4), 0, s, g, J[0], J[1], J[2],
                        rho_now, rho_prev, partials);
+}
+
+void launch_absmax_f64(const double *x, long long n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_absmax_f64, dim3(1), dim3(1024), 0, s, x, n, out);
 }
 
 void launch_final_reduce(const double *partials, double *result, hipStream_t s) {

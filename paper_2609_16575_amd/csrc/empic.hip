@@ -98,6 +98,8 @@ struct SpeciesState {
     int32_t *tile_off = nullptr;  // ntiles + 1
     int32_t *dcount = nullptr;    // device slot count
     long long host_count = 0;
+    bool tiles_valid = false;     // particles grouped by the tile offsets of a previous sort
+    double wmax = 0.0;            // largest |weight| (species w, or the loaded per-particle max)
 };
 
 struct TimedEvent {
@@ -132,6 +134,7 @@ struct empic_sim {
     empic_laser_desc laser{};
     long long nstep = 0, rho_prev_step = -1;
     bool need_sort = true;
+    double jscale = 1099511627776.0;  // fixed-point scale of the fused kernel's current window
     bool poisoned = false;
     std::string err;
     bool timing = false;
@@ -223,8 +226,9 @@ void do_sort(empic_sim *s) {
         const SpeciesP cur = species_params(s, i, S.cur);
         const SpeciesP alt = species_params(s, i, 1 - S.cur);
         launch_sort(s->g, s->ti, cur, alt, s->counts, s->scan_blocks, s->rank, S.tile_off,
-                    s->fault, s->stream);
+                    s->fault, S.tiles_valid, s->stream);
         S.cur = 1 - S.cur;
+        S.tiles_valid = true;
     }
     ev_end(s, t);
     s->need_sort = false;
@@ -241,19 +245,29 @@ void one_step(empic_sim *s) {
     launch_faraday<T>(s->g, E, B, Bb, J, true, s->stream);
     ev_end(s, t);
     // 2. gather, Boris, move, ZigZag for every species
-    ev_begin(s, t, 0);
     if constexpr (sizeof(T) == 4) {
         unsigned mask = 0;
         for (int i = 0; i < s->nsp; ++i) mask |= (unsigned)s->sp[i].cur << i;
-        launch_push_fused(s->g, s->ti, (float *const *)E, (float *const *)Bb, (float *const *)J,
-                          s->table, s->nsp, mask, s->fault, s->fallback, s->fb_list, s->fb_count,
-                          (long long)s->max_capacity * s->max_species, s->stream);
+        // the fused kernel is timed by events attached to its own dispatch
+        TimedEvent tp{nullptr, nullptr, 0};
+        if (s->timing) {
+            (void)hipEventCreate(&tp.a);
+            (void)hipEventCreate(&tp.b);
+        }
+        for (int pass = 0; pass < 2; ++pass)
+            launch_push_fused(s->g, s->ti, (float *const *)E, (float *const *)Bb,
+                              (float *const *)J, s->table, s->nsp, mask, s->fault, s->fallback,
+                              s->fb_list, s->fb_count, (long long)s->max_capacity * s->max_species,
+                              s->jscale, pass == 1, s->stream, pass == 0 ? tp.a : nullptr,
+                              pass == 0 ? tp.b : nullptr);
+        if (s->timing) s->events.push_back(tp);
     } else {
+        ev_begin(s, t, 0);
         for (int i = 0; i < s->nsp; ++i)
             launch_push_f64(s->g, (double *const *)E, (double *const *)Bb, (double *const *)J,
                             species_params(s, i, 0), s->sp[i].host_count, s->fault, s->stream);
+        ev_end(s, t);
     }
-    ev_end(s, t);
     // 3. Ampere-Maxwell, external source, absorbing faces
     ev_begin(s, t, 1);
     if (absorbing) launch_mur_save<T>(s->g, E, (T *)s->mur, s->L.mur_stride, s->stream);
@@ -288,6 +302,25 @@ empic_status fault_status(empic_sim *s, uint32_t w) {
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Fixed-point scale of the fused kernel's LDS current window: a power of two
+// S with S * B <= 2^48, B the largest current one particle can put on one
+// edge in one step, |q| w_max max_a(d_a) / (dt dV) * 13/12 (|dxi| < 1; the
+// segment weights are at most 1 + 1/12).  A register run of 4 particles then
+// stays below 2^51 (exact conversion) and one edge of a tile window can take
+// 2^15 contributions before the int64 sum could overflow.
+void update_jscale(empic_sim *s) {
+    const double dV = s->g.d[0] * s->g.d[1] * s->g.d[2];
+    const double dmax = std::fmax(s->g.d[0], std::fmax(s->g.d[1], s->g.d[2]));
+    double B = 0.0;
+    for (int i = 0; i < s->nsp; ++i)
+        B = std::fmax(B, std::fabs(s->sp[i].desc.q) * s->sp[i].wmax * dmax / (s->g.dt * dV) * 13.0 / 12.0);
+    if (!(B > 0.0) || !std::isfinite(B)) {
+        s->jscale = 1099511627776.0;
+        return;
+    }
+    s->jscale = std::ldexp(1.0, (int)std::floor(std::log2(std::ldexp(1.0, 48) / B)));
+}
 
 }  // namespace
 
@@ -422,6 +455,7 @@ empic_status empic_add_species(empic_sim *s, const empic_species_desc *desc, int
     launch_fill_i32(S.tile_off, s->ti.ntiles + 2, 0, s->stream);  // offsets and count
     const int id = s->nsp;
     s->nsp += 1;
+    S.wmax = desc->per_particle_w ? 0.0 : std::fabs(desc->w);
     DevSpecies D;
     D.p[0] = species_params(s, id, 0);
     D.p[1] = species_params(s, id, S.has_alt ? 1 : 0);
@@ -454,8 +488,18 @@ empic_status empic_load_particles_f64(empic_sim *s, int32_t sp, int64_t count,
         launch_load_f32(s->g, p, count, pos_xyz, u_xyz, w, ids, s->fault, s->stream);
     }
     S.host_count = count;
+    S.tiles_valid = false;
     s->need_sort = true;
     s->rho_prev_step = -1;
+    if (S.desc.per_particle_w && count > 0) {
+        launch_absmax_f64(w, count, s->result, s->stream);
+        double wm = 0.0;
+        EMPIC_HIP(hipGetLastError());
+        EMPIC_HIP(hipMemcpyAsync(&wm, s->result, 8, hipMemcpyDeviceToHost, s->stream));
+        EMPIC_HIP(hipStreamSynchronize(s->stream));
+        S.wmax = std::fmax(S.wmax, wm);
+    }
+    update_jscale(s);
     return check_launch(s, "load_particles");
 }
 
@@ -674,6 +718,13 @@ empic_status empic_kernel_times(empic_sim *s, double *push_ms, int64_t *push_lau
         s->t_n[k] = 0;
     }
     return EMPIC_OK;
+}
+
+void empic_tile_shape(int32_t out[3]) {
+    if (!out) return;
+    out[0] = TX;
+    out[1] = TY;
+    out[2] = TZ;
 }
 
 const char *empic_last_error(const empic_sim *s) { return s ? s->err.c_str() : "null handle"; }

@@ -23,7 +23,9 @@ struct GridP {
 };
 
 // Tile of cells owned by one workgroup of the fused FP32 particle kernel.
-constexpr int TX = 8, TY = 8, TZ = 8;
+// 8 x 8 x 4 keeps the LDS field window (27.6 KB) plus the int64 current
+// window (36.5 KB) under 80 KB, so two workgroups share a CU.
+constexpr int TX = 8, TY = 8, TZ = 4;
 constexpr int TC = TX * TY * TZ;
 // Drift margin: particles up to MARGIN cells outside their tile (moved since
 // the last sort) are still served from the tile's LDS windows.
@@ -34,8 +36,8 @@ constexpr int FWX = TX + 2 * MARGIN + 2, FWY = TY + 2 * MARGIN + 2, FWZ = TZ + 2
 constexpr int JWX = TX + 2 * MARGIN + 3, JWY = TY + 2 * MARGIN + 3, JWZ = TZ + 2 * MARGIN + 3;
 constexpr int FW3 = FWX * FWY * FWZ;
 constexpr int JW3 = JWX * JWY * JWZ;
-constexpr int PUSH_THREADS = 256;
-constexpr int PPT = 8;  // consecutive particles per thread
+constexpr int PUSH_THREADS = 512;
+constexpr int PPT = 4;  // consecutive particles per thread (one 16-byte access per array)
 static_assert(JWX <= 16 && JWY <= 16 && JWZ <= 16, "window index tables hold 16 rows");
 
 // Packed cell index of the FP32 path: i | j << 11 | k << 22; all ones = removed.
@@ -149,11 +151,14 @@ template <typename T>
 void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *partials,
                          hipStream_t s);
 
-// FP32 cell-relative path
+// FP32 cell-relative path.  fallback_pass = false launches the fused tile
+// kernel, true the follow-up pass over particles that left their tile window.
 void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
                        float *const Bbar[3], float *const J[3], const DevSpecies *tbl, int nsp,
                        unsigned cur_mask, uint32_t *fault, unsigned long long *fallback,
-                       int2 *fb_list, unsigned *fb_count, long long fb_cap, hipStream_t s);
+                       int2 *fb_list, unsigned *fb_count, long long fb_cap, double jscale,
+                       bool fallback_pass, hipStream_t s, hipEvent_t ev_start = nullptr,
+                       hipEvent_t ev_stop = nullptr);
 void launch_dry_push_f32(const GridP &g, float *const E[3], float *const Bbar[3],
                          const SpeciesP &sp, double *partial_slot, uint32_t *fault,
                          hipStream_t s);
@@ -164,9 +169,11 @@ void launch_load_f32(const GridP &g, const SpeciesP &sp, long long count, const 
                      hipStream_t s);
 void launch_store_f32(const GridP &g, const SpeciesP &sp, double *pos, double *u, int32_t *ids,
                       hipStream_t s);
+// Counting sort by (tile, cell) of `cur` into `alt`.  tiles_valid: `cur` is
+// still grouped by the tile offsets of its previous sort (faster counting).
 void launch_sort(const GridP &g, const TileInfo &ti, const SpeciesP &cur, const SpeciesP &alt,
                  int32_t *counts, int32_t *scan_blocks, int32_t *rank, int32_t *tile_off,
-                 uint32_t *fault, hipStream_t s);
+                 uint32_t *fault, bool tiles_valid, hipStream_t s);
 
 // FP64 plain path
 void launch_push_f64(const GridP &g, double *const E[3], double *const Bbar[3],
@@ -195,5 +202,7 @@ void launch_continuity(const GridP &g, T *const J[3], const double *rho_now,
                        const double *rho_prev, double *partials, hipStream_t s);
 void launch_final_reduce(const double *partials, double *result, hipStream_t s);
 void launch_fill_i32(int32_t *p, long long n, int32_t v, hipStream_t s);
+// largest |x| of n doubles into *out (one workgroup; set-up path only)
+void launch_absmax_f64(const double *x, long long n, double *out, hipStream_t s);
 
 }  // namespace empic

@@ -5,15 +5,15 @@
 // per-particle weight).  Offsets relative to the cell keep the rounding of a
 // position at 2^-24 of a cell wherever the particle is in the grid.
 //
-// k_push_fused: one workgroup per 8x8x8 tile of cells (particles counting-
-// sorted by tile, then cell).  The workgroup
+// k_push_fused: one workgroup (512 threads) per 8x8x8 tile of cells
+// (particles counting-sorted by tile, then cell).  The workgroup
 //   1. stages E^n and the centred B^n of the tile plus a halo into LDS
 //      (12^3 cells x 6 components),
 //   2. zeroes an LDS current window (13^3 x 3),
-//   3. streams its particles: each thread owns PPT = 8 consecutive particles,
-//      loaded/stored with 16-byte vector accesses, and for each particle does
-//      the staggered CIC gather from LDS (Sec. 2.5), the relativistic Boris
-//      push (Sec. 2.4), the move, and the ZigZag deposit (Sec. 2.5).  Current
+//   3. streams its particles: each thread owns PPT = 4 consecutive particles,
+//      one 16-byte access per array, and first does for all four, without
+//      branches, the staggered CIC gather from LDS (Sec. 2.5), the relativistic
+//      Boris push (Sec. 2.4) and the move, then the ZigZag deposit (Sec. 2.5).  Current
 //      of consecutive particles that stay in the same cell is summed in
 //      registers and added to LDS once per run of the cell (12 LDS atomics
 //      per run instead of 12 per particle); the second ZigZag segment of a
@@ -23,6 +23,8 @@
 // last sort are handled entirely through global memory (rare, counted).
 //
 // Algorithmic bytes per particle: 28 read + 28 written.
+#include <hip/hip_ext.h>
+
 #include "internal.hpp"
 
 namespace empic {
@@ -45,6 +47,7 @@ struct FusedArgs {
     int nsp;
     unsigned cur_mask;      // bit s: buffer set of species s
     float dtd[3];           // dt / d_a
+    double jscale, jinv;    // fixed-point scale of the LDS current window and its inverse
     uint32_t *fault;
     unsigned long long *fallback;  // cumulative count of out-of-window particles
     int2 *fb_list;                 // (species, slot) of this step's out-of-window particles
@@ -296,9 +299,22 @@ __device__ __forceinline__ int edge_off(int q) {
     return JW3 * 2 + o1 + o2 * JWX;
 }
 
-__device__ __forceinline__ void lds_add12(float *sJ, int base, const float v[12]) {
+// Float -> int64 fixed point, round to nearest: the sum with 1.5 * 2^52 puts
+// the integer part of x * scale in the low mantissa bits (valid for
+// |x * scale| < 2^51, which the choice of the scale guarantees).
+__device__ __forceinline__ long long to_fixed(float x, double scale) {
+    const double t = fma((double)x, scale, 6755399441055744.0);
+    return __double_as_longlong(t) - 0x4338000000000000LL;
+}
+
+// The LDS current window accumulates int64 fixed point: integer LDS atomics
+// are an order of magnitude faster than float ones on this LDS, and the tile's
+// sums become exact and independent of the order of the adds.
+__device__ __forceinline__ void lds_add12(unsigned long long *sJ, int base, const float v[12],
+                                          double scale) {
 #pragma unroll
-    for (int q = 0; q < 12; ++q) atomicAdd(sJ + base + edge_off(q), v[q]);
+    for (int q = 0; q < 12; ++q)
+        atomicAdd(sJ + base + edge_off(q), (unsigned long long)to_fixed(v[q], scale));
 }
 
 __device__ __forceinline__ int local_axis(const GridP &g, int a, int c, int wo) {
@@ -310,11 +326,28 @@ __device__ __forceinline__ int local_axis(const GridP &g, int a, int c, int wo) 
     return c - wo;
 }
 
-__global__ __launch_bounds__(PUSH_THREADS) void k_push_fused(FusedArgs A) {
+// Branch-free move of one axis (see move_axis).
+__device__ __forceinline__ void move_axis_sel(float o, float dx, float &e, int &dc, float &no) {
+    e = o + dx;
+    const bool up = e >= 1.f;
+    const bool dn = e < 0.f;
+    const float t = e + 1.f;
+    const bool rc = dn && t >= 1.f;  // e + 1 rounds to 1: stay at offset 0 of this cell
+    dc = up ? 1 : ((dn && !rc) ? -1 : 0);
+    no = up ? (e - 1.f) : (dn ? (rc ? 0.f : t) : e);
+    e = rc ? 0.f : e;
+}
+
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+typedef float __attribute__((address_space(1))) gfloat;
+typedef uint32_t __attribute__((address_space(1))) guint;
+
+__global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     __shared__ float sF[6 * FW3];
-    __shared__ float sJ[3 * JW3];
-    __shared__ int sG[3][JWX > JWY ? (JWX > JWZ ? JWX : JWZ) : (JWY > JWZ ? JWY : JWZ)];
-    __shared__ int sPad[3][JWX > JWY ? (JWX > JWZ ? JWX : JWZ) : (JWY > JWZ ? JWY : JWZ)];
+    __shared__ unsigned long long sJ[3 * JW3];
+    __shared__ int sG[3][16];
+    __shared__ int sPad[3][16];
 
     const GridP &g = A.g;
     const int nb8 = gridDim.x >> 3;
@@ -343,17 +376,32 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push_fused(FusedArgs A) {
         }
     }
     __syncthreads();
-    for (int e = tid; e < 6 * FW3; e += PUSH_THREADS) {
-        const int comp = e / FW3;
-        const int r = e - comp * FW3;
-        const int lz = r / (FWX * FWY);
-        const int r2 = r - lz * (FWX * FWY);
-        const int ly = r2 / FWX, lx = r2 - ly * FWX;
-        const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
-        const float *src = comp < 3 ? A.E[comp] : A.Bb[comp - 3];
-        sF[e] = (gx < 0 || gy < 0 || gz < 0) ? 0.f : src[gx + gy + gz];
+    {
+        // every thread's window loads are issued before any is waited on
+        constexpr int NST = (6 * FW3 + PUSH_THREADS - 1) / PUSH_THREADS;
+        float tmp[NST];
+#pragma unroll
+        for (int q = 0; q < NST; ++q) {
+            const int e = tid + q * PUSH_THREADS;
+            tmp[q] = 0.f;
+            if (e < 6 * FW3) {
+                const int comp = e / FW3;
+                const int r = e - comp * FW3;
+                const int lz = r / (FWX * FWY);
+                const int r2 = r - lz * (FWX * FWY);
+                const int ly = r2 / FWX, lx = r2 - ly * FWX;
+                const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
+                const float *src = comp < 3 ? A.E[comp] : A.Bb[comp - 3];
+                if (gx >= 0 && gy >= 0 && gz >= 0) tmp[q] = src[gx + gy + gz];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NST; ++q) {
+            const int e = tid + q * PUSH_THREADS;
+            if (e < 6 * FW3) sF[e] = tmp[q];
+        }
     }
-    for (int e = tid; e < 3 * JW3; e += PUSH_THREADS) sJ[e] = 0.f;
+    for (int e = tid; e < 3 * JW3; e += PUSH_THREADS) sJ[e] = 0ull;
     __syncthreads();
 
     uint32_t fbits = 0;
@@ -366,105 +414,148 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push_fused(FusedArgs A) {
         const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
         if (beg >= end) continue;
         const float r = D.r;
-        const float *WP = S.per_particle_w ? (const float *)S.w : nullptr;
-        uint32_t *CP = S.cell;
-        float *OXP = (float *)S.pos[0], *OYP = (float *)S.pos[1], *OZP = (float *)S.pos[2];
-        float *UXP = (float *)S.u[0], *UYP = (float *)S.u[1], *UZP = (float *)S.u[2];
+        const float qcx = D.qc[0], qcy = D.qc[1], qcz = D.qc[2];
+        const gfloat *WP = S.per_particle_w ? (const gfloat *)S.w : nullptr;
+        guint *CP = (guint *)S.cell;
+        gfloat *OXP = (gfloat *)S.pos[0], *OYP = (gfloat *)S.pos[1], *OZP = (gfloat *)S.pos[2];
+        gfloat *UXP = (gfloat *)S.u[0], *UYP = (gfloat *)S.u[1], *UZP = (gfloat *)S.u[2];
         const int base0 = beg & ~(PPT - 1);
         for (int base = base0 + tid * PPT; base < end; base += PUSH_THREADS * PPT) {
-            uint32_t cc[PPT];
-            float ox[PPT], oy[PPT], oz[PPT], vx[PPT], vy[PPT], vz[PPT], wq[PPT];
+            // one 16-byte (non-temporal) access per array: PPT = 4 consecutive particles
+            const vu4 c4 = __builtin_nontemporal_load((const vu4 *)(CP + base));
+            const vf4 ox4 = __builtin_nontemporal_load((const vf4 *)(OXP + base));
+            const vf4 oy4 = __builtin_nontemporal_load((const vf4 *)(OYP + base));
+            const vf4 oz4 = __builtin_nontemporal_load((const vf4 *)(OZP + base));
+            const vf4 ux4 = __builtin_nontemporal_load((const vf4 *)(UXP + base));
+            const vf4 uy4 = __builtin_nontemporal_load((const vf4 *)(UYP + base));
+            const vf4 uz4 = __builtin_nontemporal_load((const vf4 *)(UZP + base));
+            vf4 w4 = (vf4){1.f, 1.f, 1.f, 1.f};
+            if (WP) w4 = __builtin_nontemporal_load((const vf4 *)(WP + base));
+
+            // phase 1 (no branches): gather, Boris push and move of the 4 particles.
+            // A particle outside the tile window keeps its state here (it is pushed
+            // by k_push_fallback); the new state is stored right away so that only
+            // the deposit inputs stay live in registers.
+            float dxx[PPT], dxy[PPT], dxz[PPT];
+            int dcp[PPT], jbv[PPT];
             {
-                const vu4 *c4 = (const vu4 *)(CP + base);
-                const vu4 a = __builtin_nontemporal_load(c4), b = __builtin_nontemporal_load(c4 + 1);
-                cc[0] = a.x; cc[1] = a.y; cc[2] = a.z; cc[3] = a.w;
-                cc[4] = b.x; cc[5] = b.y; cc[6] = b.z; cc[7] = b.w;
-            }
-#define EMPIC_LD8(P, DST)                                                              \
-    {                                                                                  \
-        const vf4 *p4 = (const vf4 *)((P) + base);                                     \
-        const vf4 a = __builtin_nontemporal_load(p4), b = __builtin_nontemporal_load(p4 + 1); \
-        DST[0] = a.x; DST[1] = a.y; DST[2] = a.z; DST[3] = a.w;                        \
-        DST[4] = b.x; DST[5] = b.y; DST[6] = b.z; DST[7] = b.w;                        \
-    }
-            EMPIC_LD8(OXP, ox)
-            EMPIC_LD8(OYP, oy)
-            EMPIC_LD8(OZP, oz)
-            EMPIC_LD8(UXP, vx)
-            EMPIC_LD8(UYP, vy)
-            EMPIC_LD8(UZP, vz)
-            if (WP) {
-                EMPIC_LD8(WP, wq)
-            } else {
+                float nux[PPT], nuy[PPT], nuz[PPT], nox[PPT], noy[PPT], noz[PPT];
+                uint32_t ncell[PPT];
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) wq[k] = 1.f;
+                for (int k = 0; k < PPT; ++k) {
+                    const int p = base + k;
+                    const uint32_t c = c4[k];
+                    const bool valid = p >= beg && p < end && c != DEAD;
+                    const int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
+                    const float ox = ox4[k], oy = oy4[k], oz = oz4[k];
+                    if (valid && !(ox >= 0.f && ox < 1.f && oy >= 0.f && oy < 1.f && oz >= 0.f &&
+                                   oz < 1.f))
+                        fbits |= EMPIC_FAULT_OFFSET;
+                    const int lx = local_axis(g, 0, ci, wo[0]);
+                    const int ly = local_axis(g, 1, cj, wo[1]);
+                    const int lz = local_axis(g, 2, ck, wo[2]);
+                    const bool inwin = lx >= 1 && lx <= LHI_X && ly >= 1 && ly <= LHI_Y &&
+                                       lz >= 1 && lz <= LHI_Z;
+                    // clamped window coordinates keep every LDS address inside the window
+                    const int mx = clampi(lx, 1, LHI_X), my = clampi(ly, 1, LHI_Y),
+                              mz = clampi(lz, 1, LHI_Z);
+                    int hx, hy, hz;
+                    float fx, fy, fz;
+                    half_axis(ox, mx, hx, fx);
+                    half_axis(oy, my, hy, fy);
+                    half_axis(oz, mz, hz, fz);
+                    float Ep[3], Bp[3];
+                    Ep[0] = tri_lds(sF + 0 * FW3, hx, my, mz, fx, oy, oz);
+                    Ep[1] = tri_lds(sF + 1 * FW3, mx, hy, mz, ox, fy, oz);
+                    Ep[2] = tri_lds(sF + 2 * FW3, mx, my, hz, ox, oy, fz);
+                    Bp[0] = tri_lds(sF + 3 * FW3, mx, hy, hz, ox, fy, fz);
+                    Bp[1] = tri_lds(sF + 4 * FW3, hx, my, hz, fx, oy, fz);
+                    Bp[2] = tri_lds(sF + 5 * FW3, hx, hy, mz, fx, fy, oz);
+                    float ux = ux4[k], uy = uy4[k], uz = uz4[k], gam;
+                    const float ig = boris_f32(ux, uy, uz, Ep, Bp, r, gam);
+                    if (valid && !isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
+                    const float dx = ux * ig * A.dtd[0], dy = uy * ig * A.dtd[1],
+                                dz = uz * ig * A.dtd[2];
+                    if (valid && !(fabsf(dx) < 1.f && fabsf(dy) < 1.f && fabsf(dz) < 1.f))
+                        fbits |= EMPIC_FAULT_FAST;
+                    float ex, ey, ez, nx, ny, nz;
+                    int cx, cy, cz;
+                    move_axis_sel(ox, dx, ex, cx, nx);
+                    move_axis_sel(oy, dy, ey, cy, ny);
+                    move_axis_sel(oz, dz, ez, cz, nz);
+                    int ni, nj, nk;
+                    const int ok = (int)new_cell(g, 0, ci, cx, ni) & (int)new_cell(g, 1, cj, cy, nj) &
+                                   (int)new_cell(g, 2, ck, cz, nk);
+                    const bool upd = valid && inwin;
+                    ncell[k] = upd ? (ok ? pack_cell(ni, nj, nk) : DEAD) : c;
+                    nox[k] = upd ? nx : ox;
+                    noy[k] = upd ? ny : oy;
+                    noz[k] = upd ? nz : oz;
+                    nux[k] = upd ? ux : ux4[k];
+                    nuy[k] = upd ? uy : uy4[k];
+                    nuz[k] = upd ? uz : uz4[k];
+                    dxx[k] = dx;
+                    dxy[k] = dy;
+                    dxz[k] = dz;
+                    dcp[k] = (cx + 1) | ((cy + 1) << 2) | ((cz + 1) << 4);  // no crossing: 21
+                    jbv[k] = !valid ? -1 : (inwin ? lx + JWX * (ly + JWY * lz) : -2);
+                    // keep the scheduler from hoisting every particle's LDS reads at once
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if (base >= beg && base + PPT <= end) {
+                    __builtin_nontemporal_store((vu4){ncell[0], ncell[1], ncell[2], ncell[3]},
+                                                (vu4 *)(CP + base));
+                    __builtin_nontemporal_store((vf4){nox[0], nox[1], nox[2], nox[3]}, (vf4 *)(OXP + base));
+                    __builtin_nontemporal_store((vf4){noy[0], noy[1], noy[2], noy[3]}, (vf4 *)(OYP + base));
+                    __builtin_nontemporal_store((vf4){noz[0], noz[1], noz[2], noz[3]}, (vf4 *)(OZP + base));
+                    __builtin_nontemporal_store((vf4){nux[0], nux[1], nux[2], nux[3]}, (vf4 *)(UXP + base));
+                    __builtin_nontemporal_store((vf4){nuy[0], nuy[1], nuy[2], nuy[3]}, (vf4 *)(UYP + base));
+                    __builtin_nontemporal_store((vf4){nuz[0], nuz[1], nuz[2], nuz[3]}, (vf4 *)(UZP + base));
+                } else {
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        if (jbv[k] == -1) continue;
+                        const int p = base + k;
+                        CP[p] = ncell[k];
+                        OXP[p] = nox[k];
+                        OYP[p] = noy[k];
+                        OZP[p] = noz[k];
+                        UXP[p] = nux[k];
+                        UYP[p] = nuy[k];
+                        UZP[p] = nuz[k];
+                    }
+                }
             }
-#undef EMPIC_LD8
+
+            // phase 2: ZigZag deposit (Sec. 2.5) into registers / LDS
             float acc[12];
 #pragma unroll
             for (int q = 0; q < 12; ++q) acc[q] = 0.f;
             int run = -1;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                const int p = base + k;
-                if (p < beg || p >= end || cc[k] == DEAD) continue;
-                const uint32_t c = cc[k];
-                const int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
-                if (!(ox[k] >= 0.f && ox[k] < 1.f && oy[k] >= 0.f && oy[k] < 1.f && oz[k] >= 0.f &&
-                      oz[k] < 1.f))
-                    fbits |= EMPIC_FAULT_OFFSET;
-                const int lx = local_axis(g, 0, ci, wo[0]);
-                const int ly = local_axis(g, 1, cj, wo[1]);
-                const int lz = local_axis(g, 2, ck, wo[2]);
-                const bool inwin = lx >= 1 && lx <= LHI_X && ly >= 1 && ly <= LHI_Y && lz >= 1 &&
-                                   lz <= LHI_Z;
-                if (!inwin) {
-                    // drifted out of the tile window since the last sort: left unchanged
-                    // here and pushed through global memory by k_push_fallback
+                const int jb = jbv[k];
+                if (jb == -1) continue;
+                if (jb == -2) {
+                    // drifted out of the tile window since the last sort
                     ++nfb;
                     const unsigned slot = atomicAdd(A.fb_count, 1u);
-                    if (slot < (unsigned long long)A.fb_cap) A.fb_list[slot] = make_int2(s, p);
+                    if (slot < (unsigned long long)A.fb_cap) A.fb_list[slot] = make_int2(s, base + k);
                     else fbits |= EMPIC_FAULT_CELL;
                     continue;
                 }
-                // staggered CIC gather from the LDS tile (Sec. 2.5)
-                int hx, hy, hz;
-                float fx, fy, fz;
-                half_axis(ox[k], lx, hx, fx);
-                half_axis(oy[k], ly, hy, fy);
-                half_axis(oz[k], lz, hz, fz);
-                float Ep[3], Bp[3];
-                Ep[0] = tri_lds(sF + 0 * FW3, hx, ly, lz, fx, oy[k], oz[k]);
-                Ep[1] = tri_lds(sF + 1 * FW3, lx, hy, lz, ox[k], fy, oz[k]);
-                Ep[2] = tri_lds(sF + 2 * FW3, lx, ly, hz, ox[k], oy[k], fz);
-                Bp[0] = tri_lds(sF + 3 * FW3, lx, hy, hz, ox[k], fy, fz);
-                Bp[1] = tri_lds(sF + 4 * FW3, hx, ly, hz, fx, oy[k], fz);
-                Bp[2] = tri_lds(sF + 5 * FW3, hx, hy, lz, fx, fy, oz[k]);
-                // Boris push (Sec. 2.4)
-                float gam;
-                const float ig = boris_f32(vx[k], vy[k], vz[k], Ep, Bp, r, gam);
-                if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
-                // move + ZigZag (Sec. 2.5)
-                const float o[3] = {ox[k], oy[k], oz[k]};
-                const float uu[3] = {vx[k], vy[k], vz[k]};
-                float e[3], no[3], dx[3];
-                int dc[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    dx[a] = uu[a] * ig * A.dtd[a];
-                    if (!(fabsf(dx[a]) < 1.f)) fbits |= EMPIC_FAULT_FAST;
-                    move_axis(o[a], dx[a], e[a], dc[a], no[a]);
-                }
-                const float amp[3] = {D.qc[0] * wq[k], D.qc[1] * wq[k], D.qc[2] * wq[k]};
-                const int jb = lx + JWX * (ly + JWY * lz);
+                const float wq = w4[k];
+                const float amp[3] = {qcx * wq, qcy * wq, qcz * wq};
                 if (jb != run) {
-                    if (run >= 0) lds_add12(sJ, run, acc);
+                    if (run >= 0) lds_add12(sJ, run, acc, A.jscale);
 #pragma unroll
                     for (int q = 0; q < 12; ++q) acc[q] = 0.f;
                     run = jb;
                 }
+                const float o[3] = {ox4[k], oy4[k], oz4[k]};
+                const float dx[3] = {dxx[k], dxy[k], dxz[k]};
                 float v[12];
-                if ((dc[0] | dc[1] | dc[2]) == 0) {
+                if (dcp[k] == 21) {
                     // one straight segment in this cell
                     const float W[3] = {fmaf(0.5f, dx[0], o[0]), fmaf(0.5f, dx[1], o[1]),
                                         fmaf(0.5f, dx[2], o[2])};
@@ -472,55 +563,21 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push_fused(FusedArgs A) {
 #pragma unroll
                     for (int q = 0; q < 12; ++q) acc[q] += v[q];
                 } else {
-                    float WA[3], DA[3], WB[3], DB[3];
+                    const int dc[3] = {(dcp[k] & 3) - 1, ((dcp[k] >> 2) & 3) - 1,
+                                       ((dcp[k] >> 4) & 3) - 1};
+                    float e[3], WA[3], DA[3], WB[3], DB[3], nn;
+                    int dd;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) move_axis_sel(o[a], dx[a], e[a], dd, nn);
                     zigzag_split(o, dx, e, dc, WA, DA, WB, DB);
                     segment_weights(WA, DA, amp, v);
 #pragma unroll
                     for (int q = 0; q < 12; ++q) acc[q] += v[q];
                     segment_weights(WB, DB, amp, v);
-                    lds_add12(sJ, jb + dc[0] + JWX * (dc[1] + JWY * dc[2]), v);
-                }
-                int ni, nj, nk;
-                const int ok = (int)new_cell(g, 0, ci, dc[0], ni) &
-                               (int)new_cell(g, 1, cj, dc[1], nj) &
-                               (int)new_cell(g, 2, ck, dc[2], nk);
-                cc[k] = ok ? pack_cell(ni, nj, nk) : DEAD;
-                ox[k] = no[0];
-                oy[k] = no[1];
-                oz[k] = no[2];
-            }
-            if (run >= 0) lds_add12(sJ, run, acc);
-            if (base >= beg && base + PPT <= end) {
-                vu4 *c4 = (vu4 *)(CP + base);
-                __builtin_nontemporal_store((vu4){cc[0], cc[1], cc[2], cc[3]}, c4);
-                __builtin_nontemporal_store((vu4){cc[4], cc[5], cc[6], cc[7]}, c4 + 1);
-#define EMPIC_ST8(P, SRC)                                                                 \
-    {                                                                                     \
-        vf4 *p4 = (vf4 *)((P) + base);                                                    \
-        __builtin_nontemporal_store((vf4){SRC[0], SRC[1], SRC[2], SRC[3]}, p4);           \
-        __builtin_nontemporal_store((vf4){SRC[4], SRC[5], SRC[6], SRC[7]}, p4 + 1);       \
-    }
-                EMPIC_ST8(OXP, ox)
-                EMPIC_ST8(OYP, oy)
-                EMPIC_ST8(OZP, oz)
-                EMPIC_ST8(UXP, vx)
-                EMPIC_ST8(UYP, vy)
-                EMPIC_ST8(UZP, vz)
-#undef EMPIC_ST8
-            } else {
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    const int p = base + k;
-                    if (p < beg || p >= end) continue;
-                    CP[p] = cc[k];
-                    OXP[p] = ox[k];
-                    OYP[p] = oy[k];
-                    OZP[p] = oz[k];
-                    UXP[p] = vx[k];
-                    UYP[p] = vy[k];
-                    UZP[p] = vz[k];
+                    lds_add12(sJ, jb + dc[0] + JWX * (dc[1] + JWY * dc[2]), v, A.jscale);
                 }
             }
+            if (run >= 0) lds_add12(sJ, run, acc, A.jscale);
         }
     }
     if (fbits) atomicOr(A.fault, fbits | (nfb ? EMPIC_FAULT_FALLBACK : 0u));
@@ -529,8 +586,9 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push_fused(FusedArgs A) {
     __syncthreads();
     // add the tile's current to global J (non-zero entries only)
     for (int e = tid; e < 3 * JW3; e += PUSH_THREADS) {
-        const float v = sJ[e];
-        if (v == 0.f) continue;
+        const long long fx = (long long)sJ[e];
+        if (fx == 0) continue;
+        const float v = (float)((double)fx * A.jinv);
         const int comp = e / JW3;
         const int r = e - comp * JW3;
         const int lz = r / (JWX * JWY);
@@ -723,6 +781,55 @@ __global__ void k_sort_count(TileInfo ti, GridP g, SpeciesP sp, int32_t *counts,
     rank[p] = atomicAdd(counts + sort_key(ti, i, j, k), 1);
 }
 
+// Counting pass when the particles are still grouped by the tiles of the
+// previous sort (the usual case): one workgroup per old tile ranks the
+// particles that stayed in the tile with LDS atomics, then reserves each
+// key's range with one global atomic; particles that moved to another tile
+// take a global atomic directly.  rank: >= 0 final, -1 removed, <= -2 local
+// rank (-2 - r) awaiting its key's base.
+constexpr int SORT_T = 512;
+__global__ __launch_bounds__(SORT_T) void k_sort_count_tiles(TileInfo ti, GridP g, SpeciesP sp,
+                                                             int32_t *counts, int32_t *rank,
+                                                             uint32_t *fault) {
+    __shared__ int hist[TC];
+    __shared__ int basek[TC];
+    const int t = blockIdx.x;
+    const int beg = sp.tile_off[t], end = sp.tile_off[t + 1];
+    if (beg >= end) return;
+    for (int l = threadIdx.x; l < TC; l += SORT_T) hist[l] = 0;
+    __syncthreads();
+    const long long t0 = (long long)t * TC;
+    for (int p = beg + threadIdx.x; p < end; p += SORT_T) {
+        const uint32_t c = sp.cell[p];
+        if (c == DEAD) {
+            rank[p] = -1;
+            continue;
+        }
+        const int i = cell_i(c), j = cell_j(c), k = cell_k(c);
+        if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) {
+            atomicOr(fault, (uint32_t)EMPIC_FAULT_CELL);
+            rank[p] = -1;
+            continue;
+        }
+        const long long key = sort_key(ti, i, j, k);
+        if (key >= t0 && key < t0 + TC)
+            rank[p] = -2 - atomicAdd(hist + (key - t0), 1);
+        else
+            rank[p] = atomicAdd(counts + key, 1);
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < TC; l += SORT_T)
+        basek[l] = hist[l] ? atomicAdd(counts + t0 + l, hist[l]) : 0;
+    __syncthreads();
+    for (int p = beg + threadIdx.x; p < end; p += SORT_T) {
+        const int r = rank[p];
+        if (r > -2) continue;
+        const uint32_t c = sp.cell[p];
+        const long long key = sort_key(ti, cell_i(c), cell_j(c), cell_k(c));
+        rank[p] = basek[key - t0] + (-2 - r);
+    }
+}
+
 constexpr int SCAN_T = 256, SCAN_PER = 4, SCAN_B = SCAN_T * SCAN_PER;
 
 __device__ inline int block_exclusive_scan(int v, int *sm, int &total) {
@@ -835,7 +942,9 @@ void launch_write_species(DevSpecies *dst, const DevSpecies &v, hipStream_t s) {
 void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
                        float *const Bbar[3], float *const J[3], const DevSpecies *tbl, int nsp,
                        unsigned cur_mask, uint32_t *fault, unsigned long long *fallback,
-                       int2 *fb_list, unsigned *fb_count, long long fb_cap, hipStream_t s) {
+                       int2 *fb_list, unsigned *fb_count, long long fb_cap, double jscale,
+                       bool fallback_pass, hipStream_t s, hipEvent_t ev_start,
+                       hipEvent_t ev_stop) {
     FusedArgs A;
     A.g = g;
     A.ti = ti;
@@ -848,14 +957,21 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
     A.tbl = tbl;
     A.nsp = nsp;
     A.cur_mask = cur_mask;
+    A.jscale = jscale;
+    A.jinv = 1.0 / jscale;
     A.fault = fault;
     A.fallback = fallback;
     A.fb_list = fb_list;
     A.fb_count = fb_count;
     A.fb_cap = fb_cap;
     const int nb = 8 * ((ti.ntiles + 7) / 8);
-    hipLaunchKernelGGL(k_push_fused, dim3(nb), dim3(PUSH_THREADS), 0, s, A);
-    hipLaunchKernelGGL(k_push_fallback, dim3(64), dim3(256), 0, s, A);
+    if (fallback_pass)
+        hipLaunchKernelGGL(k_push_fallback, dim3(64), dim3(256), 0, s, A);
+    else if (ev_start)  // timestamps taken by the dispatch itself
+        hipExtLaunchKernelGGL(k_push_fused, dim3(nb), dim3(PUSH_THREADS), 0, s, ev_start, ev_stop,
+                              0, A);
+    else
+        hipLaunchKernelGGL(k_push_fused, dim3(nb), dim3(PUSH_THREADS), 0, s, A);
 }
 
 void launch_dry_push_f32(const GridP &g, float *const E[3], float *const Bbar[3],
@@ -891,12 +1007,17 @@ void launch_store_f32(const GridP &g, const SpeciesP &sp, double *pos, double *u
 
 void launch_sort(const GridP &g, const TileInfo &ti, const SpeciesP &cur, const SpeciesP &alt,
                  int32_t *counts, int32_t *scan_blocks, int32_t *rank, int32_t *tile_off,
-                 uint32_t *fault, hipStream_t s) {
+                 uint32_t *fault, bool tiles_valid, hipStream_t s) {
     const long long NK = ti.NK;
     launch_fill_i32(counts, NK + 1, 0, s);
-    if (cur.capacity > 0)
-        hipLaunchKernelGGL(k_sort_count, dim3(nblk(cur.capacity, 256)), dim3(256), 0, s, ti, g,
-                           cur, counts, rank, fault);
+    if (cur.capacity > 0) {
+        if (tiles_valid)
+            hipLaunchKernelGGL(k_sort_count_tiles, dim3(ti.ntiles), dim3(SORT_T), 0, s, ti, g, cur,
+                               counts, rank, fault);
+        else
+            hipLaunchKernelGGL(k_sort_count, dim3(nblk(cur.capacity, 256)), dim3(256), 0, s, ti,
+                               g, cur, counts, rank, fault);
+    }
     const int nb = (int)((NK + SCAN_B - 1) / SCAN_B);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_T), 0, s, counts, NK, scan_blocks);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_T), 0, s, scan_blocks, nb, counts, NK);

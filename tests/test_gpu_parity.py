@@ -206,11 +206,17 @@ def test_sort_is_a_permutation():
     for (P0, U0, I0), (P1, U1, I1) in zip(before, after):
         assert np.array_equal(I0, I1)
         assert np.array_equal(P0, P1) and np.array_equal(U0, U1)
-    # storage order is by tile then cell
+    # storage order is by tile, then by cell inside the tile
+    from paper_2609_16575_amd import _lib
+    T = np.array(_lib.tile_shape())
+    nt = -(-np.array(w.n) // T)
     P, _, _ = g.particles(0)
     c = np.floor(P).astype(int)
-    tile = (c[:, 0] // 8) + 2 * ((c[:, 1] // 8) + 2 * (c[:, 2] // 8))
-    assert np.all(np.diff(tile) >= 0)
+    t = c // T
+    loc = c - t * T
+    key = ((t[:, 0] + nt[0] * (t[:, 1] + nt[1] * t[:, 2])) * T.prod()
+           + loc[:, 0] + T[0] * (loc[:, 1] + T[1] * loc[:, 2]))
+    assert np.all(np.diff(key) >= 0)
 
 
 def test_empty_species_and_no_species():
