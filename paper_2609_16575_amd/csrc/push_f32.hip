@@ -11,13 +11,10 @@
 //      (12^3 cells x 6 components),
 //   2. zeroes an LDS current window (13^3 x 3),
 //   3. streams its particles: each thread owns PPT = 4 consecutive particles,
-//      one 16-byte access per array, and first does for all four, without
-//      branches, the staggered CIC gather from LDS (Sec. 2.5), the relativistic
-//      Boris push (Sec. 2.4) and the move, then the ZigZag deposit (Sec. 2.5).  Current
-//      of consecutive particles that stay in the same cell is summed in
-//      registers and added to LDS once per run of the cell (12 LDS atomics
-//      per run instead of 12 per particle); the second ZigZag segment of a
-//      cell-crossing particle is added to LDS directly,
+//      one 16-byte access per array, and for each does the staggered CIC
+//      gather from LDS (Sec. 2.5), the relativistic Boris push (Sec. 2.4), the
+//      move and the ZigZag deposit (Sec. 2.5): 12 int64 LDS atomics per
+//      straight segment (24 for a particle crossing a cell face),
 //   4. adds the non-zero LDS current to global J with float atomics.
 // Particles that drifted more than MARGIN cells out of their tile since the
 // last sort are handled entirely through global memory (rare, counted).
@@ -338,7 +335,6 @@ __device__ __forceinline__ void move_axis_sel(float o, float dx, float &e, int &
     e = rc ? 0.f : e;
 }
 
-__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 typedef float __attribute__((address_space(1))) gfloat;
 typedef uint32_t __attribute__((address_space(1))) guint;
@@ -432,152 +428,117 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
             vf4 w4 = (vf4){1.f, 1.f, 1.f, 1.f};
             if (WP) w4 = __builtin_nontemporal_load((const vf4 *)(WP + base));
 
-            // phase 1 (no branches): gather, Boris push and move of the 4 particles.
-            // A particle outside the tile window keeps its state here (it is pushed
-            // by k_push_fallback); the new state is stored right away so that only
-            // the deposit inputs stay live in registers.
-            float dxx[PPT], dxy[PPT], dxz[PPT];
-            int dcp[PPT], jbv[PPT];
-            {
-                float nux[PPT], nuy[PPT], nuz[PPT], nox[PPT], noy[PPT], noz[PPT];
-                uint32_t ncell[PPT];
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    const int p = base + k;
-                    const uint32_t c = c4[k];
-                    const bool valid = p >= beg && p < end && c != DEAD;
-                    const int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
-                    const float ox = ox4[k], oy = oy4[k], oz = oz4[k];
-                    if (valid && !(ox >= 0.f && ox < 1.f && oy >= 0.f && oy < 1.f && oz >= 0.f &&
-                                   oz < 1.f))
-                        fbits |= EMPIC_FAULT_OFFSET;
-                    const int lx = local_axis(g, 0, ci, wo[0]);
-                    const int ly = local_axis(g, 1, cj, wo[1]);
-                    const int lz = local_axis(g, 2, ck, wo[2]);
-                    const bool inwin = lx >= 1 && lx <= LHI_X && ly >= 1 && ly <= LHI_Y &&
-                                       lz >= 1 && lz <= LHI_Z;
-                    // clamped window coordinates keep every LDS address inside the window
-                    const int mx = clampi(lx, 1, LHI_X), my = clampi(ly, 1, LHI_Y),
-                              mz = clampi(lz, 1, LHI_Z);
-                    int hx, hy, hz;
-                    float fx, fy, fz;
-                    half_axis(ox, mx, hx, fx);
-                    half_axis(oy, my, hy, fy);
-                    half_axis(oz, mz, hz, fz);
-                    float Ep[3], Bp[3];
-                    Ep[0] = tri_lds(sF + 0 * FW3, hx, my, mz, fx, oy, oz);
-                    Ep[1] = tri_lds(sF + 1 * FW3, mx, hy, mz, ox, fy, oz);
-                    Ep[2] = tri_lds(sF + 2 * FW3, mx, my, hz, ox, oy, fz);
-                    Bp[0] = tri_lds(sF + 3 * FW3, mx, hy, hz, ox, fy, fz);
-                    Bp[1] = tri_lds(sF + 4 * FW3, hx, my, hz, fx, oy, fz);
-                    Bp[2] = tri_lds(sF + 5 * FW3, hx, hy, mz, fx, fy, oz);
-                    float ux = ux4[k], uy = uy4[k], uz = uz4[k], gam;
-                    const float ig = boris_f32(ux, uy, uz, Ep, Bp, r, gam);
-                    if (valid && !isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
-                    const float dx = ux * ig * A.dtd[0], dy = uy * ig * A.dtd[1],
-                                dz = uz * ig * A.dtd[2];
-                    if (valid && !(fabsf(dx) < 1.f && fabsf(dy) < 1.f && fabsf(dz) < 1.f))
-                        fbits |= EMPIC_FAULT_FAST;
-                    float ex, ey, ez, nx, ny, nz;
-                    int cx, cy, cz;
-                    move_axis_sel(ox, dx, ex, cx, nx);
-                    move_axis_sel(oy, dy, ey, cy, ny);
-                    move_axis_sel(oz, dz, ez, cz, nz);
-                    int ni, nj, nk;
-                    const int ok = (int)new_cell(g, 0, ci, cx, ni) & (int)new_cell(g, 1, cj, cy, nj) &
-                                   (int)new_cell(g, 2, ck, cz, nk);
-                    const bool upd = valid && inwin;
-                    ncell[k] = upd ? (ok ? pack_cell(ni, nj, nk) : DEAD) : c;
-                    nox[k] = upd ? nx : ox;
-                    noy[k] = upd ? ny : oy;
-                    noz[k] = upd ? nz : oz;
-                    nux[k] = upd ? ux : ux4[k];
-                    nuy[k] = upd ? uy : uy4[k];
-                    nuz[k] = upd ? uz : uz4[k];
-                    dxx[k] = dx;
-                    dxy[k] = dy;
-                    dxz[k] = dz;
-                    dcp[k] = (cx + 1) | ((cy + 1) << 2) | ((cz + 1) << 4);  // no crossing: 21
-                    jbv[k] = !valid ? -1 : (inwin ? lx + JWX * (ly + JWY * lz) : -2);
-                    // keep the scheduler from hoisting every particle's LDS reads at once
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                if (base >= beg && base + PPT <= end) {
-                    __builtin_nontemporal_store((vu4){ncell[0], ncell[1], ncell[2], ncell[3]},
-                                                (vu4 *)(CP + base));
-                    __builtin_nontemporal_store((vf4){nox[0], nox[1], nox[2], nox[3]}, (vf4 *)(OXP + base));
-                    __builtin_nontemporal_store((vf4){noy[0], noy[1], noy[2], noy[3]}, (vf4 *)(OYP + base));
-                    __builtin_nontemporal_store((vf4){noz[0], noz[1], noz[2], noz[3]}, (vf4 *)(OZP + base));
-                    __builtin_nontemporal_store((vf4){nux[0], nux[1], nux[2], nux[3]}, (vf4 *)(UXP + base));
-                    __builtin_nontemporal_store((vf4){nuy[0], nuy[1], nuy[2], nuy[3]}, (vf4 *)(UYP + base));
-                    __builtin_nontemporal_store((vf4){nuz[0], nuz[1], nuz[2], nuz[3]}, (vf4 *)(UZP + base));
-                } else {
-#pragma unroll
-                    for (int k = 0; k < PPT; ++k) {
-                        if (jbv[k] == -1) continue;
-                        const int p = base + k;
-                        CP[p] = ncell[k];
-                        OXP[p] = nox[k];
-                        OYP[p] = noy[k];
-                        OZP[p] = noz[k];
-                        UXP[p] = nux[k];
-                        UYP[p] = nuy[k];
-                        UZP[p] = nuz[k];
-                    }
-                }
-            }
-
-            // phase 2: ZigZag deposit (Sec. 2.5) into registers / LDS
-            float acc[12];
-#pragma unroll
-            for (int q = 0; q < 12; ++q) acc[q] = 0.f;
-            int run = -1;
+            // per particle: staggered CIC gather from LDS (Sec. 2.5), Boris push
+            // (Sec. 2.4), move, ZigZag deposit (Sec. 2.5) into the fixed-point LDS
+            // window.  A particle outside the tile window keeps its state here and is
+            // pushed by k_push_fallback.
+            float nux[PPT], nuy[PPT], nuz[PPT], nox[PPT], noy[PPT], noz[PPT];
+            uint32_t ncell[PPT];
+            bool live[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                const int jb = jbv[k];
-                if (jb == -1) continue;
-                if (jb == -2) {
+                const int p = base + k;
+                const uint32_t c = c4[k];
+                const bool valid = p >= beg && p < end && c != DEAD;
+                live[k] = valid;
+                const int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
+                const float ox = ox4[k], oy = oy4[k], oz = oz4[k];
+                ncell[k] = c;
+                nox[k] = ox;
+                noy[k] = oy;
+                noz[k] = oz;
+                nux[k] = ux4[k];
+                nuy[k] = uy4[k];
+                nuz[k] = uz4[k];
+                if (!valid) continue;
+                if (!(ox >= 0.f && ox < 1.f && oy >= 0.f && oy < 1.f && oz >= 0.f && oz < 1.f))
+                    fbits |= EMPIC_FAULT_OFFSET;
+                const int lx = local_axis(g, 0, ci, wo[0]);
+                const int ly = local_axis(g, 1, cj, wo[1]);
+                const int lz = local_axis(g, 2, ck, wo[2]);
+                if (!(lx >= 1 && lx <= LHI_X && ly >= 1 && ly <= LHI_Y && lz >= 1 && lz <= LHI_Z)) {
                     // drifted out of the tile window since the last sort
                     ++nfb;
                     const unsigned slot = atomicAdd(A.fb_count, 1u);
-                    if (slot < (unsigned long long)A.fb_cap) A.fb_list[slot] = make_int2(s, base + k);
+                    if (slot < (unsigned long long)A.fb_cap) A.fb_list[slot] = make_int2(s, p);
                     else fbits |= EMPIC_FAULT_CELL;
                     continue;
                 }
+                int hx, hy, hz;
+                float fx, fy, fz;
+                half_axis(ox, lx, hx, fx);
+                half_axis(oy, ly, hy, fy);
+                half_axis(oz, lz, hz, fz);
+                float Ep[3], Bp[3];
+                Ep[0] = tri_lds(sF + 0 * FW3, hx, ly, lz, fx, oy, oz);
+                Ep[1] = tri_lds(sF + 1 * FW3, lx, hy, lz, ox, fy, oz);
+                Ep[2] = tri_lds(sF + 2 * FW3, lx, ly, hz, ox, oy, fz);
+                Bp[0] = tri_lds(sF + 3 * FW3, lx, hy, hz, ox, fy, fz);
+                Bp[1] = tri_lds(sF + 4 * FW3, hx, ly, hz, fx, oy, fz);
+                Bp[2] = tri_lds(sF + 5 * FW3, hx, hy, lz, fx, fy, oz);
+                float ux = ux4[k], uy = uy4[k], uz = uz4[k], gam;
+                const float ig = boris_f32(ux, uy, uz, Ep, Bp, r, gam);
+                if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
+                const float o[3] = {ox, oy, oz};
+                const float dx[3] = {ux * ig * A.dtd[0], uy * ig * A.dtd[1], uz * ig * A.dtd[2]};
+                if (!(fabsf(dx[0]) < 1.f && fabsf(dx[1]) < 1.f && fabsf(dx[2]) < 1.f))
+                    fbits |= EMPIC_FAULT_FAST;
+                float e[3], no[3];
+                int dc[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) move_axis_sel(o[a], dx[a], e[a], dc[a], no[a]);
                 const float wq = w4[k];
                 const float amp[3] = {qcx * wq, qcy * wq, qcz * wq};
-                if (jb != run) {
-                    if (run >= 0) lds_add12(sJ, run, acc, A.jscale);
-#pragma unroll
-                    for (int q = 0; q < 12; ++q) acc[q] = 0.f;
-                    run = jb;
-                }
-                const float o[3] = {ox4[k], oy4[k], oz4[k]};
-                const float dx[3] = {dxx[k], dxy[k], dxz[k]};
+                const int jb = lx + JWX * (ly + JWY * lz);
                 float v[12];
-                if (dcp[k] == 21) {
+                if ((dc[0] | dc[1] | dc[2]) == 0) {
                     // one straight segment in this cell
                     const float W[3] = {fmaf(0.5f, dx[0], o[0]), fmaf(0.5f, dx[1], o[1]),
                                         fmaf(0.5f, dx[2], o[2])};
                     segment_weights(W, dx, amp, v);
-#pragma unroll
-                    for (int q = 0; q < 12; ++q) acc[q] += v[q];
+                    lds_add12(sJ, jb, v, A.jscale);
                 } else {
-                    const int dc[3] = {(dcp[k] & 3) - 1, ((dcp[k] >> 2) & 3) - 1,
-                                       ((dcp[k] >> 4) & 3) - 1};
-                    float e[3], WA[3], DA[3], WB[3], DB[3], nn;
-                    int dd;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) move_axis_sel(o[a], dx[a], e[a], dd, nn);
+                    float WA[3], DA[3], WB[3], DB[3];
                     zigzag_split(o, dx, e, dc, WA, DA, WB, DB);
                     segment_weights(WA, DA, amp, v);
-#pragma unroll
-                    for (int q = 0; q < 12; ++q) acc[q] += v[q];
+                    lds_add12(sJ, jb, v, A.jscale);
                     segment_weights(WB, DB, amp, v);
                     lds_add12(sJ, jb + dc[0] + JWX * (dc[1] + JWY * dc[2]), v, A.jscale);
                 }
+                int ni, nj, nk;
+                const int ok = (int)new_cell(g, 0, ci, dc[0], ni) & (int)new_cell(g, 1, cj, dc[1], nj) &
+                               (int)new_cell(g, 2, ck, dc[2], nk);
+                ncell[k] = ok ? pack_cell(ni, nj, nk) : DEAD;
+                nox[k] = no[0];
+                noy[k] = no[1];
+                noz[k] = no[2];
+                nux[k] = ux;
+                nuy[k] = uy;
+                nuz[k] = uz;
             }
-            if (run >= 0) lds_add12(sJ, run, acc, A.jscale);
+            if (base >= beg && base + PPT <= end) {
+                __builtin_nontemporal_store((vu4){ncell[0], ncell[1], ncell[2], ncell[3]},
+                                            (vu4 *)(CP + base));
+                __builtin_nontemporal_store((vf4){nox[0], nox[1], nox[2], nox[3]}, (vf4 *)(OXP + base));
+                __builtin_nontemporal_store((vf4){noy[0], noy[1], noy[2], noy[3]}, (vf4 *)(OYP + base));
+                __builtin_nontemporal_store((vf4){noz[0], noz[1], noz[2], noz[3]}, (vf4 *)(OZP + base));
+                __builtin_nontemporal_store((vf4){nux[0], nux[1], nux[2], nux[3]}, (vf4 *)(UXP + base));
+                __builtin_nontemporal_store((vf4){nuy[0], nuy[1], nuy[2], nuy[3]}, (vf4 *)(UYP + base));
+                __builtin_nontemporal_store((vf4){nuz[0], nuz[1], nuz[2], nuz[3]}, (vf4 *)(UZP + base));
+            } else {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    if (!live[k]) continue;
+                    const int p = base + k;
+                    CP[p] = ncell[k];
+                    OXP[p] = nox[k];
+                    OYP[p] = noy[k];
+                    OZP[p] = noz[k];
+                    UXP[p] = nux[k];
+                    UYP[p] = nuy[k];
+                    UZP[p] = nuz[k];
+                }
+            }
         }
     }
     if (fbits) atomicOr(A.fault, fbits | (nfb ? EMPIC_FAULT_FALLBACK : 0u));
