@@ -527,3 +527,251 @@ double orc_kinetic(int64_t np, const double *u, const int8_t *alive, const doubl
     }
     return s;
 }
+
+/* ======================================================================== */
+/* Adjoint of one step (vector-Jacobian product), periodic grids.             */
+/* Not in the paper: the differentiable variant of the cycle.  The step is    */
+/*   B' = B - dt Cf E,  Bbar = (B + B')/2,  E_p = G_E(x) E,  B_p = G_B(x) Bbar, */
+/*   u' = Boris(u, E_p, B_p),  x' = x + dt u'/gamma',  J = Z(x, x'),          */
+/*   E' = E + dt Cb B' - dt J                                                 */
+/* with Cf / Cb the forward / backward difference curls (Cf^T = Cb on a       */
+/* periodic grid).  Given the adjoints of (E', B', x', u') it returns those   */
+/* of (E, B, x, u), differentiating inside the current piece of every         */
+/* piecewise map (relay-point branch and interpolation corners frozen).       */
+/* ======================================================================== */
+
+/* adjoint of the Boris push: forward from (u, E, B), reverse with lu' */
+static void boris_vjp(const double u[3], const double Ep[3], const double Bp[3], double r,
+                      const double lup[3], double lu[3], double lE[3], double lB[3]) {
+    double um[3], t[3], s[3], up[3];
+    for (int a = 0; a < 3; ++a) um[a] = u[a] + r * Ep[a];
+    const double gm = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    for (int a = 0; a < 3; ++a) t[a] = r * Bp[a] / gm;
+    const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    for (int a = 0; a < 3; ++a) s[a] = 2.0 * t[a] / (1.0 + tt);
+    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+    /* u' = upl + r E */
+    double lupl[3], lum[3], lupv[3], ls[3], lt[3];
+    for (int a = 0; a < 3; ++a) {
+        lupl[a] = lup[a];
+        lE[a] = r * lup[a];
+    }
+    /* upl = um + up x s: d/d up -> s x l ; d/d s -> l x up */
+    for (int a = 0; a < 3; ++a) lum[a] = lupl[a];
+    lupv[0] = s[1] * lupl[2] - s[2] * lupl[1];
+    lupv[1] = s[2] * lupl[0] - s[0] * lupl[2];
+    lupv[2] = s[0] * lupl[1] - s[1] * lupl[0];
+    ls[0] = lupl[1] * up[2] - lupl[2] * up[1];
+    ls[1] = lupl[2] * up[0] - lupl[0] * up[2];
+    ls[2] = lupl[0] * up[1] - lupl[1] * up[0];
+    /* up = um + um x t: d/d um -> l + t x l ; d/d t -> l x um */
+    lum[0] += lupv[0] + (t[1] * lupv[2] - t[2] * lupv[1]);
+    lum[1] += lupv[1] + (t[2] * lupv[0] - t[0] * lupv[2]);
+    lum[2] += lupv[2] + (t[0] * lupv[1] - t[1] * lupv[0]);
+    lt[0] = lupv[1] * um[2] - lupv[2] * um[1];
+    lt[1] = lupv[2] * um[0] - lupv[0] * um[2];
+    lt[2] = lupv[0] * um[1] - lupv[1] * um[0];
+    /* s = 2 t / (1 + t.t) */
+    const double den = 1.0 + tt;
+    const double tls = t[0] * ls[0] + t[1] * ls[1] + t[2] * ls[2];
+    for (int a = 0; a < 3; ++a) lt[a] += 2.0 * ls[a] / den - 4.0 * t[a] * tls / (den * den);
+    /* t = r B / gm */
+    double tlt = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        lB[a] = r * lt[a] / gm;
+        tlt += t[a] * lt[a];
+    }
+    const double lgm = -tlt / gm;
+    /* gm = sqrt(1 + um.um) */
+    for (int a = 0; a < 3; ++a) lum[a] += lgm * um[a] / gm;
+    /* um = u + r E */
+    for (int a = 0; a < 3; ++a) {
+        lu[a] = lum[a];
+        lE[a] += r * lum[a];
+    }
+}
+
+/* gather adjoint for one component: scatter l * weights into lF and return */
+/* the derivative of the interpolated value along xi (cell units) times l  */
+static void gather_one_vjp(const orc_grid *g, const double *F, double *lF, const int stag[3],
+                           const double xi[3], double l, double dxi[3]) {
+    int64_t i0[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        const double t = xi[a] - 0.5 * stag[a];
+        const double fl = floor(t);
+        i0[a] = (int64_t)fl;
+        f[a] = t - fl;
+    }
+    for (int oz = 0; oz < 2; ++oz)
+        for (int oy = 0; oy < 2; ++oy)
+            for (int ox = 0; ox < 2; ++ox) {
+                const int64_t ip = at(g, i0[0] + ox, i0[1] + oy, i0[2] + oz);
+                const double wx = ox ? f[0] : 1.0 - f[0], wy = oy ? f[1] : 1.0 - f[1],
+                             wz = oz ? f[2] : 1.0 - f[2];
+                lF[ip] += l * wx * wy * wz;
+                const double v = l * F[ip];
+                dxi[0] += v * (ox ? 1.0 : -1.0) * wy * wz;
+                dxi[1] += v * wx * (oy ? 1.0 : -1.0) * wz;
+                dxi[2] += v * wx * wy * (oz ? 1.0 : -1.0);
+            }
+}
+
+/* adjoint of deposit_segment: d/d s and d/d e of sum_edges lJ . J_seg */
+static void deposit_segment_vjp(const orc_grid *g, const double *lJ, const int64_t cell[3],
+                                const double s[3], const double e[3], double qsp, double ls[3],
+                                double le[3]) {
+    const double dV = g->d[0] * g->d[1] * g->d[2];
+    const int64_t V = vol_of(g);
+    double dxi[3], W[3], lD[3] = {0, 0, 0}, lW[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        dxi[a] = e[a] - s[a];
+        W[a] = 0.5 * (s[a] + e[a]) - (double)cell[a];
+    }
+    for (int c = 0; c < 3; ++c) {
+        const int b1 = (c + 1) % 3, b2 = (c + 2) % 3;
+        const double ampc = qsp * g->d[c] / (g->dt * dV); /* J = ampc * dxi_c * weight */
+        for (int o2 = 0; o2 < 2; ++o2)
+            for (int o1 = 0; o1 < 2; ++o1) {
+                int64_t p[3] = {cell[0], cell[1], cell[2]};
+                p[b1] += o1;
+                p[b2] += o2;
+                const double lam = lJ[c * V + at(g, p[0], p[1], p[2])];
+                const double w1 = o1 ? W[b1] : 1.0 - W[b1];
+                const double w2 = o2 ? W[b2] : 1.0 - W[b2];
+                const double sg = (o1 == o2) ? 1.0 : -1.0;
+                const double weight = w1 * w2 + sg * dxi[b1] * dxi[b2] / 12.0;
+                lD[c] += lam * ampc * weight;
+                const double k = lam * ampc * dxi[c];
+                lW[b1] += k * (o1 ? 1.0 : -1.0) * w2;
+                lW[b2] += k * w1 * (o2 ? 1.0 : -1.0);
+                lD[b1] += k * sg * dxi[b2] / 12.0;
+                lD[b2] += k * sg * dxi[b1] / 12.0;
+            }
+    }
+    for (int a = 0; a < 3; ++a) {
+        ls[a] += -lD[a] + 0.5 * lW[a];
+        le[a] += lD[a] + 0.5 * lW[a];
+    }
+}
+
+static void zigzag_vjp(const orc_grid *g, const double *lJ, const double xi1[3],
+                       const double xi2[3], double qsp, double l1[3], double l2[3]) {
+    int64_t c1[3], c2[3];
+    double xr[3], dr1[3], dr2[3];
+    for (int a = 0; a < 3; ++a) {
+        const int64_t i1 = (int64_t)floor(xi1[a]);
+        const int64_t i2 = (int64_t)floor(xi2[a]);
+        const double lo = (double)((i1 < i2 ? i1 : i2) + 1);
+        const double hi = (double)(i1 > i2 ? i1 : i2);
+        const double mid = 0.5 * (xi1[a] + xi2[a]);
+        xr[a] = fmin(lo, fmax(hi, mid));
+        /* relay point: mid-point (both derivatives 1/2) unless clamped to a face */
+        const int is_mid = (mid >= hi) && (mid <= lo);
+        dr1[a] = is_mid ? 0.5 : 0.0;
+        dr2[a] = is_mid ? 0.5 : 0.0;
+        c1[a] = i1;
+        c2[a] = i2;
+    }
+    double lsA[3] = {0, 0, 0}, leA[3] = {0, 0, 0}, lsB[3] = {0, 0, 0}, leB[3] = {0, 0, 0};
+    deposit_segment_vjp(g, lJ, c1, xi1, xr, qsp, lsA, leA);
+    deposit_segment_vjp(g, lJ, c2, xr, xi2, qsp, lsB, leB);
+    for (int a = 0; a < 3; ++a) {
+        const double lr = leA[a] + lsB[a];
+        l1[a] += lsA[a] + lr * dr1[a];
+        l2[a] += leB[a] + lr * dr2[a];
+    }
+}
+
+/* Cf^T = Cb: out += scale * curl_b(F) (F B-located, out E-located) and
+ * out += scale * curl_f(F) (F E-located, out B-located), periodic.          */
+static void curl_b_add(const orc_grid *g, const double *F, double *out, double scale) {
+    const int64_t V = vol_of(g);
+    double *Z = (double *)calloc(3 * V, sizeof(double));
+    orc_ampere(g, Z, F, NULL); /* Z = dt curl_b(F) */
+    for (int64_t i = 0; i < 3 * V; ++i) out[i] += scale * Z[i] / g->dt;
+    free(Z);
+}
+static void curl_f_add(const orc_grid *g, const double *F, double *out, double scale) {
+    const int64_t V = vol_of(g);
+    double *Z = (double *)calloc(3 * V, sizeof(double));
+    orc_faraday(g, F, Z, NULL); /* Z = -dt curl_f(F) */
+    for (int64_t i = 0; i < 3 * V; ++i) out[i] -= scale * Z[i] / g->dt;
+    free(Z);
+}
+
+/* One species' particle adjoint.  pos/u: state at n (x^n, u^{n-1/2});
+ * lx/lu in: adjoints of x^{n+1}, u^{n+1/2}; out: of x^n, u^{n-1/2}.
+ * lJ = -dt * (adjoint of E^{n+1}); accumulates into lE (adjoint of E^n
+ * through the gather) and lBbar.                                            */
+void orc_particles_vjp(const orc_grid *g, const double *E, const double *Bbar, const double *lJ,
+                       int64_t np, const double *pos, const double *u, const double *wpp,
+                       double q, double m, double w, double *lx, double *lu, double *lE,
+                       double *lBbar) {
+    const int64_t V = vol_of(g);
+    const double r = q * g->dt / (2.0 * m);
+    for (int64_t p = 0; p < np; ++p) {
+        const double wp = wpp ? wpp[p] : w;
+        double xi1[3], Ep[3], Bp[3], un[3];
+        for (int a = 0; a < 3; ++a) xi1[a] = pos[3 * p + a] / g->d[a];
+        orc_gather(g, E, Bbar, pos + 3 * p, Ep, Bp);
+        for (int a = 0; a < 3; ++a) un[a] = u[3 * p + a];
+        orc_boris(un, Ep, Bp, r);
+        const double uu = un[0] * un[0] + un[1] * un[1] + un[2] * un[2];
+        const double gm = sqrt(1.0 + uu);
+        double xi2[3];
+        for (int a = 0; a < 3; ++a) xi2[a] = xi1[a] + g->dt * un[a] / (gm * g->d[a]);
+        /* deposit adjoint */
+        double l1[3] = {0, 0, 0}, l2[3] = {0, 0, 0};
+        zigzag_vjp(g, lJ, xi1, xi2, q * wp, l1, l2);
+        /* x' = x + dt v'; xi2 = x/d + dt v'/d; xi1 = x/d */
+        double lxn[3], lv[3];
+        for (int a = 0; a < 3; ++a) {
+            lxn[a] = lx[3 * p + a] + l1[a] / g->d[a] + l2[a] / g->d[a];
+            lv[a] = g->dt * (lx[3 * p + a] + l2[a] / g->d[a]);
+        }
+        /* v' = u'/gamma': d/du' = I/g - u' u'^T / g^3 */
+        const double uv = un[0] * lv[0] + un[1] * lv[1] + un[2] * lv[2];
+        double lup[3];
+        for (int a = 0; a < 3; ++a)
+            lup[a] = lu[3 * p + a] + lv[a] / gm - un[a] * uv / (gm * gm * gm);
+        double lu0[3], lEp[3], lBp[3];
+        boris_vjp(u + 3 * p, Ep, Bp, r, lup, lu0, lEp, lBp);
+        /* gather adjoint */
+        double dxi[3] = {0, 0, 0};
+        for (int c = 0; c < 3; ++c) {
+            int se[3], sb[3];
+            for (int a = 0; a < 3; ++a) {
+                se[a] = stag_E(c, a);
+                sb[a] = stag_B(c, a);
+            }
+            gather_one_vjp(g, E + c * V, lE + c * V, se, xi1, lEp[c], dxi);
+            gather_one_vjp(g, Bbar + c * V, lBbar + c * V, sb, xi1, lBp[c], dxi);
+        }
+        for (int a = 0; a < 3; ++a) {
+            lx[3 * p + a] = lxn[a] + dxi[a] / g->d[a];
+            lu[3 * p + a] = lu0[a];
+        }
+    }
+}
+
+/* Field part of the step adjoint.  lE, lB in: adjoints of E^{n+1}, B^{n+1/2};
+ * lE_gather, lBbar: accumulated by orc_particles_vjp.  Out (in place):
+ * adjoints of E^n, B^{n-1/2}.                                               */
+void orc_fields_vjp(const orc_grid *g, double *lE, double *lB, const double *lE_gather,
+                    const double *lBbar) {
+    const int64_t V = vol_of(g);
+    double *lBt = (double *)malloc(sizeof(double) * 3 * V);
+    /* lB' = lB + dt Cb^T lE' + lBbar/2 = lB + dt Cf(lE') + lBbar/2 */
+    for (int64_t i = 0; i < 3 * V; ++i) lBt[i] = lB[i] + 0.5 * lBbar[i];
+    curl_f_add(g, lE, lBt, g->dt);
+    /* lB = lB' + lBbar/2 ; lE = lE' + lE_gather - dt Cf^T lB' = ... - dt Cb(lB') */
+    for (int64_t i = 0; i < 3 * V; ++i) {
+        lB[i] = lBt[i] + 0.5 * lBbar[i];
+        lE[i] += lE_gather[i];
+    }
+    curl_b_add(g, lBt, lE, -g->dt);
+    free(lBt);
+}

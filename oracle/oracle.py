@@ -72,6 +72,9 @@ def lib():
     L.orc_energy_B.restype = C.c_double
     L.orc_kinetic.argtypes = [C.c_int64, _D, _I8, _D, C.c_double, C.c_double]
     L.orc_kinetic.restype = C.c_double
+    L.orc_particles_vjp.argtypes = [G, _D, _D, _D, C.c_int64, _D, _D, _D, C.c_double, C.c_double,
+                                    C.c_double, _D, _D, _D, _D]
+    L.orc_fields_vjp.argtypes = [G, _D, _D, _D, _D]
     _lib = L
     return L
 
@@ -174,6 +177,48 @@ class OracleSim:
             if absorbing:
                 L.orc_mur(g, _p(self.E), _p(E_old))
             self.nstep += 1
+
+    # -- adjoint of one step (periodic grids) ----------------------------------
+    def step_vjp(self, lamE, lamB, lamX, lamU):
+        """Vector-Jacobian product of one step taken from the current state.
+
+        lamE, lamB: adjoints of E^{n+1}, B^{n+1/2}; lamX[s], lamU[s]: adjoints
+        of x^{n+1}, u^{n+1/2} of species s ((N,3) arrays).  Returns the adjoints
+        of E^n, B^{n-1/2}, x^n, u^{n-1/2}.  The state is not changed.
+        """
+        assert all(b == PERIODIC for b in self.bc), "adjoint needs a periodic grid"
+        L = lib()
+        g = C.byref(self.g)
+        Bh = self.B.copy()
+        Bbar = np.zeros_like(self.B)
+        L.orc_faraday(g, _p(self.E), _p(Bh), _p(Bbar))
+        lJ = np.ascontiguousarray(-self.dt * lamE)
+        lE = np.ascontiguousarray(lamE, dtype=np.float64).copy()
+        lB = np.ascontiguousarray(lamB, dtype=np.float64).copy()
+        lEg = np.zeros_like(lE)
+        lBbar = np.zeros_like(lB)
+        outX, outU = [], []
+        for s, lx, lu in zip(self.species, lamX, lamU):
+            lx = np.ascontiguousarray(lx, dtype=np.float64).copy()
+            lu = np.ascontiguousarray(lu, dtype=np.float64).copy()
+            L.orc_particles_vjp(g, _p(self.E), _p(Bbar), _p(lJ), s.np, _p(s.pos), _p(s.u),
+                                _p(s.wpp), s.q, s.m, s.w, _p(lx), _p(lu), _p(lEg), _p(lBbar))
+            outX.append(lx)
+            outU.append(lu)
+        L.orc_fields_vjp(g, _p(lE), _p(lB), _p(lEg), _p(lBbar))
+        return lE, lB, outX, outU
+
+    def state(self):
+        return (self.E.copy(), self.B.copy(), [s.pos.copy() for s in self.species],
+                [s.u.copy() for s in self.species])
+
+    def set_state(self, st):
+        E, B, X, U = st
+        self.E[...] = E
+        self.B[...] = B
+        for s, x, u in zip(self.species, X, U):
+            s.pos[...] = x
+            s.u[...] = u
 
     # -- moments and diagnostics ---------------------------------------------
     def rho(self, species=None, with_background=False):
