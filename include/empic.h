@@ -230,6 +230,40 @@ empic_status empic_kernel_times(empic_sim *s, double *push_ms, int64_t *push_lau
                                 double *field_ms, int64_t *field_launches,
                                 double *sort_ms, int64_t *sort_launches);
 
+/* ---- Differentiable runs (FP32 path, periodic grid) ------------------------
+ * Not in the paper: the adjoint of the step, for gradients of a loss of the
+ * final fields or particles with respect to the initial state.  A state is
+ * E^n, B^{n-1/2} and, per species, cell, in-cell offsets and u^{n-1/2}, in the
+ * current storage order (arrays of the species' capacity).  An adjoint holds
+ * d(loss)/d(state): fields like E and B, positions per unit length (global
+ * coordinates), momenta.  All FP32 device arrays owned by the caller. */
+typedef struct {
+    void *E[3], *B[3];
+    int32_t *cell[EMPIC_MAX_SPECIES];
+    void *pos[EMPIC_MAX_SPECIES][3];
+    void *u[EMPIC_MAX_SPECIES][3];
+} empic_state;
+
+typedef struct {
+    void *E[3], *B[3];
+    void *pos[EMPIC_MAX_SPECIES][3];
+    void *u[EMPIC_MAX_SPECIES][3];
+} empic_adjoint;
+
+/* Copy the current state into dst / set the current state from src (device
+ * copies on the handle's stream).  A state loaded back must come from this
+ * handle with no sort in between (same storage order and counts). */
+empic_status empic_save_state(empic_sim *s, const empic_state *dst);
+empic_status empic_load_state(empic_sim *s, const empic_state *src);
+
+/* Vector-Jacobian product of one step taken from state st: lam holds the
+ * adjoint of the state after the step on entry and that of st on return
+ * (in place).  Transposed curls for the fields, deposit-as-gather of -dt
+ * lam_E, reverse Boris, gather-as-scatter (float atomics).  Derivatives are
+ * those of the current piece of each piecewise map.  EMPIC_E_UNSUPPORTED for
+ * the FP64 path or a non-periodic grid. */
+empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adjoint *lam);
+
 /* Cells per tile of the FP32 path's sort order and fused kernel (x, y, z):
  * particles are stored tile by tile (tiles x-fastest), cell by cell inside a
  * tile (x-fastest).  Host-only; needs no handle. */

@@ -50,6 +50,16 @@ class Diag(C.Structure):
                 ("n_particles", C.c_int64 * MAX_SPECIES), ("fallback_particles", C.c_int64)]
 
 
+class State(C.Structure):
+    _fields_ = [("E", C.c_void_p * 3), ("B", C.c_void_p * 3), ("cell", C.c_void_p * MAX_SPECIES),
+                ("pos", (C.c_void_p * 3) * MAX_SPECIES), ("u", (C.c_void_p * 3) * MAX_SPECIES)]
+
+
+class Adjoint(C.Structure):
+    _fields_ = [("E", C.c_void_p * 3), ("B", C.c_void_p * 3),
+                ("pos", (C.c_void_p * 3) * MAX_SPECIES), ("u", (C.c_void_p * 3) * MAX_SPECIES)]
+
+
 class EmpicError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (STATUS.get(status, status), msg))
@@ -81,6 +91,9 @@ SIGNATURES = {
     "empic_kernel_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "empic_save_state": (C.c_int, [_P, C.POINTER(State)]),
+    "empic_load_state": (C.c_int, [_P, C.POINTER(State)]),
+    "empic_step_vjp": (C.c_int, [_P, C.POINTER(State), C.POINTER(Adjoint)]),
     "empic_tile_shape": (None, [C.POINTER(C.c_int32)]),
     "empic_last_error": (C.c_char_p, [_P]),
     "empic_destroy": (None, [_P]),

@@ -23,7 +23,7 @@ inline size_t up_align(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t Bbar, fault, table, partials, result, rho_cur, rho_prev, tile_off, counts, scan, rank,
-        fb_list, mur, total;
+        fb_list, adj, mur, total;
     size_t tile_off_stride;
     long long mur_stride;
 };
@@ -75,6 +75,8 @@ Layout layout(const empic_grid_desc *d, int max_species, long long max_capacity)
     o += up_align((size_t)max_capacity * 4);
     L.fb_list = o;  // out-of-window list: every slot of every species fits
     o += up_align((size_t)max_capacity * max_species * 8);
+    L.adj = o;      // adjoint accumulators (FP32 path): gather lam_E, lam_Bbar, lam_B'
+    o += d->precision == EMPIC_FP64_PLAIN ? 0 : up_align((size_t)9 * g.V * 4);
     long long ps = 0;
     for (int a = 0; a < 3; ++a) {
         const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
@@ -125,6 +127,7 @@ struct empic_sim {
     void *mur = nullptr;
     int2 *fb_list = nullptr;
     unsigned *fb_count = nullptr;
+    float *adj = nullptr;
     void *E[3]{}, *B[3]{}, *J[3]{};
     bool bound = false;
     SpeciesState sp[EMPIC_MAX_SPECIES];
@@ -384,6 +387,7 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
     s->rank = (int32_t *)(s->ws + L.rank);
     s->mur = s->ws + L.mur;
     s->fb_list = (int2 *)(s->ws + L.fb_list);
+    s->adj = (float *)(s->ws + L.adj);
     s->fb_count = (unsigned *)(s->ws + L.fault + 16);
     s->max_species = max_species;
     s->max_capacity = max_capacity;
@@ -718,6 +722,90 @@ empic_status empic_kernel_times(empic_sim *s, double *push_ms, int64_t *push_lau
         s->t_n[k] = 0;
     }
     return EMPIC_OK;
+}
+
+static empic_status copy_state(empic_sim *s, const empic_state *st, bool save) {
+    const size_t fb = (size_t)s->g.V * 4;
+    for (int a = 0; a < 3; ++a) {
+        if (!st->E[a] || !st->B[a]) return fail(s, EMPIC_E_ARG, "null state field");
+        EMPIC_HIP(hipMemcpyAsync(save ? st->E[a] : s->E[a], save ? s->E[a] : st->E[a], fb,
+                                 hipMemcpyDeviceToDevice, s->stream));
+        EMPIC_HIP(hipMemcpyAsync(save ? st->B[a] : s->B[a], save ? s->B[a] : st->B[a], fb,
+                                 hipMemcpyDeviceToDevice, s->stream));
+    }
+    for (int i = 0; i < s->nsp; ++i) {
+        const SpeciesState &S = s->sp[i];
+        const empic_particle_buffers &b = S.buf[S.cur];
+        const size_t pb = (size_t)S.capacity * 4;
+        if (pb == 0) continue;
+        if (!st->cell[i]) return fail(s, EMPIC_E_ARG, "null state cell array");
+        EMPIC_HIP(hipMemcpyAsync(save ? (void *)st->cell[i] : (void *)b.cell,
+                                 save ? (void *)b.cell : (void *)st->cell[i], pb,
+                                 hipMemcpyDeviceToDevice, s->stream));
+        for (int a = 0; a < 3; ++a) {
+            if (!st->pos[i][a] || !st->u[i][a]) return fail(s, EMPIC_E_ARG, "null state array");
+            EMPIC_HIP(hipMemcpyAsync(save ? st->pos[i][a] : b.pos[a], save ? b.pos[a] : st->pos[i][a],
+                                     pb, hipMemcpyDeviceToDevice, s->stream));
+            EMPIC_HIP(hipMemcpyAsync(save ? st->u[i][a] : b.u[a], save ? b.u[a] : st->u[i][a], pb,
+                                     hipMemcpyDeviceToDevice, s->stream));
+        }
+    }
+    return EMPIC_OK;
+}
+
+empic_status empic_save_state(empic_sim *s, const empic_state *dst) {
+    EMPIC_GUARD(s);
+    if (!dst || !s->bound) return fail(s, EMPIC_E_ARG, "null state or fields not bound");
+    if (fp64(s)) return fail(s, EMPIC_E_UNSUPPORTED, "states are for the FP32 path");
+    return copy_state(s, dst, true);
+}
+
+empic_status empic_load_state(empic_sim *s, const empic_state *src) {
+    EMPIC_GUARD(s);
+    if (!src || !s->bound) return fail(s, EMPIC_E_ARG, "null state or fields not bound");
+    if (fp64(s)) return fail(s, EMPIC_E_UNSUPPORTED, "states are for the FP32 path");
+    s->rho_prev_step = -1;
+    return copy_state(s, src, false);
+}
+
+empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adjoint *lam) {
+    EMPIC_GUARD(s);
+    if (!st || !lam || !s->bound) return fail(s, EMPIC_E_ARG, "null state or adjoint");
+    if (fp64(s) || s->g.bc[0] || s->g.bc[1] || s->g.bc[2])
+        return fail(s, EMPIC_E_UNSUPPORTED, "the adjoint needs the FP32 path on a periodic grid");
+    float *E[3], *B[3], *Bb[3], *lE[3], *lB[3], *lEg[3], *lBb[3], *tB[3];
+    for (int a = 0; a < 3; ++a) {
+        E[a] = (float *)st->E[a];
+        B[a] = (float *)st->B[a];
+        Bb[a] = (float *)s->Bbar[a];
+        lE[a] = (float *)lam->E[a];
+        lB[a] = (float *)lam->B[a];
+        lEg[a] = s->adj + (size_t)a * s->g.V;
+        lBb[a] = s->adj + (size_t)(3 + a) * s->g.V;
+        tB[a] = s->adj + (size_t)(6 + a) * s->g.V;
+        if (!E[a] || !B[a] || !lE[a] || !lB[a]) return fail(s, EMPIC_E_ARG, "null field array");
+    }
+    // centred B of the state
+    launch_faraday<float>(s->g, E, B, Bb, nullptr, false, s->stream);
+    SpeciesP sp[EMPIC_MAX_SPECIES];
+    float *lx[EMPIC_MAX_SPECIES][3], *lu[EMPIC_MAX_SPECIES][3];
+    for (int i = 0; i < s->nsp; ++i) {
+        sp[i] = species_params(s, i, s->sp[i].cur);
+        if (s->sp[i].capacity > 0) {
+            if (!st->cell[i]) return fail(s, EMPIC_E_ARG, "null state cell array");
+            sp[i].cell = (uint32_t *)st->cell[i];
+        }
+        for (int a = 0; a < 3; ++a) {
+            sp[i].pos[a] = st->pos[i][a];
+            sp[i].u[a] = st->u[i][a];
+            lx[i][a] = (float *)lam->pos[i][a];
+            lu[i][a] = (float *)lam->u[i][a];
+            if (s->sp[i].capacity > 0 && (!sp[i].pos[a] || !sp[i].u[a] || !lx[i][a] || !lu[i][a]))
+                return fail(s, EMPIC_E_ARG, "null particle array in state or adjoint");
+        }
+    }
+    launch_step_vjp(s->g, E, Bb, lE, lB, lEg, lBb, tB, sp, lx, lu, s->nsp, s->stream);
+    return check_launch(s, "step_vjp");
 }
 
 void empic_tile_shape(int32_t out[3]) {

@@ -192,6 +192,12 @@ void launch_load_f64(const GridP &g, const SpeciesP &sp, long long count, const 
 void launch_store_f64(const SpeciesP &sp, long long count, double *pos, double *u, int32_t *ids,
                       hipStream_t s);
 
+// adjoint of one FP32 step (periodic)
+void launch_step_vjp(const GridP &g, float *const E[3], float *const Bbar[3],
+                     float *const lE[3], float *const lB[3], float *const lEg[3],
+                     float *const lBb[3], float *const tB[3], const SpeciesP *sp,
+                     float *const (*lx)[3], float *const (*lu)[3], int nsp, hipStream_t s);
+
 // diagnostics
 void launch_zero_f64(double *p, long long n, hipStream_t s);
 template <typename T>

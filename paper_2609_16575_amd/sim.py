@@ -199,6 +199,69 @@ class Sim:
         LB.check(self.h, self.L.empic_particle_count(self.h, sp, C.byref(n)))
         return n.value
 
+    # -- differentiable runs (FP32 path, periodic grid) ----------------------------
+    def alloc_state(self):
+        """Device tensors for one saved state (fields + current particle layout)."""
+        t = self.torch
+        st = {"E": t.empty_like(self.E), "B": t.empty_like(self.B), "cell": [], "pos": [], "u": []}
+        for cap in self.caps:
+            st["cell"].append(t.empty(cap, dtype=t.int32, device=self.dev))
+            st["pos"].append(t.empty((3, cap), dtype=self.dtype, device=self.dev))
+            st["u"].append(t.empty((3, cap), dtype=self.dtype, device=self.dev))
+        return st
+
+    def alloc_adjoint(self):
+        t = self.torch
+        lam = {"E": t.zeros_like(self.E), "B": t.zeros_like(self.B), "pos": [], "u": []}
+        for cap in self.caps:
+            lam["pos"].append(t.zeros((3, cap), dtype=self.dtype, device=self.dev))
+            lam["u"].append(t.zeros((3, cap), dtype=self.dtype, device=self.dev))
+        return lam
+
+    def _state_struct(self, st):
+        S = LB.State()
+        for a in range(3):
+            S.E[a] = _ptr(st["E"][a])
+            S.B[a] = _ptr(st["B"][a])
+        for i in range(len(self.caps)):
+            S.cell[i] = _ptr(st["cell"][i])
+            for a in range(3):
+                S.pos[i][a] = _ptr(st["pos"][i][a])
+                S.u[i][a] = _ptr(st["u"][i][a])
+        return S
+
+    def _adjoint_struct(self, lam):
+        A = LB.Adjoint()
+        for a in range(3):
+            A.E[a] = _ptr(lam["E"][a])
+            A.B[a] = _ptr(lam["B"][a])
+        for i in range(len(self.caps)):
+            for a in range(3):
+                A.pos[i][a] = _ptr(lam["pos"][i][a])
+                A.u[i][a] = _ptr(lam["u"][i][a])
+        return A
+
+    def save_state(self, st=None):
+        st = self.alloc_state() if st is None else st
+        S = self._state_struct(st)
+        LB.check(self.h, self.L.empic_save_state(self.h, C.byref(S)))
+        return st
+
+    def load_state(self, st):
+        S = self._state_struct(st)
+        LB.check(self.h, self.L.empic_load_state(self.h, C.byref(S)))
+
+    def step_vjp(self, st, lam):
+        """In place: lam (adjoint after the step taken from st) -> adjoint of st."""
+        S, A = self._state_struct(st), self._adjoint_struct(lam)
+        LB.check(self.h, self.L.empic_step_vjp(self.h, C.byref(S), C.byref(A)))
+
+    def current_buffers(self, sp):
+        """Tensors of species sp's current buffer set (storage order)."""
+        w = C.c_int32()
+        LB.check(self.h, self.L.empic_current_buffer(self.h, sp, C.byref(w)))
+        return self.bufs[sp][w.value]
+
     def enable_timing(self, on=True):
         LB.check(self.h, self.L.empic_enable_timing(self.h, 1 if on else 0))
 
