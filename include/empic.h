@@ -233,15 +233,21 @@ empic_status empic_kernel_times(empic_sim *s, double *push_ms, int64_t *push_lau
 /* ---- Differentiable runs (FP32 path, periodic grid) ------------------------
  * Not in the paper: the adjoint of the step, for gradients of a loss of the
  * final fields or particles with respect to the initial state.  A state is
- * E^n, B^{n-1/2} and, per species, cell, in-cell offsets and u^{n-1/2}, in the
- * current storage order (arrays of the species' capacity).  An adjoint holds
+ * everything a step reads: E^n, B^{n-1/2} and, per species, the particle
+ * record in the current storage order (cell, in-cell offsets, u^{n-1/2}, id,
+ * per-particle weight; arrays of the species' capacity) plus its tile
+ * offsets and slot count (empic_state_tile_words int32).  An adjoint holds
  * d(loss)/d(state): fields like E and B, positions per unit length (global
- * coordinates), momenta.  All FP32 device arrays owned by the caller. */
+ * coordinates), momenta.  All device arrays, owned by the caller, FP32 for
+ * floating point. */
 typedef struct {
     void *E[3], *B[3];
     int32_t *cell[EMPIC_MAX_SPECIES];
     void *pos[EMPIC_MAX_SPECIES][3];
     void *u[EMPIC_MAX_SPECIES][3];
+    int32_t *id[EMPIC_MAX_SPECIES];
+    void *w[EMPIC_MAX_SPECIES];        /* NULL for species without per-particle w */
+    int32_t *tiles[EMPIC_MAX_SPECIES];
 } empic_state;
 
 typedef struct {
@@ -250,9 +256,13 @@ typedef struct {
     void *u[EMPIC_MAX_SPECIES][3];
 } empic_adjoint;
 
+/* int32 words of a state's tiles[] array per species (tile count + 2). */
+empic_status empic_state_tile_words(empic_sim *s, int64_t *words);
+
 /* Copy the current state into dst / set the current state from src (device
- * copies on the handle's stream).  A state loaded back must come from this
- * handle with no sort in between (same storage order and counts). */
+ * copies on the handle's stream).  Saving needs particles that have been
+ * sorted since they were loaded (EMPIC_E_ARG otherwise); a loaded state
+ * must come from this handle. */
 empic_status empic_save_state(empic_sim *s, const empic_state *dst);
 empic_status empic_load_state(empic_sim *s, const empic_state *src);
 
@@ -263,6 +273,20 @@ empic_status empic_load_state(empic_sim *s, const empic_state *src);
  * those of the current piece of each piecewise map.  EMPIC_E_UNSUPPORTED for
  * the FP64 path or a non-periodic grid. */
 empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adjoint *lam);
+
+/* empic_sort that also writes, per species, perm[i][j] = the slot before the
+ * sort of the particle in slot j after it (-1 for slots past the new count);
+ * perm[i] holds the species' capacity of int32 (device).  For sorts inside a
+ * differentiable run. */
+empic_status empic_sort_recorded(empic_sim *s, int32_t *const perm[EMPIC_MAX_SPECIES]);
+
+/* Adjoint of a recorded sort, in place on lam's particle arrays: moves each
+ * slot's position and momentum adjoints back to the slot before the sort;
+ * slots no particle came from (removed particles) get zero.  Entries of perm
+ * outside [0, capacity) are ignored.  Uses the species' second buffer set as
+ * scratch, whose contents no step reads between sorts. */
+empic_status empic_sort_vjp(empic_sim *s, int32_t *const perm[EMPIC_MAX_SPECIES],
+                            const empic_adjoint *lam);
 
 /* Cells per tile of the FP32 path's sort order and fused kernel (x, y, z):
  * particles are stored tile by tile (tiles x-fastest), cell by cell inside a

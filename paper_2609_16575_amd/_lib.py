@@ -52,7 +52,9 @@ class Diag(C.Structure):
 
 class State(C.Structure):
     _fields_ = [("E", C.c_void_p * 3), ("B", C.c_void_p * 3), ("cell", C.c_void_p * MAX_SPECIES),
-                ("pos", (C.c_void_p * 3) * MAX_SPECIES), ("u", (C.c_void_p * 3) * MAX_SPECIES)]
+                ("pos", (C.c_void_p * 3) * MAX_SPECIES), ("u", (C.c_void_p * 3) * MAX_SPECIES),
+                ("id", C.c_void_p * MAX_SPECIES), ("w", C.c_void_p * MAX_SPECIES),
+                ("tiles", C.c_void_p * MAX_SPECIES)]
 
 
 class Adjoint(C.Structure):
@@ -94,6 +96,9 @@ SIGNATURES = {
     "empic_save_state": (C.c_int, [_P, C.POINTER(State)]),
     "empic_load_state": (C.c_int, [_P, C.POINTER(State)]),
     "empic_step_vjp": (C.c_int, [_P, C.POINTER(State), C.POINTER(Adjoint)]),
+    "empic_state_tile_words": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "empic_sort_recorded": (C.c_int, [_P, C.c_void_p * MAX_SPECIES]),
+    "empic_sort_vjp": (C.c_int, [_P, C.c_void_p * MAX_SPECIES, C.POINTER(Adjoint)]),
     "empic_tile_shape": (None, [C.POINTER(C.c_int32)]),
     "empic_last_error": (C.c_char_p, [_P]),
     "empic_destroy": (None, [_P]),

@@ -1,12 +1,16 @@
 """Differentiable PIC runs: a torch.autograd.Function over the C ABI.
 
-Forward: nsteps steps of a Sim (FP32 path, periodic grid, no sort inside the
-run) from initial fields E0, B0 and initial momenta U0 (one (3, capacity)
-tensor per species, storage order), saving the full state every K steps.
+Forward: nsteps steps of a Sim (FP32 path, periodic grid) from initial fields
+E0, B0 and initial momenta U0 (one (3, capacity) tensor per species, in the
+storage order at the call), saving the full state every K steps.  With
+sort=True the particles are also sorted (recording the permutation) at every
+checkpoint, which is the counting sort every K steps of a long run; the
+Sim's own periodic sort must then be off (sort_every=0).
 Backward: for each checkpoint segment, from the last: reload its state,
-recompute the segment's states, then apply the step adjoint
-(empic_step_vjp) backwards through them.  Memory: one saved state per K
-steps plus K states of the segment being reversed.
+recompute the segment's states, apply the step adjoint (empic_step_vjp)
+backwards through them, then the adjoint of the segment's sort.  Memory: one
+saved state (and permutation) per K steps plus K states of the segment being
+reversed.  The Sim holds a recomputed state afterwards, not the final one.
 """
 from __future__ import annotations
 
@@ -15,20 +19,31 @@ import torch
 
 class PicRun(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sim, nsteps, K, E0, B0, *U0):
+    def forward(ctx, sim, nsteps, K, sort, E0, B0, *U0):
         if sim.fp64:
             raise ValueError("differentiable runs use the FP32 path")
+        if sim.sort_every != 0:
+            raise ValueError("create the Sim with sort_every=0: a differentiable run sorts "
+                             "at its checkpoints (sort=True)")
+        if K < 1:
+            raise ValueError("checkpoint interval K must be >= 1")
         with torch.no_grad():
             sim.E.copy_(E0)
             sim.B.copy_(B0)
             for i, u in enumerate(U0):
                 sim.current_buffers(i)["u"].copy_(u)
-            ckpts = []
+            ckpts, perms = [], []
             for n in range(int(nsteps)):
                 if n % K == 0:
+                    perm = None
+                    if sort:
+                        perm = sim.alloc_perm()
+                        sim.sort_recorded(perm)
+                    perms.append(perm)
                     ckpts.append(sim.save_state())
                 sim.step(1)
-        ctx.sim, ctx.nsteps, ctx.K, ctx.ckpts = sim, int(nsteps), int(K), ckpts
+        ctx.sim, ctx.nsteps, ctx.K = sim, int(nsteps), int(K)
+        ctx.ckpts, ctx.perms = ckpts, perms
         return sim.E.clone(), sim.B.clone()
 
     @staticmethod
@@ -40,7 +55,8 @@ class PicRun(torch.autograd.Function):
                 lam["E"].copy_(gE)
             if gB is not None:
                 lam["B"].copy_(gB)
-            pool = [sim.alloc_state() for _ in range(K)]
+            # slot 0 of a segment is its checkpoint
+            pool = [None] + [sim.alloc_state() for _ in range(min(K, nsteps) - 1)]
             for seg in reversed(range(len(ctx.ckpts))):
                 start = seg * K
                 stop = min(start + K, nsteps)
@@ -51,10 +67,12 @@ class PicRun(torch.autograd.Function):
                     states.append(sim.save_state(pool[j]))
                 for st in reversed(states):
                     sim.step_vjp(st, lam)
-        ctx.ckpts = None
-        return (None, None, None, lam["E"], lam["B"], *lam["u"])
+                if ctx.perms[seg] is not None:
+                    sim.sort_vjp(ctx.perms[seg], lam)
+        ctx.ckpts = ctx.perms = None
+        return (None, None, None, None, lam["E"], lam["B"], *lam["u"])
 
 
-def run(sim, nsteps, K, E0, B0, U0):
+def run(sim, nsteps, K, E0, B0, U0, sort=False):
     """Differentiable (E_N, B_{N-1/2}) of `nsteps` steps from (E0, B0, U0)."""
-    return PicRun.apply(sim, nsteps, K, E0, B0, *U0)
+    return PicRun.apply(sim, nsteps, K, bool(sort), E0, B0, *U0)

@@ -348,6 +348,32 @@ __global__ void k_adj_e(GridP g, float *lEx, float *lEy, float *lEz, const float
     }
 }
 
+// a sort moves the particle in slot perm[j] to slot j; its adjoint moves the
+// slot adjoints back.  Pass 1 copies them aside and clears them, pass 2
+// writes each to the slot its particle came from.
+struct Lam6 {
+    float *p[6];
+};
+
+__global__ void k_sort_vjp_stash(Lam6 lam, Lam6 tmp, long long cap) {
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j >= cap) return;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+        tmp.p[a][j] = lam.p[a][j];
+        lam.p[a][j] = 0.f;
+    }
+}
+
+__global__ void k_sort_vjp_scatter(Lam6 lam, Lam6 tmp, const int32_t *perm, long long cap) {
+    const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (j >= cap) return;
+    const int32_t q = perm[j];
+    if (q < 0 || q >= cap) return;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) lam.p[a][q] = tmp.p[a][j];
+}
+
 __global__ void k_zero_f32(float *p, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
@@ -400,6 +426,20 @@ void launch_step_vjp(const GridP &g, float *const E[3], float *const Bbar[3],
                        lB[2], lBb[0], lBb[1], lBb[2], tB[0], tB[1], tB[2]);
     hipLaunchKernelGGL(k_adj_e, grid, dim3(64, 4), 0, s, g, lE[0], lE[1], lE[2], lEg[0], lEg[1],
                        lEg[2], tB[0], tB[1], tB[2]);
+}
+
+void launch_sort_vjp(const int32_t *perm, long long cap, float *const lx[3], float *const lu[3],
+                     float *const scratch[6], hipStream_t s) {
+    if (cap <= 0) return;
+    Lam6 lam, tmp;
+    for (int a = 0; a < 3; ++a) {
+        lam.p[a] = lx[a];
+        lam.p[3 + a] = lu[a];
+    }
+    for (int a = 0; a < 6; ++a) tmp.p[a] = scratch[a];
+    const unsigned nb = (unsigned)((cap + 255) / 256);
+    hipLaunchKernelGGL(k_sort_vjp_stash, dim3(nb), dim3(256), 0, s, lam, tmp, cap);
+    hipLaunchKernelGGL(k_sort_vjp_scatter, dim3(nb), dim3(256), 0, s, lam, tmp, perm, cap);
 }
 
 }  // namespace empic

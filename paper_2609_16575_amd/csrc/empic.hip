@@ -221,7 +221,7 @@ void field_ptrs(empic_sim *s, T *E[3], T *B[3], T *J[3], T *Bb[3]) {
     }
 }
 
-void do_sort(empic_sim *s) {
+void do_sort(empic_sim *s, int32_t *const *perm = nullptr) {
     TimedEvent t;
     ev_begin(s, t, 2);
     for (int i = 0; i < s->nsp; ++i) {
@@ -229,7 +229,7 @@ void do_sort(empic_sim *s) {
         const SpeciesP cur = species_params(s, i, S.cur);
         const SpeciesP alt = species_params(s, i, 1 - S.cur);
         launch_sort(s->g, s->ti, cur, alt, s->counts, s->scan_blocks, s->rank, S.tile_off,
-                    s->fault, S.tiles_valid, s->stream);
+                    s->fault, S.tiles_valid, perm ? perm[i] : nullptr, s->stream);
         S.cur = 1 - S.cur;
         S.tiles_valid = true;
     }
@@ -726,30 +726,46 @@ empic_status empic_kernel_times(empic_sim *s, double *push_ms, int64_t *push_lau
 
 static empic_status copy_state(empic_sim *s, const empic_state *st, bool save) {
     const size_t fb = (size_t)s->g.V * 4;
-    for (int a = 0; a < 3; ++a) {
+    auto cp = [&](void *state_arr, void *live, size_t n) {
+        return hipMemcpyAsync(save ? state_arr : live, save ? live : state_arr, n,
+                              hipMemcpyDeviceToDevice, s->stream);
+    };
+    for (int a = 0; a < 3; ++a)
         if (!st->E[a] || !st->B[a]) return fail(s, EMPIC_E_ARG, "null state field");
-        EMPIC_HIP(hipMemcpyAsync(save ? st->E[a] : s->E[a], save ? s->E[a] : st->E[a], fb,
-                                 hipMemcpyDeviceToDevice, s->stream));
-        EMPIC_HIP(hipMemcpyAsync(save ? st->B[a] : s->B[a], save ? s->B[a] : st->B[a], fb,
-                                 hipMemcpyDeviceToDevice, s->stream));
+    for (int i = 0; i < s->nsp; ++i) {
+        const SpeciesState &S = s->sp[i];
+        if (S.capacity == 0) continue;
+        bool ok = st->cell[i] && st->id[i] && st->tiles[i];
+        for (int a = 0; a < 3; ++a) ok = ok && st->pos[i][a] && st->u[i][a];
+        if (S.desc.per_particle_w) ok = ok && st->w[i];
+        if (!ok) return fail(s, EMPIC_E_ARG, "null state particle array");
+    }
+    for (int a = 0; a < 3; ++a) {
+        EMPIC_HIP(cp(st->E[a], s->E[a], fb));
+        EMPIC_HIP(cp(st->B[a], s->B[a], fb));
     }
     for (int i = 0; i < s->nsp; ++i) {
         const SpeciesState &S = s->sp[i];
         const empic_particle_buffers &b = S.buf[S.cur];
         const size_t pb = (size_t)S.capacity * 4;
         if (pb == 0) continue;
-        if (!st->cell[i]) return fail(s, EMPIC_E_ARG, "null state cell array");
-        EMPIC_HIP(hipMemcpyAsync(save ? (void *)st->cell[i] : (void *)b.cell,
-                                 save ? (void *)b.cell : (void *)st->cell[i], pb,
-                                 hipMemcpyDeviceToDevice, s->stream));
+        EMPIC_HIP(cp(st->cell[i], b.cell, pb));
+        EMPIC_HIP(cp(st->id[i], b.id, pb));
         for (int a = 0; a < 3; ++a) {
-            if (!st->pos[i][a] || !st->u[i][a]) return fail(s, EMPIC_E_ARG, "null state array");
-            EMPIC_HIP(hipMemcpyAsync(save ? st->pos[i][a] : b.pos[a], save ? b.pos[a] : st->pos[i][a],
-                                     pb, hipMemcpyDeviceToDevice, s->stream));
-            EMPIC_HIP(hipMemcpyAsync(save ? st->u[i][a] : b.u[a], save ? b.u[a] : st->u[i][a], pb,
-                                     hipMemcpyDeviceToDevice, s->stream));
+            EMPIC_HIP(cp(st->pos[i][a], b.pos[a], pb));
+            EMPIC_HIP(cp(st->u[i][a], b.u[a], pb));
         }
+        if (S.desc.per_particle_w) EMPIC_HIP(cp(st->w[i], b.w, pb));
+        // tile offsets and the slot count after them
+        EMPIC_HIP(cp(st->tiles[i], S.tile_off, ((size_t)s->ti.ntiles + 2) * 4));
     }
+    return EMPIC_OK;
+}
+
+empic_status empic_state_tile_words(empic_sim *s, int64_t *words) {
+    EMPIC_GUARD(s);
+    if (!words) return fail(s, EMPIC_E_ARG, "null output");
+    *words = (int64_t)s->ti.ntiles + 2;
     return EMPIC_OK;
 }
 
@@ -757,6 +773,8 @@ empic_status empic_save_state(empic_sim *s, const empic_state *dst) {
     EMPIC_GUARD(s);
     if (!dst || !s->bound) return fail(s, EMPIC_E_ARG, "null state or fields not bound");
     if (fp64(s)) return fail(s, EMPIC_E_UNSUPPORTED, "states are for the FP32 path");
+    if (s->nsp > 0 && s->need_sort)
+        return fail(s, EMPIC_E_ARG, "sort the particles before saving a state");
     return copy_state(s, dst, true);
 }
 
@@ -764,8 +782,48 @@ empic_status empic_load_state(empic_sim *s, const empic_state *src) {
     EMPIC_GUARD(s);
     if (!src || !s->bound) return fail(s, EMPIC_E_ARG, "null state or fields not bound");
     if (fp64(s)) return fail(s, EMPIC_E_UNSUPPORTED, "states are for the FP32 path");
+    const empic_status st = copy_state(s, src, false);
+    if (st != EMPIC_OK) return st;
+    // a saved state is grouped by its own tile offsets
+    for (int i = 0; i < s->nsp; ++i) s->sp[i].tiles_valid = true;
+    s->need_sort = false;
     s->rho_prev_step = -1;
-    return copy_state(s, src, false);
+    return EMPIC_OK;
+}
+
+empic_status empic_sort_recorded(empic_sim *s, int32_t *const perm[EMPIC_MAX_SPECIES]) {
+    EMPIC_GUARD(s);
+    if (!perm) return fail(s, EMPIC_E_ARG, "null permutation arrays");
+    if (fp64(s)) return fail(s, EMPIC_E_UNSUPPORTED, "the FP64 path does not sort");
+    for (int i = 0; i < s->nsp; ++i)
+        if (s->sp[i].capacity > 0 && !perm[i]) return fail(s, EMPIC_E_ARG, "null permutation array");
+    if (s->nsp == 0) return EMPIC_OK;
+    do_sort(s, perm);
+    return check_launch(s, "sort_recorded");
+}
+
+empic_status empic_sort_vjp(empic_sim *s, int32_t *const perm[EMPIC_MAX_SPECIES],
+                            const empic_adjoint *lam) {
+    EMPIC_GUARD(s);
+    if (!perm || !lam) return fail(s, EMPIC_E_ARG, "null permutation or adjoint");
+    if (fp64(s)) return fail(s, EMPIC_E_UNSUPPORTED, "the FP64 path does not sort");
+    for (int i = 0; i < s->nsp; ++i) {
+        const SpeciesState &S = s->sp[i];
+        if (S.capacity == 0) continue;
+        float *lx[3], *lu[3], *scratch[6];
+        bool ok = perm[i] != nullptr && S.has_alt;
+        const empic_particle_buffers &alt = S.buf[1 - S.cur];
+        for (int a = 0; a < 3; ++a) {
+            lx[a] = (float *)lam->pos[i][a];
+            lu[a] = (float *)lam->u[i][a];
+            scratch[a] = (float *)alt.pos[a];
+            scratch[3 + a] = (float *)alt.u[a];
+            ok = ok && lx[a] && lu[a];
+        }
+        if (!ok) return fail(s, EMPIC_E_ARG, "null permutation or adjoint array");
+        launch_sort_vjp(perm[i], S.capacity, lx, lu, scratch, s->stream);
+    }
+    return check_launch(s, "sort_vjp");
 }
 
 empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adjoint *lam) {

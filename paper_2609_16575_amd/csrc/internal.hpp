@@ -173,7 +173,7 @@ void launch_store_f32(const GridP &g, const SpeciesP &sp, double *pos, double *u
 // still grouped by the tile offsets of its previous sort (faster counting).
 void launch_sort(const GridP &g, const TileInfo &ti, const SpeciesP &cur, const SpeciesP &alt,
                  int32_t *counts, int32_t *scan_blocks, int32_t *rank, int32_t *tile_off,
-                 uint32_t *fault, bool tiles_valid, hipStream_t s);
+                 uint32_t *fault, bool tiles_valid, int32_t *perm, hipStream_t s);
 
 // FP64 plain path
 void launch_push_f64(const GridP &g, double *const E[3], double *const Bbar[3],
@@ -197,6 +197,9 @@ void launch_step_vjp(const GridP &g, float *const E[3], float *const Bbar[3],
                      float *const lE[3], float *const lB[3], float *const lEg[3],
                      float *const lBb[3], float *const tB[3], const SpeciesP *sp,
                      float *const (*lx)[3], float *const (*lu)[3], int nsp, hipStream_t s);
+// adjoint of a recorded sort: lam[perm[j]] = lam_post[j] (scratch: 6 x cap floats)
+void launch_sort_vjp(const int32_t *perm, long long cap, float *const lx[3], float *const lu[3],
+                     float *const scratch[6], hipStream_t s);
 
 // diagnostics
 void launch_zero_f64(double *p, long long n, hipStream_t s);

@@ -856,7 +856,7 @@ __global__ void k_scan_down(int32_t *counts, long long NK, const int32_t *bsum) 
 }
 
 __global__ void k_sort_scatter(TileInfo ti, SpeciesP cur, SpeciesP alt, const int32_t *offs,
-                               const int32_t *rank) {
+                               const int32_t *rank, int32_t *perm) {
     const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (p >= *cur.count) return;
     const int rk = rank[p];
@@ -870,6 +870,7 @@ __global__ void k_sort_scatter(TileInfo ti, SpeciesP cur, SpeciesP alt, const in
     }
     alt.id[dst] = cur.id[p];
     if (cur.w && alt.w) ((float *)alt.w)[dst] = ((const float *)cur.w)[p];
+    if (perm) perm[dst] = (int32_t)p;
 }
 
 __global__ void k_tile_offsets(const int32_t *offs, long long NK, int ntiles, int32_t *tile_off,
@@ -968,9 +969,10 @@ void launch_store_f32(const GridP &g, const SpeciesP &sp, double *pos, double *u
 
 void launch_sort(const GridP &g, const TileInfo &ti, const SpeciesP &cur, const SpeciesP &alt,
                  int32_t *counts, int32_t *scan_blocks, int32_t *rank, int32_t *tile_off,
-                 uint32_t *fault, bool tiles_valid, hipStream_t s) {
+                 uint32_t *fault, bool tiles_valid, int32_t *perm, hipStream_t s) {
     const long long NK = ti.NK;
     launch_fill_i32(counts, NK + 1, 0, s);
+    if (perm && cur.capacity > 0) launch_fill_i32(perm, cur.capacity, -1, s);
     if (cur.capacity > 0) {
         if (tiles_valid)
             hipLaunchKernelGGL(k_sort_count_tiles, dim3(ti.ntiles), dim3(SORT_T), 0, s, ti, g, cur,
@@ -985,7 +987,7 @@ void launch_sort(const GridP &g, const TileInfo &ti, const SpeciesP &cur, const 
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(SCAN_T), 0, s, counts, NK, scan_blocks);
     if (cur.capacity > 0)
         hipLaunchKernelGGL(k_sort_scatter, dim3(nblk(cur.capacity, 256)), dim3(256), 0, s, ti,
-                           cur, alt, counts, rank);
+                           cur, alt, counts, rank, perm);
     hipLaunchKernelGGL(k_tile_offsets, dim3(nblk(ti.ntiles + 1, 256)), dim3(256), 0, s, counts,
                        NK, ti.ntiles, tile_off, cur.count);
 }

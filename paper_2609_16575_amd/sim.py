@@ -64,6 +64,7 @@ class Sim:
         d.dt = float(workload.dt)
         d.precision = LB.FP64_PLAIN if self.fp64 else LB.FP32_CELLREL
         d.sort_every = int(workload.sort_every if sort_every is None else sort_every)
+        self.sort_every = d.sort_every
         self.desc = d
         wsb = self.L.empic_workspace_bytes(C.byref(d), max(nsp, 1), max_cap)
         if wsb == 0:
@@ -201,13 +202,22 @@ class Sim:
 
     # -- differentiable runs (FP32 path, periodic grid) ----------------------------
     def alloc_state(self):
-        """Device tensors for one saved state (fields + current particle layout)."""
+        """Device tensors for one saved state (fields + the full particle record)."""
         t = self.torch
-        st = {"E": t.empty_like(self.E), "B": t.empty_like(self.B), "cell": [], "pos": [], "u": []}
-        for cap in self.caps:
+        if not hasattr(self, "_tile_words"):
+            n = C.c_int64()
+            LB.check(self.h, self.L.empic_state_tile_words(self.h, C.byref(n)))
+            self._tile_words = n.value
+        st = {"E": t.empty_like(self.E), "B": t.empty_like(self.B), "cell": [], "pos": [], "u": [],
+              "id": [], "w": [], "tiles": []}
+        for i, cap in enumerate(self.caps):
             st["cell"].append(t.empty(cap, dtype=t.int32, device=self.dev))
             st["pos"].append(t.empty((3, cap), dtype=self.dtype, device=self.dev))
             st["u"].append(t.empty((3, cap), dtype=self.dtype, device=self.dev))
+            st["id"].append(t.empty(cap, dtype=t.int32, device=self.dev))
+            has_w = self.bufs[i][0]["w"] is not None
+            st["w"].append(t.empty(cap, dtype=self.dtype, device=self.dev) if has_w else None)
+            st["tiles"].append(t.empty(self._tile_words, dtype=t.int32, device=self.dev))
         return st
 
     def alloc_adjoint(self):
@@ -225,6 +235,9 @@ class Sim:
             S.B[a] = _ptr(st["B"][a])
         for i in range(len(self.caps)):
             S.cell[i] = _ptr(st["cell"][i])
+            S.id[i] = _ptr(st["id"][i])
+            S.w[i] = _ptr(st["w"][i]) if st["w"][i] is not None else None
+            S.tiles[i] = _ptr(st["tiles"][i])
             for a in range(3):
                 S.pos[i][a] = _ptr(st["pos"][i][a])
                 S.u[i][a] = _ptr(st["u"][i][a])
@@ -255,6 +268,26 @@ class Sim:
         """In place: lam (adjoint after the step taken from st) -> adjoint of st."""
         S, A = self._state_struct(st), self._adjoint_struct(lam)
         LB.check(self.h, self.L.empic_step_vjp(self.h, C.byref(S), C.byref(A)))
+
+    def alloc_perm(self):
+        """One int32 permutation array per species, for sort_recorded."""
+        t = self.torch
+        return [t.empty(cap, dtype=t.int32, device=self.dev) for cap in self.caps]
+
+    def _perm_array(self, perm):
+        P = (C.c_void_p * LB.MAX_SPECIES)()
+        for i, p in enumerate(perm):
+            P[i] = _ptr(p)
+        return P
+
+    def sort_recorded(self, perm):
+        """Sort now; perm[i][j] = slot before the sort of what is in slot j."""
+        LB.check(self.h, self.L.empic_sort_recorded(self.h, self._perm_array(perm)))
+
+    def sort_vjp(self, perm, lam):
+        """In place: particle adjoints after a recorded sort -> before it."""
+        A = self._adjoint_struct(lam)
+        LB.check(self.h, self.L.empic_sort_vjp(self.h, self._perm_array(perm), C.byref(A)))
 
     def current_buffers(self, sp):
         """Tensors of species sp's current buffer set (storage order)."""
