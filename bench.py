@@ -11,7 +11,9 @@ Prints one JSON line.  value = FP32 cell-relative particle-pushes/s; the plain
 FP64 step on the same workload is reported beside it.  The dominant kernel is
 the fused FP32 particle kernel; its roofline entry uses the algorithmic bytes
 56 per particle (28 read + 28 written) + 36 per cell (E and centred B read,
-J written) per launch over its HIP-event-timed average duration.
+J written) per launch over its HIP-event-timed average duration.  The
+"adjoint" entry times a 50-step forward + adjoint on a 128^3 anisotropic
+plasma (see adjoint_leg).
 """
 from __future__ import annotations
 
@@ -84,6 +86,61 @@ def cpu_baseline(n=(64, 64, 64), steps=2):
                       "single-threaded FP64 C, %.1f s" % (steps, *n, w.n_particles, dt)}
 
 
+def adjoint_leg(torch, n=128, steps=50, K=10):
+    """Forward + adjoint on a 128^3 periodic slice of the anisotropic
+    (T_x/T_perp = 25) electron plasma, 16 per cell (33.55M particles), 50
+    steps, checkpoints and sorts every 10 steps; loss = 1/2 dV sum |B|^2 of
+    the final step.  Reports the plain FP32 step on the same workload (sort
+    every 10) beside the differentiable forward and the adjoint step
+    (backward wall time over the steps: segment recompute + step VJPs)."""
+    from paper_2609_16575_amd import autograd as AG
+    from paper_2609_16575_amd import workloads as W
+    from paper_2609_16575_amd.sim import Sim
+    w = W.weibel_bimaxwellian(n=(n,) * 3, steps=steps, sort_every=K)
+    sim = Sim(w, precision="fp32")
+    wall, _ = time_steps(sim, steps, 5, torch)
+    fwd_ms = 1e3 * wall / steps
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    sim = Sim(w, precision="fp32", sort_every=0)
+    sim.sort()
+    st0 = sim.save_state()
+    U = sim.current_buffers(0)["u"].clone()
+    dV = float(w.d[0] * w.d[1] * w.d[2])
+    rec = {}
+    for rep in range(2):  # the first run warms up
+        sim.load_state(st0)
+        U0 = U.clone().requires_grad_(True)
+        E0 = torch.zeros_like(sim.E).requires_grad_(True)
+        B0 = torch.zeros_like(sim.B)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, BN = AG.run(sim, steps, K, E0, B0, [U0], sort=True)
+        loss = 0.5 * dV * (BN * BN).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        rec = {"fwd": t1 - t0, "bwd": t2 - t1, "loss": float(loss.item()),
+               "gU_norm": float(U0.grad.double().norm().item()),
+               "finite": bool(torch.isfinite(U0.grad).all().item() and torch.isfinite(E0.grad).all().item())}
+        _log("adjoint rep %d: fwd %.3f s bwd %.3f s" % (rep, rec["fwd"], rec["bwd"]))
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    adj_ms = 1e3 * rec["bwd"] / steps
+    return {"workload": "anisotropic electron plasma (T_x/T_perp=25, v_th,x=0.25c), periodic "
+                        "%dx%dx%d, 16 per cell (%d particles), %d steps, checkpoints and sorts "
+                        "every %d, loss 1/2 dV sum |B|^2" % (n, n, n, w.n_particles, steps, K),
+            "forward_step_ms": fwd_ms,
+            "diff_forward_ms_per_step": 1e3 * rec["fwd"] / steps,
+            "adjoint_step_ms": adj_ms,
+            "adjoint_over_forward": adj_ms / fwd_ms,
+            "loss": rec["loss"], "grad_u_norm": rec["gU_norm"], "grad_finite": rec["finite"]}
+
+
 def copy_calibration(torch, nbytes=1 << 30):
     """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
     x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -104,11 +161,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--only", choices=["fp32", "fp64", "adjoint"], default=None)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the step would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -131,7 +189,7 @@ def main():
                                   % (*n, npart),
                       "particles": npart, "cells": ncell, "sort_every": 10}}
 
-    if args.only != "fp64":
+    if args.only in (None, "fp32"):
         sim = Sim(w, precision="fp32")
         _log("fp32 sim ready")
         wall, kt = time_steps(sim, args.steps, args.warmup, torch)
@@ -158,7 +216,7 @@ def main():
         del sim
         torch.cuda.empty_cache()
 
-    if not args.no_fp64 and args.only != "fp32":
+    if not args.no_fp64 and args.only in (None, "fp64"):
         sim = Sim(w, precision="fp64")
         _log("fp64 sim ready")
         wall, kt = time_steps(sim, args.steps, args.warmup, torch)
@@ -173,7 +231,9 @@ def main():
         torch.cuda.empty_cache()
 
     out["adjoint"] = None
-    if not args.no_cpu_baseline:
+    if not args.no_adjoint and args.only in (None, "adjoint"):
+        out["adjoint"] = adjoint_leg(torch)
+    if not args.no_cpu_baseline and args.only is None:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 

@@ -8,11 +8,20 @@
 // with Cf / Cb the forward / backward difference curls of the Yee scheme
 // (Sec. 2.3; on a periodic grid Cf^T = Cb).  Given the adjoints of
 // (E', B', x', u') the kernels below return those of (E, B, x, u):
-//   k_adj_particles: per particle, recompute the forward in FP32 from the saved
-//     state, then reverse it: the ZigZag deposit adjoint gathers -dt lam_E' on
-//     the edges the particle touched (Sec. 2.5), the position and Boris adjoints
-//     follow, and the gather adjoint scatters lam_Ep, lam_Bp onto the Yee
-//     sub-grids (float atomics) while its derivative in x adds to lam_x;
+//   k_adj_fused: one workgroup per tile of the particle sort, like the step's
+//     fused kernel.  Per particle it re-computes the forward step with the
+//     step kernel's own arithmetic (gather from the staged E, Bbar window,
+//     Boris, move), then reverses it: the ZigZag deposit adjoint gathers
+//     -dt lam_E' on the edges the particle touched (Sec. 2.5) from a staged
+//     lam_E' window, the position and Boris adjoints follow, and the gather
+//     adjoint scatters lam_Ep, lam_Bp onto the six Yee sub-grids while its
+//     derivative in x adds to lam_x.  The scatter accumulates in an LDS window
+//     in int64 fixed point (integer LDS atomics are ~20x cheaper than float
+//     ones here) whose scale follows the largest |lam| met so far in the tile
+//     (a block-wide exponent; the window is shifted down when it grows), and
+//     the window is added to global memory once per tile.  Each round gives
+//     the 64 lanes of a wave particles 32 apart in the tile, so that lanes
+//     seldom hit the same LDS word in one atomic instruction.
 //   k_adj_bprime: lam_B'_t = lam_B' + dt Cf lam_E' + lam_Bbar / 2,
 //                 lam_B = lam_B'_t + lam_Bbar / 2;
 //   k_adj_e:      lam_E = lam_E' + lam_Egather - dt Cb lam_B'_t.
@@ -20,68 +29,92 @@
 // relay-point branch and the interpolation corners are frozen).  Position
 // adjoints are per unit length (global coordinates).
 #include "internal.hpp"
+#include "pic_math.hpp"
 
 namespace empic {
 
 namespace {
 
-__device__ __forceinline__ float rcpf_(float x) { return __builtin_amdgcn_rcpf(x); }
+constexpr int ADJ_THREADS = 512;
+constexpr int APPT = 2;  // consecutive particles per thread and round
+typedef float vfA __attribute__((ext_vector_type(APPT)));
+typedef uint32_t vuA __attribute__((ext_vector_type(APPT)));
+constexpr int NO_EXP = -100000;
 
 __device__ __forceinline__ int pwrap(int x, int n) {
     int m = x % n;
     return m < 0 ? m + n : m;
 }
-__device__ __forceinline__ long long gidx(const GridP &g, int i, int j, int k) {
-    return pwrap(i, g.n[0]) + (long long)g.ext[0] * (pwrap(j, g.n[1]) + (long long)g.ext[1] * pwrap(k, g.n[2]));
+
+// ---- field and lam_E' access: the tile's LDS windows or global memory --------
+struct LdsAcc {
+    const float *sF;  // 6 x FW3: E0..2, Bbar0..2
+    const float *sL;  // 3 x JW3: lam_E'
+    __device__ float F(int q, int i, int j, int k) const {
+        return sF[q * FW3 + i + FWX * (j + FWY * k)];
+    }
+    __device__ float L(int c, int i, int j, int k) const {
+        return sL[c * JW3 + i + JWX * (j + JWY * k)];
+    }
+};
+
+struct GlobAcc {
+    int n0, n1, n2, e0, e1;
+    const float *E[3];
+    const float *Bb[3];
+    const float *lJ[3];
+    __device__ long long idx(int i, int j, int k) const {
+        return pwrap(i, n0) + (long long)e0 * (pwrap(j, n1) + (long long)e1 * pwrap(k, n2));
+    }
+    __device__ float F(int q, int i, int j, int k) const {
+        return (q < 3 ? E[q] : Bb[q - 3])[idx(i, j, k)];
+    }
+    __device__ float L(int c, int i, int j, int k) const { return lJ[c][idx(i, j, k)]; }
+};
+
+// trilinear value with the step kernel's operation order (tri_lds / tri_global)
+// and its gradient in the fractional coordinates
+template <class Acc>
+__device__ __forceinline__ void tri_vg(const Acc &a, int q, int i, int j, int k, float fx, float fy,
+                                       float fz, float &val, float gr[3]) {
+    const float v0 = a.F(q, i, j, k), v1 = a.F(q, i + 1, j, k);
+    const float v2 = a.F(q, i, j + 1, k), v3 = a.F(q, i + 1, j + 1, k);
+    const float v4 = a.F(q, i, j, k + 1), v5 = a.F(q, i + 1, j, k + 1);
+    const float v6 = a.F(q, i, j + 1, k + 1), v7 = a.F(q, i + 1, j + 1, k + 1);
+    const float c00 = lerpf(v0, v1, fx), c10 = lerpf(v2, v3, fx);
+    const float c01 = lerpf(v4, v5, fx), c11 = lerpf(v6, v7, fx);
+    const float c0 = lerpf(c00, c10, fy), c1 = lerpf(c01, c11, fy);
+    val = lerpf(c0, c1, fz);
+    gr[2] = c1 - c0;
+    gr[1] = lerpf(c10 - c00, c11 - c01, fz);
+    gr[0] = lerpf(lerpf(v1 - v0, v3 - v2, fy), lerpf(v5 - v4, v7 - v6, fy), fz);
 }
 
-// trilinear value of F at corner (i0,j0,k0) + (fx,fy,fz), and its gradient in f
-__device__ void tri_val_grad(const GridP &g, const float *F, int i0, int j0, int k0, float fx,
-                             float fy, float fz, float &val, float grad[3]) {
-    float v[8];
+// corner and fractions of component q (E0..2, Bbar0..2) on its staggered
+// sub-grid for a particle at offset o in cell l (any coordinates): E_a is
+// half-staggered along a, Bbar_a along the two other axes
+__device__ __forceinline__ void stagger(int q, const int l[3], const float o[3], int c[3],
+                                        float f[3]) {
 #pragma unroll
-    for (int o = 0; o < 8; ++o) v[o] = F[gidx(g, i0 + (o & 1), j0 + ((o >> 1) & 1), k0 + (o >> 2))];
-    const float gx = 1.f - fx, gy = 1.f - fy, gz = 1.f - fz;
-    val = gz * (gy * (gx * v[0] + fx * v[1]) + fy * (gx * v[2] + fx * v[3])) +
-          fz * (gy * (gx * v[4] + fx * v[5]) + fy * (gx * v[6] + fx * v[7]));
-    grad[0] = gz * (gy * (v[1] - v[0]) + fy * (v[3] - v[2])) +
-              fz * (gy * (v[5] - v[4]) + fy * (v[7] - v[6]));
-    grad[1] = gz * (gx * (v[2] - v[0]) + fx * (v[3] - v[1])) +
-              fz * (gx * (v[6] - v[4]) + fx * (v[7] - v[5]));
-    grad[2] = gy * (gx * (v[4] - v[0]) + fx * (v[5] - v[1])) +
-              fy * (gx * (v[6] - v[2]) + fx * (v[7] - v[3]));
-}
-
-__device__ void tri_scatter(const GridP &g, float *lF, int i0, int j0, int k0, float fx, float fy,
-                            float fz, float l) {
-    if (l == 0.f) return;
-    const float gx = 1.f - fx, gy = 1.f - fy, gz = 1.f - fz;
-    const float w[8] = {gx * gy * gz, fx * gy * gz, gx * fy * gz, fx * fy * gz,
-                        gx * gy * fz, fx * gy * fz, gx * fy * fz, fx * fy * fz};
-#pragma unroll
-    for (int o = 0; o < 8; ++o)
-        atomicAdd(lF + gidx(g, i0 + (o & 1), j0 + ((o >> 1) & 1), k0 + (o >> 2)), l * w[o]);
-}
-
-__device__ __forceinline__ void half_idx(float o, int c, int &h, float &f) {
-    if (o < 0.5f) {
-        h = c - 1;
-        f = o + 0.5f;
-    } else {
-        h = c;
-        f = o - 0.5f;
+    for (int a = 0; a < 3; ++a) {
+        const bool half = q < 3 ? (a == q) : (a != q - 3);
+        if (half) {
+            half_axis(o[a], l[a], c[a], f[a]);
+        } else {
+            c[a] = l[a];
+            f[a] = o[a];
+        }
     }
 }
 
-// adjoint of one straight segment inside cell (ci,cj,ck) (global cell index),
-// given per axis its midpoint W relative to that cell and its displacement D:
-// accumulates d/ds and d/de (cell units) of sum_edges lJ . J_segment, with
-// D = e - s and W = (s + e)/2 - cell.
-__device__ void segment_vjp(const GridP &g, const float *const lJ[3], int ci, int cj, int ck,
-                            const float W[3], const float D[3], const float ampc[3], float ls[3],
-                            float le[3]) {
+// adjoint of one straight segment inside cell `cell`, given per axis its
+// midpoint W relative to that cell and its displacement D: adds d/ds and d/de
+// (cell units) of sum_edges lam . J_segment, with D = e - s, W = (s + e)/2 - cell.
+template <class Acc>
+__device__ __forceinline__ void segment_vjp(const Acc &a, const int cell[3], const float W[3],
+                                            const float D[3], const float ampc[3], float ls[3],
+                                            float le[3]) {
     float lD[3] = {0.f, 0.f, 0.f}, lW[3] = {0.f, 0.f, 0.f};
-    const int cell[3] = {ci, cj, ck};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int b1 = (c + 1) % 3, b2 = (c + 2) % 3;
@@ -91,13 +124,12 @@ __device__ void segment_vjp(const GridP &g, const float *const lJ[3], int ci, in
             int p[3] = {cell[0], cell[1], cell[2]};
             p[b1] += o1;
             p[b2] += o2;
-            const float lam = lJ[c][gidx(g, p[0], p[1], p[2])];
+            const float lam = a.L(c, p[0], p[1], p[2]) * ampc[c];
             const float w1 = o1 ? W[b1] : 1.f - W[b1];
             const float w2 = o2 ? W[b2] : 1.f - W[b2];
             const float sg = (o1 == o2) ? 1.f : -1.f;
-            const float weight = w1 * w2 + sg * D[b1] * D[b2] * (1.f / 12.f);
-            lD[c] += lam * ampc[c] * weight;
-            const float k = lam * ampc[c] * D[c];
+            lD[c] += lam * (w1 * w2 + sg * D[b1] * D[b2] * (1.f / 12.f));
+            const float k = lam * D[c];
             lW[b1] += k * (o1 ? 1.f : -1.f) * w2;
             lW[b2] += k * w1 * (o2 ? 1.f : -1.f);
             lD[b1] += k * sg * D[b2] * (1.f / 12.f);
@@ -105,19 +137,20 @@ __device__ void segment_vjp(const GridP &g, const float *const lJ[3], int ci, in
         }
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        ls[a] += -lD[a] + 0.5f * lW[a];
-        le[a] += lD[a] + 0.5f * lW[a];
+    for (int b = 0; b < 3; ++b) {
+        ls[b] += -lD[b] + 0.5f * lW[b];
+        le[b] += lD[b] + 0.5f * lW[b];
     }
 }
 
 struct AdjArgs {
     GridP g;
+    TileInfo ti;
     const float *E[3];
     const float *Bb[3];
-    const float *lJsrc[3];  // adjoint of E^{n+1}; lam_J = -dt * it
-    float *lEg[3];          // accumulated adjoint of E^n through the gather
-    float *lBb[3];          // accumulated adjoint of Bbar
+    const float *lJ[3];  // adjoint of E^{n+1}; lam_J = -dt * lam_E'
+    float *lEg[3];       // accumulated adjoint of E^n through the gather
+    float *lBb[3];       // accumulated adjoint of Bbar
     float dtd[3];
     float inv_d[3];
     float dt;
@@ -127,69 +160,59 @@ struct AdjSpecies {
     const uint32_t *cell;
     const float *pos[3];
     const float *u[3];
-    const float *w;
+    const float *w;            // per-particle weight or nullptr
     float *lx[3];
     float *lu[3];
-    const int32_t *count;
-    float r;
-    float qc[3];
+    const int32_t *tile_off;   // the state's tile offsets
+    float r;                   // q dt / (2 m)
+    float qc[3];               // q w d_a / (dt dV)  (w = 1 when per-particle)
 };
 
-__global__ __launch_bounds__(256) void k_adj_particles(AdjArgs A, AdjSpecies S) {
-    const GridP &g = A.g;
-    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (p >= *S.count) return;
-    const uint32_t c = S.cell[p];
-    if (c == DEAD) return;
-    const int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
-    const float o[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
-    const float u0[3] = {S.u[0][p], S.u[1][p], S.u[2][p]};
-    const float wq = S.w ? S.w[p] : 1.f;
-    // ---- forward recompute: gather (value and d/d offset) ----
-    int hx, hy, hz;
-    float fx, fy, fz;
-    half_idx(o[0], ci, hx, fx);
-    half_idx(o[1], cj, hy, fy);
-    half_idx(o[2], ck, hz, fz);
-    const int idx[6][3] = {{hx, cj, ck}, {ci, hy, ck}, {ci, cj, hz},
-                           {ci, hy, hz}, {hx, cj, hz}, {hx, hy, ck}};
-    const float fr[6][3] = {{fx, o[1], o[2]}, {o[0], fy, o[2]}, {o[0], o[1], fz},
-                            {o[0], fy, fz}, {fx, o[1], fz}, {fx, fy, o[2]}};
+// One particle's adjoint up to the gather scatter: returns lam_Ep, lam_Bp in
+// l6 and updates lam_x, lam_u (lx, lu in/out).  Cell coordinates l are the
+// accessor's (window-local or global).
+template <class Acc>
+__device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, const AdjSpecies &S,
+                                             const int l[3], const float o[3], const float u[3],
+                                             float wq, float lx[3], float lu[3], float l6[6]) {
+    // ---- forward re-computation: gather (value and d/d offset) ----
     float F6[6], G6[6][3];
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
-        tri_val_grad(g, q < 3 ? A.E[q] : A.Bb[q - 3], idx[q][0], idx[q][1], idx[q][2], fr[q][0],
-                     fr[q][1], fr[q][2], F6[q], G6[q]);
-    const float Ep[3] = {F6[0], F6[1], F6[2]}, Bp[3] = {F6[3], F6[4], F6[5]};
-    // ---- Boris forward (keeping intermediates) ----
+    for (int q = 0; q < 6; ++q) {
+        int c[3];
+        float f[3];
+        stagger(q, l, o, c, f);
+        tri_vg(acc, q, c[0], c[1], c[2], f[0], f[1], f[2], F6[q], G6[q]);
+    }
+    // ---- Boris with the step kernel's operations, keeping intermediates ----
     const float r = S.r;
     float um[3], t[3], s[3], up[3], un[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) um[a] = fmaf(r, Ep[a], u0[a]);
+    for (int a = 0; a < 3; ++a) um[a] = fmaf(r, F6[a], u[a]);
     const float gm = sqrtf(fmaf(um[0], um[0], fmaf(um[1], um[1], fmaf(um[2], um[2], 1.f))));
-    const float igm = rcpf_(gm);
+    const float igm = rcpf(gm);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) t[a] = r * Bp[a] * igm;
-    const float tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-    const float den = 1.f + tt;
-    const float sf = 2.f * rcpf_(den);
+    for (int a = 0; a < 3; ++a) t[a] = r * F6[3 + a] * igm;
+    const float den = fmaf(t[0], t[0], fmaf(t[1], t[1], fmaf(t[2], t[2], 1.f)));
+    const float iden = rcpf(den);
+    const float sf = 2.f * iden;
 #pragma unroll
     for (int a = 0; a < 3; ++a) s[a] = sf * t[a];
     up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
     up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
     up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
-    un[0] = um[0] + (up[1] * s[2] - up[2] * s[1]) + r * Ep[0];
-    un[1] = um[1] + (up[2] * s[0] - up[0] * s[2]) + r * Ep[1];
-    un[2] = um[2] + (up[0] * s[1] - up[1] * s[0]) + r * Ep[2];
+    un[0] = fmaf(r, F6[0], um[0] + (up[1] * s[2] - up[2] * s[1]));
+    un[1] = fmaf(r, F6[1], um[1] + (up[2] * s[0] - up[0] * s[2]));
+    un[2] = fmaf(r, F6[2], um[2] + (up[0] * s[1] - up[1] * s[0]));
     const float gn = sqrtf(fmaf(un[0], un[0], fmaf(un[1], un[1], fmaf(un[2], un[2], 1.f))));
-    const float ign = rcpf_(gn);
+    const float ign = rcpf(gn);
     float dx[3], e[3];
     int dc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+        float no;
         dx[a] = un[a] * ign * A.dtd[a];
-        e[a] = o[a] + dx[a];
-        dc[a] = e[a] >= 1.f ? 1 : (e[a] < 0.f ? -1 : 0);
+        move_axis_sel(o[a], dx[a], e[a], dc[a], no);
     }
     // ---- deposit adjoint: lam_J = -dt lam_E' on the touched edges ----
     const float ampc[3] = {S.qc[0] * wq, S.qc[1] * wq, S.qc[2] * wq};
@@ -198,54 +221,36 @@ __global__ __launch_bounds__(256) void k_adj_particles(AdjArgs A, AdjSpecies S) 
         // one straight segment; midpoint and displacement from the unrounded dx
         const float W[3] = {fmaf(0.5f, dx[0], o[0]), fmaf(0.5f, dx[1], o[1]),
                             fmaf(0.5f, dx[2], o[2])};
-        segment_vjp(g, A.lJsrc, ci, cj, ck, W, dx, ampc, l1, l2);
+        segment_vjp(acc, l, W, dx, ampc, l1, l2);
     } else {
-        float WA[3], DA[3], WB[3], DB[3], dr[3], lsA[3] = {0.f, 0.f, 0.f},
-              leA[3] = {0.f, 0.f, 0.f}, lsB[3] = {0.f, 0.f, 0.f}, leB[3] = {0.f, 0.f, 0.f};
+        float WA[3], DA[3], WB[3], DB[3];
+        float lsA[3] = {0.f, 0.f, 0.f}, leA[3] = {0.f, 0.f, 0.f};
+        float lsB[3] = {0.f, 0.f, 0.f}, leB[3] = {0.f, 0.f, 0.f};
+        zigzag_split(o, dx, e, dc, WA, DA, WB, DB);
+        const int lb[3] = {l[0] + dc[0], l[1] + dc[1], l[2] + dc[2]};
+        segment_vjp(acc, l, WA, DA, ampc, lsA, leA);
+        segment_vjp(acc, lb, WB, DB, ampc, lsB, leB);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            if (dc[a] == 0) {  // relay at the mid-point: derivative 1/2 in both ends
-                DA[a] = DB[a] = 0.5f * dx[a];
-                WA[a] = fmaf(0.25f, dx[a], o[a]);
-                WB[a] = fmaf(0.75f, dx[a], o[a]);
-                dr[a] = 0.5f;
-            } else {           // relay on the crossed face: constant
-                const float xr = dc[a] > 0 ? 1.f : 0.f;
-                DA[a] = xr - o[a];
-                WA[a] = 0.5f * (o[a] + xr);
-                DB[a] = e[a] - xr;
-                WB[a] = 0.5f * (xr + e[a]) - (float)dc[a];
-                dr[a] = 0.f;
-            }
-        }
-        segment_vjp(g, A.lJsrc, ci, cj, ck, WA, DA, ampc, lsA, leA);
-        segment_vjp(g, A.lJsrc, ci + dc[0], cj + dc[1], ck + dc[2], WB, DB, ampc, lsB, leB);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const float lr = leA[a] + lsB[a];
-            l1[a] = lsA[a] + lr * dr[a];
-            l2[a] = leB[a] + lr * dr[a];
+            // relay point: the mid-point (derivative 1/2 in both ends) or a face
+            const float lr = dc[a] == 0 ? 0.5f * (leA[a] + lsB[a]) : 0.f;
+            l1[a] = lsA[a] + lr;
+            l2[a] = leB[a] + lr;
         }
     }
-    // lam_J = -dt lam_E': the segment adjoints were taken with lam_E', scale now
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        l1[a] *= -A.dt;
-        l2[a] *= -A.dt;
-    }
-    // ---- position chain: x' = x + dt v', xi1 = x/d, xi2 = x/d + dt v'/d ----
+    // ---- position chain: x' = x + dt v', end point e = o + dt v'/d ----
     float lxn[3], lv[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float lxp = S.lx[a][p];
-        lxn[a] = lxp + (l1[a] + l2[a]) * A.inv_d[a];
-        lv[a] = A.dt * (lxp + l2[a] * A.inv_d[a]);
+        const float m1 = -A.dt * l1[a], m2 = -A.dt * l2[a];  // lam_J = -dt lam_E'
+        lxn[a] = lx[a] + (m1 + m2) * A.inv_d[a];
+        lv[a] = A.dt * (lx[a] + m2 * A.inv_d[a]);
     }
     const float uv = un[0] * lv[0] + un[1] * lv[1] + un[2] * lv[2];
     const float ign3 = ign * ign * ign;
     float lupl[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) lupl[a] = S.lu[a][p] + lv[a] * ign - un[a] * uv * ign3;
+    for (int a = 0; a < 3; ++a) lupl[a] = lu[a] + lv[a] * ign - un[a] * uv * ign3;
     // ---- Boris adjoint ----
     float lE[3], lB[3], lum[3], lup[3], ls[3], lt[3];
 #pragma unroll
@@ -266,7 +271,6 @@ __global__ __launch_bounds__(256) void k_adj_particles(AdjArgs A, AdjSpecies S) 
     lt[1] = lup[2] * um[0] - lup[0] * um[2];
     lt[2] = lup[0] * um[1] - lup[1] * um[0];
     const float tls = t[0] * ls[0] + t[1] * ls[1] + t[2] * ls[2];
-    const float iden = rcpf_(den);
 #pragma unroll
     for (int a = 0; a < 3; ++a) lt[a] += 2.f * ls[a] * iden - 4.f * t[a] * tls * iden * iden;
     float tlt = 0.f;
@@ -281,20 +285,252 @@ __global__ __launch_bounds__(256) void k_adj_particles(AdjArgs A, AdjSpecies S) 
         lum[a] += lgm * um[a] * igm;
         lE[a] += r * lum[a];
     }
-    // ---- gather adjoint: scatter onto the sub-grids, derivative in x ----
-    const float l6[6] = {lE[0], lE[1], lE[2], lB[0], lB[1], lB[2]};
-    float dxi[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        tri_scatter(g, q < 3 ? A.lEg[q] : A.lBb[q - 3], idx[q][0], idx[q][1], idx[q][2], fr[q][0],
-                    fr[q][1], fr[q][2], l6[q]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) dxi[a] += l6[q] * G6[q][a];
-    }
+    // ---- gather adjoint: derivative in x (the scatter is the caller's) ----
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        S.lx[a][p] = lxn[a] + dxi[a] * A.inv_d[a];
-        S.lu[a][p] = lum[a];
+        l6[a] = lE[a];
+        l6[3 + a] = lB[a];
+    }
+    float dxi[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dxi[a] += l6[q] * G6[q][a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lx[a] = lxn[a] + dxi[a] * A.inv_d[a];
+        lu[a] = lum[a];
+    }
+}
+
+__device__ __forceinline__ void tri_weights(const float f[3], float w[8]) {
+    const float gx = 1.f - f[0], gy = 1.f - f[1], gz = 1.f - f[2];
+    w[0] = gx * gy * gz;
+    w[1] = f[0] * gy * gz;
+    w[2] = gx * f[1] * gz;
+    w[3] = f[0] * f[1] * gz;
+    w[4] = gx * gy * f[2];
+    w[5] = f[0] * gy * f[2];
+    w[6] = gx * f[1] * f[2];
+    w[7] = f[0] * f[1] * f[2];
+}
+
+// gather-as-scatter of one particle straight into global memory (float atomics)
+__device__ void scatter_global(const GlobAcc &G, float *const lEg[3], float *const lBb[3],
+                               const int l[3], const float o[3], const float l6[6]) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        if (l6[q] == 0.f) continue;
+        int c[3];
+        float f[3], w[8];
+        stagger(q, l, o, c, f);
+        tri_weights(f, w);
+        float *dst = q < 3 ? lEg[q] : lBb[q - 3];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            atomicAdd(dst + G.idx(c[0] + (k & 1), c[1] + ((k >> 1) & 1), c[2] + (k >> 2)),
+                      l6[q] * w[k]);
+    }
+}
+
+__global__ __launch_bounds__(ADJ_THREADS, 1) void k_adj_fused(AdjArgs A, AdjSpecies S) {
+    __shared__ float sF[6 * FW3];
+    __shared__ float sL[3 * JW3];
+    __shared__ unsigned long long sA[6 * FW3];
+    __shared__ int sG[3][16];
+    __shared__ int sE;
+
+    const GridP &g = A.g;
+    const int nb8 = gridDim.x >> 3;
+    const int tile = (blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);  // XCD-contiguous tiles
+    if (tile >= A.ti.ntiles) return;
+    const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
+    if (beg >= end) return;
+
+    const int tx = tile % A.ti.nt[0];
+    const int tyz = tile / A.ti.nt[0];
+    const int ty = tyz % A.ti.nt[1], tz = tyz / A.ti.nt[1];
+    const int wo[3] = {tx * TX - MARGIN - 1, ty * TY - MARGIN - 1, tz * TZ - MARGIN - 1};
+    const int tid = threadIdx.x;
+
+    // global index tables of the window rows: x index, y*ext0, z*ext0*ext1
+    if (tid < 3 * 16) {
+        const int a = tid / 16, r = tid % 16;
+        const int wl = a == 0 ? JWX : (a == 1 ? JWY : JWZ);
+        if (r < wl) {
+            const int mul = a == 0 ? 1 : (a == 1 ? g.ext[0] : g.ext[0] * g.ext[1]);
+            sG[a][r] = pwrap(wo[a] + r, g.n[a]) * mul;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < 6 * FW3; e += ADJ_THREADS) {
+        const int comp = e / FW3;
+        const int r = e - comp * FW3;
+        const int lz = r / (FWX * FWY);
+        const int r2 = r - lz * (FWX * FWY);
+        const int ly = r2 / FWX, lx = r2 - ly * FWX;
+        const float *src = comp < 3 ? A.E[comp] : A.Bb[comp - 3];
+        sF[e] = src[sG[0][lx] + sG[1][ly] + sG[2][lz]];
+        sA[e] = 0ull;
+    }
+    for (int e = tid; e < 3 * JW3; e += ADJ_THREADS) {
+        const int comp = e / JW3;
+        const int r = e - comp * JW3;
+        const int lz = r / (JWX * JWY);
+        const int r2 = r - lz * (JWX * JWY);
+        const int ly = r2 / JWX, lx = r2 - ly * JWX;
+        sL[e] = A.lJ[comp][sG[0][lx] + sG[1][ly] + sG[2][lz]];
+    }
+
+    const LdsAcc lacc{sF, sL};
+    const GlobAcc gacc{g.n[0], g.n[1], g.n[2], g.ext[0], g.ext[1],
+                       {A.E[0], A.E[1], A.E[2]}, {A.Bb[0], A.Bb[1], A.Bb[2]},
+                       {A.lJ[0], A.lJ[1], A.lJ[2]}};
+    constexpr int LHI_X = TX + 2 * MARGIN, LHI_Y = TY + 2 * MARGIN, LHI_Z = TZ + 2 * MARGIN;
+    // fixed point: every contribution is below 2^EB in units of the scale and
+    // one entry takes at most one per particle of the tile, so |sum| < 2^61
+    int nbits = 0;
+    while (nbits < 31 && (1ll << nbits) <= (long long)(end - beg)) ++nbits;
+    const int EB = min(50, 61 - nbits);
+    int ecur = NO_EXP;  // block-uniform exponent of the window's scale
+    const int lane = tid & 63, wave = tid >> 6;
+    const int q0 = lane * (APPT * (ADJ_THREADS / 64)) + wave * APPT;
+    const int base0 = beg & ~(APPT - 1);
+
+    for (int rb = base0; rb < end; rb += ADJ_THREADS * APPT) {
+        if (tid == 0) sE = NO_EXP;
+        __syncthreads();
+        const int base = rb + q0;
+        float l6s[APPT][6], os[APPT][3];
+        int ls[APPT];  // window-local cell, packed; -1 = nothing to scatter here
+        int emax = NO_EXP;
+#pragma unroll
+        for (int k = 0; k < APPT; ++k) ls[k] = -1;
+        if (base < end) {
+            const vuA c4 = *(const vuA *)(S.cell + base);
+            const vfA ox4 = *(const vfA *)(S.pos[0] + base), oy4 = *(const vfA *)(S.pos[1] + base),
+                      oz4 = *(const vfA *)(S.pos[2] + base);
+            const vfA ux4 = *(const vfA *)(S.u[0] + base), uy4 = *(const vfA *)(S.u[1] + base),
+                      uz4 = *(const vfA *)(S.u[2] + base);
+            vfA w4 = (vfA)(1.f);
+            if (S.w) w4 = *(const vfA *)(S.w + base);
+            vfA lx4[3], lu4[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lx4[a] = *(const vfA *)(S.lx[a] + base);
+                lu4[a] = *(const vfA *)(S.lu[a] + base);
+            }
+#pragma unroll
+            for (int k = 0; k < APPT; ++k) {
+                const int p = base + k;
+                const uint32_t c = c4[k];
+                if (p < beg || p >= end || c == DEAD) continue;
+                const float o[3] = {ox4[k], oy4[k], oz4[k]};
+                const float u[3] = {ux4[k], uy4[k], uz4[k]};
+                float lx[3] = {lx4[0][k], lx4[1][k], lx4[2][k]};
+                float lu[3] = {lu4[0][k], lu4[1][k], lu4[2][k]};
+                float l6[6];
+                const int gl[3] = {cell_i(c), cell_j(c), cell_k(c)};
+                const int wl[3] = {local_axis(g, 0, gl[0], wo[0]), local_axis(g, 1, gl[1], wo[1]),
+                                   local_axis(g, 2, gl[2], wo[2])};
+                const bool inwin = wl[0] >= 1 && wl[0] <= LHI_X && wl[1] >= 1 && wl[1] <= LHI_Y &&
+                                   wl[2] >= 1 && wl[2] <= LHI_Z;
+                if (inwin) {
+                    particle_vjp(lacc, A, S, wl, o, u, w4[k], lx, lu, l6);
+                    float m = 0.f;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) m = fmaxf(m, fabsf(l6[q]));
+                    if (m > 0.f && m <= 3.0e38f) {
+                        int ex;
+                        frexpf(m, &ex);  // m < 2^ex
+                        emax = max(emax, ex);
+                        ls[k] = wl[0] | (wl[1] << 8) | (wl[2] << 16);
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) l6s[k][q] = l6[q];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) os[k][a] = o[a];
+                    } else if (m != 0.f) {
+                        // not finite: let it reach the result through global memory
+                        scatter_global(gacc, A.lEg, A.lBb, gl, o, l6);
+                    }
+                } else {
+                    // drifted more than MARGIN cells out of its tile since the sort
+                    particle_vjp(gacc, A, S, gl, o, u, w4[k], lx, lu, l6);
+                    scatter_global(gacc, A.lEg, A.lBb, gl, o, l6);
+                }
+                lx4[0][k] = lx[0];
+                lx4[1][k] = lx[1];
+                lx4[2][k] = lx[2];
+                lu4[0][k] = lu[0];
+                lu4[1][k] = lu[1];
+                lu4[2][k] = lu[2];
+            }
+            if (base >= beg && base + APPT <= end) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    *(vfA *)(S.lx[a] + base) = lx4[a];
+                    *(vfA *)(S.lu[a] + base) = lu4[a];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < APPT; ++k) {
+                    const int p = base + k;
+                    if (p < beg || p >= end) continue;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        S.lx[a][p] = lx4[a][k];
+                        S.lu[a][p] = lu4[a][k];
+                    }
+                }
+            }
+        }
+        if (emax != NO_EXP) atomicMax(&sE, emax);
+        __syncthreads();
+        const int enew = max(ecur, sE);
+        if (ecur != NO_EXP && enew > ecur) {
+            // the scale drops: shift what the window holds to the new one
+            const int sh = min(enew - ecur, 63);
+            for (int e = tid; e < 6 * FW3; e += ADJ_THREADS)
+                sA[e] = (unsigned long long)((long long)sA[e] >> sh);
+            __syncthreads();
+        }
+        ecur = enew;
+        if (ecur != NO_EXP) {
+            const double scale = ldexp(1.0, EB - ecur);
+#pragma unroll
+            for (int k = 0; k < APPT; ++k) {
+                if (ls[k] < 0) continue;
+                const int wl[3] = {ls[k] & 0xFF, (ls[k] >> 8) & 0xFF, ls[k] >> 16};
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    int c[3];
+                    float f[3], w[8];
+                    stagger(q, wl, os[k], c, f);
+                    tri_weights(f, w);
+                    const float v = l6s[k][q];
+                    unsigned long long *dst = sA + q * FW3 + c[0] + FWX * (c[1] + FWY * c[2]);
+#pragma unroll
+                    for (int o = 0; o < 8; ++o)
+                        atomicAdd(dst + (o & 1) + FWX * (((o >> 1) & 1) + FWY * (o >> 2)),
+                                  (unsigned long long)to_fixed(v * w[o], scale));
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (ecur == NO_EXP) return;
+    // add the window to the global gather adjoints (non-zero entries only)
+    const double inv = ldexp(1.0, ecur - EB);
+    for (int e = tid; e < 6 * FW3; e += ADJ_THREADS) {
+        const long long fx = (long long)sA[e];
+        if (fx == 0) continue;
+        const int comp = e / FW3;
+        const int r = e - comp * FW3;
+        const int lz = r / (FWX * FWY);
+        const int r2 = r - lz * (FWX * FWY);
+        const int ly = r2 / FWX, lx = r2 - ly * FWX;
+        float *dst = comp < 3 ? A.lEg[comp] : A.lBb[comp - 3];
+        atomicAdd(dst + sG[0][lx] + sG[1][ly] + sG[2][lz], (float)((double)fx * inv));
     }
 }
 
@@ -302,7 +538,8 @@ __global__ __launch_bounds__(256) void k_adj_particles(AdjArgs A, AdjSpecies S) 
 __device__ inline long long nb(const GridP &g, int i, int j, int k, int a, int dir) {
     int p[3] = {i, j, k};
     p[a] += dir;
-    return gidx(g, p[0], p[1], p[2]);
+    return pwrap(p[0], g.n[0]) +
+           (long long)g.ext[0] * (pwrap(p[1], g.n[1]) + (long long)g.ext[1] * pwrap(p[2], g.n[2]));
 }
 
 __global__ void k_adj_bprime(GridP g, const float *lEx, const float *lEy, const float *lEz,
@@ -311,7 +548,7 @@ __global__ void k_adj_bprime(GridP g, const float *lEx, const float *lEy, const 
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y,
               k = blockIdx.z;
     if (i >= g.n[0] || j >= g.n[1]) return;
-    const long long p = gidx(g, i, j, k);
+    const long long p = i + (long long)g.ext[0] * (j + (long long)g.ext[1] * k);
     const float *lE[3] = {lEx, lEy, lEz};
     float *lB[3] = {lBx, lBy, lBz};
     const float *lb[3] = {lbx, lby, lbz};
@@ -334,7 +571,7 @@ __global__ void k_adj_e(GridP g, float *lEx, float *lEy, float *lEz, const float
     const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y * blockDim.y + threadIdx.y,
               k = blockIdx.z;
     if (i >= g.n[0] || j >= g.n[1]) return;
-    const long long p = gidx(g, i, j, k);
+    const long long p = i + (long long)g.ext[0] * (j + (long long)g.ext[1] * k);
     float *lE[3] = {lEx, lEy, lEz};
     const float *ge[3] = {gx, gy, gz};
     const float *tB[3] = {tx, ty, tz};
@@ -382,20 +619,22 @@ __global__ void k_zero_f32(float *p, long long n) {
 
 }  // namespace
 
-void launch_step_vjp(const GridP &g, float *const E[3], float *const Bbar[3],
+void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], float *const Bbar[3],
                      float *const lE[3], float *const lB[3], float *const lEg[3],
                      float *const lBb[3], float *const tB[3], const SpeciesP *sp,
-                     float *const (*lx)[3], float *const (*lu)[3], int nsp, hipStream_t s) {
+                     const int32_t *const *tile_off, float *const (*lx)[3],
+                     float *const (*lu)[3], int nsp, hipStream_t s) {
     for (int a = 0; a < 3; ++a) {
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, lEg[a], g.V);
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, lBb[a], g.V);
     }
     AdjArgs A;
     A.g = g;
+    A.ti = ti;
     for (int a = 0; a < 3; ++a) {
         A.E[a] = E[a];
         A.Bb[a] = Bbar[a];
-        A.lJsrc[a] = lE[a];
+        A.lJ[a] = lE[a];
         A.lEg[a] = lEg[a];
         A.lBb[a] = lBb[a];
         A.dtd[a] = (float)(g.dt / g.d[a]);
@@ -403,7 +642,10 @@ void launch_step_vjp(const GridP &g, float *const E[3], float *const Bbar[3],
     }
     A.dt = (float)g.dt;
     const double dV = g.d[0] * g.d[1] * g.d[2];
+    // one workgroup per tile; a multiple of 8 for the XCD-contiguous tile map
+    const unsigned nblocks = (unsigned)(8 * ((ti.ntiles + 7) / 8));
     for (int i = 0; i < nsp; ++i) {
+        if (sp[i].capacity <= 0) continue;
         AdjSpecies S;
         S.cell = sp[i].cell;
         for (int a = 0; a < 3; ++a) {
@@ -413,13 +655,11 @@ void launch_step_vjp(const GridP &g, float *const E[3], float *const Bbar[3],
             S.lu[a] = lu[i][a];
         }
         S.w = (sp[i].per_particle_w && sp[i].w) ? (const float *)sp[i].w : nullptr;
-        S.count = sp[i].count;
+        S.tile_off = tile_off[i];
         S.r = (float)(sp[i].q * g.dt / (2.0 * sp[i].m));
         const double w = sp[i].per_particle_w ? 1.0 : sp[i].w_species;
         for (int a = 0; a < 3; ++a) S.qc[a] = (float)(sp[i].q * w * g.d[a] / (g.dt * dV));
-        if (sp[i].capacity > 0)
-            hipLaunchKernelGGL(k_adj_particles, dim3((unsigned)((sp[i].capacity + 255) / 256)),
-                               dim3(256), 0, s, A, S);
+        hipLaunchKernelGGL(k_adj_fused, dim3(nblocks), dim3(ADJ_THREADS), 0, s, A, S);
     }
     const dim3 grid((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]);
     hipLaunchKernelGGL(k_adj_bprime, grid, dim3(64, 4), 0, s, g, lE[0], lE[1], lE[2], lB[0], lB[1],

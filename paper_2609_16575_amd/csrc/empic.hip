@@ -846,12 +846,18 @@ empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adj
     // centred B of the state
     launch_faraday<float>(s->g, E, B, Bb, nullptr, false, s->stream);
     SpeciesP sp[EMPIC_MAX_SPECIES];
+    const int32_t *tiles[EMPIC_MAX_SPECIES] = {};
     float *lx[EMPIC_MAX_SPECIES][3], *lu[EMPIC_MAX_SPECIES][3];
     for (int i = 0; i < s->nsp; ++i) {
         sp[i] = species_params(s, i, s->sp[i].cur);
         if (s->sp[i].capacity > 0) {
-            if (!st->cell[i]) return fail(s, EMPIC_E_ARG, "null state cell array");
+            if (!st->cell[i] || !st->tiles[i])
+                return fail(s, EMPIC_E_ARG, "null state cell or tile array");
+            if (s->sp[i].desc.per_particle_w && !st->w[i])
+                return fail(s, EMPIC_E_ARG, "null state weight array");
             sp[i].cell = (uint32_t *)st->cell[i];
+            sp[i].w = st->w[i];
+            tiles[i] = st->tiles[i];
         }
         for (int a = 0; a < 3; ++a) {
             sp[i].pos[a] = st->pos[i][a];
@@ -862,7 +868,7 @@ empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adj
                 return fail(s, EMPIC_E_ARG, "null particle array in state or adjoint");
         }
     }
-    launch_step_vjp(s->g, E, Bb, lE, lB, lEg, lBb, tB, sp, lx, lu, s->nsp, s->stream);
+    launch_step_vjp(s->g, s->ti, E, Bb, lE, lB, lEg, lBb, tB, sp, tiles, lx, lu, s->nsp, s->stream);
     return check_launch(s, "step_vjp");
 }
 

@@ -193,10 +193,11 @@ void launch_store_f64(const SpeciesP &sp, long long count, double *pos, double *
                       hipStream_t s);
 
 // adjoint of one FP32 step (periodic)
-void launch_step_vjp(const GridP &g, float *const E[3], float *const Bbar[3],
+void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], float *const Bbar[3],
                      float *const lE[3], float *const lB[3], float *const lEg[3],
                      float *const lBb[3], float *const tB[3], const SpeciesP *sp,
-                     float *const (*lx)[3], float *const (*lu)[3], int nsp, hipStream_t s);
+                     const int32_t *const *tile_off, float *const (*lx)[3],
+                     float *const (*lu)[3], int nsp, hipStream_t s);
 // adjoint of a recorded sort: lam[perm[j]] = lam_post[j] (scratch: 6 x cap floats)
 void launch_sort_vjp(const int32_t *perm, long long cap, float *const lx[3], float *const lu[3],
                      float *const scratch[6], hipStream_t s);

@@ -1,0 +1,224 @@
+// pic_math.hpp -- per-particle arithmetic of the FP32 path shared by the
+// fused step kernel and its adjoint, so that the adjoint re-computes each
+// particle's step with exactly the forward kernel's operations and branch
+// decisions: staggered CIC gather (Sec. 2.5), relativistic Boris push
+// (Sec. 2.4), move with offset canonicalization, ZigZag segments and their
+// exact straight-segment edge weights (Sec. 2.5), and the LDS window indexing.
+#pragma once
+
+#include "internal.hpp"
+
+namespace empic {
+
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// global index of cell-axis coordinate x on axis a: periodic wrap (any x),
+// -1 outside an absorbing axis' array
+__device__ __forceinline__ int gaxis(const GridP &g, int a, int x) {
+    if (g.bc[a] == EMPIC_BC_PERIODIC) {
+        int m = x % g.n[a];
+        return m < 0 ? m + g.n[a] : m;
+    }
+    return (x < 0 || x >= g.ext[a]) ? -1 : x;
+}
+
+__device__ inline float tri_global(const GridP &g, const float *F, int i0, int j0, int k0, float fx,
+                            float fy, float fz) {
+    float v[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        const int gx = gaxis(g, 0, i0 + (o & 1)), gy = gaxis(g, 1, j0 + ((o >> 1) & 1)),
+                  gz = gaxis(g, 2, k0 + (o >> 2));
+        v[o] = (gx < 0 || gy < 0 || gz < 0)
+                   ? 0.f
+                   : F[gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz)];
+    }
+    const float c00 = lerpf(v[0], v[1], fx), c10 = lerpf(v[2], v[3], fx);
+    const float c01 = lerpf(v[4], v[5], fx), c11 = lerpf(v[6], v[7], fx);
+    return lerpf(lerpf(c00, c10, fy), lerpf(c01, c11, fy), fz);
+}
+
+__device__ __forceinline__ void half_axis(float o, int l, int &h, float &fh) {
+    if (o < 0.5f) {
+        h = l - 1;
+        fh = o + 0.5f;
+    } else {
+        h = l;
+        fh = o - 0.5f;
+    }
+}
+
+__device__ inline void gather_global(const GridP &g, const float *const E[3], const float *const Bb[3],
+                              int ci, int cj, int ck, float ox, float oy, float oz, float Ep[3],
+                              float Bp[3]) {
+    int hx, hy, hz;
+    float fx, fy, fz;
+    half_axis(ox, ci, hx, fx);
+    half_axis(oy, cj, hy, fy);
+    half_axis(oz, ck, hz, fz);
+    Ep[0] = tri_global(g, E[0], hx, cj, ck, fx, oy, oz);
+    Ep[1] = tri_global(g, E[1], ci, hy, ck, ox, fy, oz);
+    Ep[2] = tri_global(g, E[2], ci, cj, hz, ox, oy, fz);
+    Bp[0] = tri_global(g, Bb[0], ci, hy, hz, ox, fy, fz);
+    Bp[1] = tri_global(g, Bb[1], hx, cj, hz, fx, oy, fz);
+    Bp[2] = tri_global(g, Bb[2], hx, hy, ck, fx, fy, oz);
+}
+
+// relativistic Boris push in FP32 (standard t/s rotation); returns 1/gamma of u+
+__device__ __forceinline__ float boris_f32(float &ux, float &uy, float &uz, const float E[3],
+                                           const float B[3], float r, float &gam) {
+    const float umx = fmaf(r, E[0], ux), umy = fmaf(r, E[1], uy), umz = fmaf(r, E[2], uz);
+    const float gm = sqrtf(fmaf(umx, umx, fmaf(umy, umy, fmaf(umz, umz, 1.f))));
+    const float ig = rcpf(gm);
+    const float tx = r * B[0] * ig, ty = r * B[1] * ig, tz = r * B[2] * ig;
+    const float sf = 2.f * rcpf(fmaf(tx, tx, fmaf(ty, ty, fmaf(tz, tz, 1.f))));
+    const float sx = sf * tx, sy = sf * ty, sz = sf * tz;
+    const float upx = umx + (umy * tz - umz * ty);
+    const float upy = umy + (umz * tx - umx * tz);
+    const float upz = umz + (umx * ty - umy * tx);
+    const float plx = umx + (upy * sz - upz * sy);
+    const float ply = umy + (upz * sx - upx * sz);
+    const float plz = umz + (upx * sy - upy * sx);
+    ux = fmaf(r, E[0], plx);
+    uy = fmaf(r, E[1], ply);
+    uz = fmaf(r, E[2], plz);
+    gam = sqrtf(fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.f))));
+    return rcpf(gam);
+}
+
+// Line integral of the bilinear CIC edge weights along a straight segment
+// inside one cell, given per axis the segment midpoint W (relative to that
+// cell) and its displacement D (cell units):
+// out[0..3] J_x edges (oy,oz) = (0,0),(1,0),(0,1),(1,1); out[4..7] J_y edges
+// (oz,ox); out[8..11] J_z edges (ox,oy).
+__device__ __forceinline__ void segment_weights(const float W[3], const float D[3],
+                                                const float amp_c[3], float out[12]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int b1 = (c + 1) % 3, b2 = (c + 2) % 3;
+        const float amp = amp_c[c] * D[c];
+        const float cr = D[b1] * D[b2] * (1.f / 12.f);
+        const float w1 = W[b1], w2 = W[b2];
+        out[4 * c + 0] = amp * ((1.f - w1) * (1.f - w2) + cr);
+        out[4 * c + 1] = amp * (w1 * (1.f - w2) - cr);
+        out[4 * c + 2] = amp * ((1.f - w1) * w2 - cr);
+        out[4 * c + 3] = amp * (w1 * w2 + cr);
+    }
+}
+
+// Midpoints and displacements of the ZigZag segments of a move from offset o
+// by dxi (end e = o + dxi as rounded, cell step dc per axis).  The
+// displacement is taken from dxi itself wherever the segment does not end on
+// a cell face, so that a small move keeps its full FP32 precision instead of
+// the difference of two rounded offsets.
+//   no crossing: one segment, W = o + dxi/2, D = dxi
+//   crossing:    relay xr = 1 (dc = +1), 0 (dc = -1), mid-point (dc = 0);
+//                segment A in the particle's cell, B in the cell + dc
+__device__ __forceinline__ void zigzag_split(const float o[3], const float dxi[3],
+                                             const float e[3], const int dc[3], float WA[3],
+                                             float DA[3], float WB[3], float DB[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (dc[a] == 0) {
+            DA[a] = DB[a] = 0.5f * dxi[a];
+            WA[a] = fmaf(0.25f, dxi[a], o[a]);
+            WB[a] = fmaf(0.75f, dxi[a], o[a]);
+        } else {
+            const float xr = dc[a] > 0 ? 1.f : 0.f;
+            DA[a] = xr - o[a];
+            WA[a] = 0.5f * (o[a] + xr);
+            DB[a] = e[a] - xr;
+            WB[a] = 0.5f * (xr + e[a]) - (float)dc[a];
+        }
+    }
+}
+
+// Per-axis move of a particle: new end point e (relative to its cell), cell
+// step dc in {-1,0,1} and canonical new offset in [0,1).  When e + 1 rounds
+// to 1 the particle is put at offset 0 of its own cell and e is set to 0,
+// so that deposit and stored state agree.
+__device__ __forceinline__ void move_axis(float o, float dxi, float &e, int &dc, float &no) {
+    e = o + dxi;
+    dc = 0;
+    if (e >= 1.f) {
+        dc = 1;
+        no = e - 1.f;
+    } else if (e < 0.f) {
+        const float t = e + 1.f;
+        if (t >= 1.f) {
+            e = 0.f;
+            no = 0.f;
+        } else {
+            dc = -1;
+            no = t;
+        }
+    } else {
+        no = e;
+    }
+}
+
+__device__ __forceinline__ bool new_cell(const GridP &g, int a, int c, int dc, int &out) {
+    int x = c + dc;
+    if (g.bc[a] == EMPIC_BC_PERIODIC) {
+        x = x < 0 ? x + g.n[a] : (x >= g.n[a] ? x - g.n[a] : x);
+    } else if (x < 0 || x >= g.n[a]) {
+        return false;
+    }
+    out = x;
+    return true;
+}
+
+// ---- LDS window versions ----
+__device__ __forceinline__ float tri_lds(const float *F, int i, int j, int k, float fx, float fy,
+                                         float fz) {
+    const float *p = F + i + FWX * (j + FWY * k);
+    const float c00 = lerpf(p[0], p[1], fx);
+    const float c10 = lerpf(p[FWX], p[FWX + 1], fx);
+    const float c01 = lerpf(p[FWX * FWY], p[FWX * FWY + 1], fx);
+    const float c11 = lerpf(p[FWX * FWY + FWX], p[FWX * FWY + FWX + 1], fx);
+    return lerpf(lerpf(c00, c10, fy), lerpf(c01, c11, fy), fz);
+}
+
+// J window offsets of the 12 edges of a cell, in segment_weights order
+__device__ __forceinline__ int edge_off(int q) {
+    // J_x (oy,oz); J_y (oz,ox); J_z (ox,oy)
+    const int c = q >> 2, b = q & 3, o1 = b & 1, o2 = b >> 1;
+    if (c == 0) return JW3 * 0 + o1 * JWX + o2 * JWX * JWY;
+    if (c == 1) return JW3 * 1 + o1 * JWX * JWY + o2;
+    return JW3 * 2 + o1 + o2 * JWX;
+}
+
+// Float -> int64 fixed point, round to nearest: the sum with 1.5 * 2^52 puts
+// the integer part of x * scale in the low mantissa bits (valid for
+// |x * scale| < 2^51, which the choice of the scale guarantees).
+__device__ __forceinline__ long long to_fixed(float x, double scale) {
+    const double t = fma((double)x, scale, 6755399441055744.0);
+    return __double_as_longlong(t) - 0x4338000000000000LL;
+}
+
+__device__ __forceinline__ int local_axis(const GridP &g, int a, int c, int wo) {
+    if (g.bc[a] == EMPIC_BC_PERIODIC) {
+        int m = c - wo - 1;
+        m = m < 0 ? m + g.n[a] : (m >= g.n[a] ? m - g.n[a] : m);
+        return m + 1;
+    }
+    return c - wo;
+}
+
+// Branch-free move of one axis (see move_axis).
+__device__ __forceinline__ void move_axis_sel(float o, float dx, float &e, int &dc, float &no) {
+    e = o + dx;
+    const bool up = e >= 1.f;
+    const bool dn = e < 0.f;
+    const float t = e + 1.f;
+    const bool rc = dn && t >= 1.f;  // e + 1 rounds to 1: stay at offset 0 of this cell
+    dc = up ? 1 : ((dn && !rc) ? -1 : 0);
+    no = up ? (e - 1.f) : (dn ? (rc ? 0.f : t) : e);
+    e = rc ? 0.f : e;
+}
+
+}  // namespace empic
