@@ -266,6 +266,15 @@ empic_status empic_state_tile_words(empic_sim *s, int64_t *words);
 empic_status empic_save_state(empic_sim *s, const empic_state *dst);
 empic_status empic_load_state(empic_sim *s, const empic_state *src);
 
+/* One step (as empic_step, without a sort) from state src into state dst:
+ * the handle's fields are set to src's, particles are read from src's arrays
+ * and written to dst's (the handle's own particle buffers are untouched),
+ * tile offsets and slot count are carried over, ids and per-particle weights
+ * copied unless dst shares src's arrays, and dst receives the new fields.
+ * For re-computing the states between checkpoints without copying them.
+ * src and dst must not share cell, offset or momentum arrays. */
+empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_state *dst);
+
 /* Vector-Jacobian product of one step taken from state st: lam holds the
  * adjoint of the state after the step on entry and that of st on return
  * (in place).  Transposed curls for the fields, deposit-as-gather of -dt

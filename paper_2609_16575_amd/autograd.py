@@ -6,11 +6,13 @@ storage order at the call), saving the full state every K steps.  With
 sort=True the particles are also sorted (recording the permutation) at every
 checkpoint, which is the counting sort every K steps of a long run; the
 Sim's own periodic sort must then be off (sort_every=0).
-Backward: for each checkpoint segment, from the last: reload its state,
-recompute the segment's states, apply the step adjoint (empic_step_vjp)
-backwards through them, then the adjoint of the segment's sort.  Memory: one
-saved state (and permutation) per K steps plus K states of the segment being
-reversed.  The Sim holds a recomputed state afterwards, not the final one.
+Backward: for each checkpoint segment, from the last: re-compute the
+segment's states from its checkpoint, each step written straight into the
+next state's arrays (empic_step_state), apply the step adjoint
+(empic_step_vjp) backwards through them, then the adjoint of the segment's
+sort.  Memory: one saved state (and permutation) per K steps plus K - 1
+states of the segment being reversed.  The Sim's fields hold a re-computed
+state afterwards, not the final one.
 """
 from __future__ import annotations
 
@@ -55,16 +57,19 @@ class PicRun(torch.autograd.Function):
                 lam["E"].copy_(gE)
             if gB is not None:
                 lam["B"].copy_(gB)
-            # slot 0 of a segment is its checkpoint
-            pool = [None] + [sim.alloc_state() for _ in range(min(K, nsteps) - 1)]
+            # slot 0 of a segment is its checkpoint; the re-computed states share
+            # its ids and weights, which no step changes
+            pool = [None] + [sim.alloc_state(particle_record=False)
+                             for _ in range(min(K, nsteps) - 1)]
             for seg in reversed(range(len(ctx.ckpts))):
                 start = seg * K
                 stop = min(start + K, nsteps)
-                sim.load_state(ctx.ckpts[seg])
-                states = [ctx.ckpts[seg]]
+                ck = ctx.ckpts[seg]
+                states = [ck]
                 for j in range(1, stop - start):
-                    sim.step(1)
-                    states.append(sim.save_state(pool[j]))
+                    st = dict(pool[j], id=ck["id"], w=ck["w"])
+                    sim.step_state(states[-1], st)
+                    states.append(st)
                 for st in reversed(states):
                     sim.step_vjp(st, lam)
                 if ctx.perms[seg] is not None:

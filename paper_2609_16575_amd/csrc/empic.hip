@@ -55,7 +55,7 @@ Layout layout(const empic_grid_desc *d, int max_species, long long max_capacity)
     L.fault = o;
     o += up_align(64);
     L.table = o;
-    o += up_align(sizeof(DevSpecies) * EMPIC_MAX_SPECIES);
+    o += up_align(sizeof(DevSpecies) * 2 * EMPIC_MAX_SPECIES);  // own sets; state-to-state
     L.partials = o;
     o += up_align((size_t)NQ * PSTRIDE * 8);
     L.result = o;
@@ -121,7 +121,8 @@ struct empic_sim {
     void *Bbar[3]{};
     uint32_t *fault = nullptr;
     unsigned long long *fallback = nullptr;
-    DevSpecies *table = nullptr;
+    DevSpecies *table = nullptr;   // the species' own buffer sets
+    DevSpecies *xtable = nullptr;  // (source, destination) state of empic_step_state
     double *partials = nullptr, *result = nullptr, *rho_cur = nullptr, *rho_prev = nullptr;
     int32_t *counts = nullptr, *scan_blocks = nullptr, *rank = nullptr;
     void *mur = nullptr;
@@ -237,8 +238,11 @@ void do_sort(empic_sim *s, int32_t *const *perm = nullptr) {
     s->need_sort = false;
 }
 
+// One PIC cycle.  FP32 path: particles are read from buffer set bit s of
+// rd_mask and written to bit s of wr_mask of table `tbl` (the species' own
+// sets by default).
 template <typename T>
-void one_step(empic_sim *s) {
+void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, int wr_mask = -1) {
     T *E[3], *B[3], *J[3], *Bb[3];
     field_ptrs<T>(s, E, B, J, Bb);
     const bool absorbing = s->g.bc[0] || s->g.bc[1] || s->g.bc[2];
@@ -251,6 +255,9 @@ void one_step(empic_sim *s) {
     if constexpr (sizeof(T) == 4) {
         unsigned mask = 0;
         for (int i = 0; i < s->nsp; ++i) mask |= (unsigned)s->sp[i].cur << i;
+        if (!tbl) tbl = s->table;
+        const unsigned rmask = rd_mask < 0 ? mask : (unsigned)rd_mask;
+        const unsigned wmask = wr_mask < 0 ? mask : (unsigned)wr_mask;
         // the fused kernel is timed by events attached to its own dispatch
         TimedEvent tp{nullptr, nullptr, 0};
         if (s->timing) {
@@ -259,7 +266,7 @@ void one_step(empic_sim *s) {
         }
         for (int pass = 0; pass < 2; ++pass)
             launch_push_fused(s->g, s->ti, (float *const *)E, (float *const *)Bb,
-                              (float *const *)J, s->table, s->nsp, mask, s->fault, s->fallback,
+                              (float *const *)J, tbl, s->nsp, rmask, wmask, s->fault, s->fallback,
                               s->fb_list, s->fb_count, (long long)s->max_capacity * s->max_species,
                               s->jscale, pass == 1, s->stream, pass == 0 ? tp.a : nullptr,
                               pass == 0 ? tp.b : nullptr);
@@ -378,6 +385,7 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
     s->fault = (uint32_t *)(s->ws + L.fault);
     s->fallback = (unsigned long long *)(s->ws + L.fault + 8);
     s->table = (DevSpecies *)(s->ws + L.table);
+    s->xtable = s->table + EMPIC_MAX_SPECIES;
     s->partials = (double *)(s->ws + L.partials);
     s->result = (double *)(s->ws + L.result);
     s->rho_cur = (double *)(s->ws + L.rho_cur);
@@ -870,6 +878,76 @@ empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adj
     }
     launch_step_vjp(s->g, s->ti, E, Bb, lE, lB, lEg, lBb, tB, sp, tiles, lx, lu, s->nsp, s->stream);
     return check_launch(s, "step_vjp");
+}
+
+empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_state *dst) {
+    EMPIC_GUARD(s);
+    if (!src || !dst || !s->bound) return fail(s, EMPIC_E_ARG, "null state or fields not bound");
+    if (fp64(s)) return fail(s, EMPIC_E_UNSUPPORTED, "states are for the FP32 path");
+    if (src == dst) return fail(s, EMPIC_E_ARG, "source and destination must differ");
+    const size_t fb = (size_t)s->g.V * 4;
+    for (int a = 0; a < 3; ++a)
+        if (!src->E[a] || !src->B[a] || !dst->E[a] || !dst->B[a])
+            return fail(s, EMPIC_E_ARG, "null state field");
+    for (int i = 0; i < s->nsp; ++i) {
+        const SpeciesState &S = s->sp[i];
+        if (S.capacity == 0) continue;
+        const empic_state *st[2] = {src, dst};
+        for (const empic_state *x : st) {
+            bool ok = x->cell[i] && x->id[i] && x->tiles[i];
+            for (int a = 0; a < 3; ++a) ok = ok && x->pos[i][a] && x->u[i][a];
+            if (S.desc.per_particle_w) ok = ok && x->w[i];
+            bool al = aligned16(x->cell[i]);
+            for (int a = 0; a < 3; ++a) al = al && aligned16(x->pos[i][a]) && aligned16(x->u[i][a]);
+            if (!ok) return fail(s, EMPIC_E_ARG, "null state particle array");
+            if (!al) return fail(s, EMPIC_E_ARG, "state particle arrays must be 16-byte aligned");
+        }
+        if (dst->cell[i] == src->cell[i]) return fail(s, EMPIC_E_ARG, "source and destination overlap");
+    }
+    // fields of the source into the handle's
+    for (int a = 0; a < 3; ++a) {
+        EMPIC_HIP(hipMemcpyAsync(s->E[a], src->E[a], fb, hipMemcpyDeviceToDevice, s->stream));
+        EMPIC_HIP(hipMemcpyAsync(s->B[a], src->B[a], fb, hipMemcpyDeviceToDevice, s->stream));
+    }
+    // species table: set 0 = source state, set 1 = destination state
+    const size_t tw = ((size_t)s->ti.ntiles + 2) * 4;
+    for (int i = 0; i < s->nsp; ++i) {
+        const SpeciesState &S = s->sp[i];
+        DevSpecies D;
+        const empic_state *st[2] = {src, dst};
+        for (int k = 0; k < 2; ++k) {
+            SpeciesP p = species_params(s, i, S.cur);
+            p.cell = (uint32_t *)st[k]->cell[i];
+            for (int a = 0; a < 3; ++a) {
+                p.pos[a] = st[k]->pos[i][a];
+                p.u[a] = st[k]->u[i][a];
+            }
+            p.id = st[k]->id[i];
+            p.w = S.desc.per_particle_w ? st[k]->w[i] : nullptr;
+            p.tile_off = st[k]->tiles[i];
+            p.count = st[k]->tiles[i] ? st[k]->tiles[i] + s->ti.ntiles + 1 : nullptr;
+            D.p[k] = p;
+        }
+        D.r = (float)(S.desc.q * s->g.dt / (2.0 * S.desc.m));
+        const double dV = s->g.d[0] * s->g.d[1] * s->g.d[2];
+        const double wsp = S.desc.per_particle_w ? 1.0 : S.desc.w;
+        for (int a = 0; a < 3; ++a) D.qc[a] = (float)(S.desc.q * wsp * s->g.d[a] / (s->g.dt * dV));
+        launch_write_species(s->xtable + i, D, s->stream);
+        if (S.capacity == 0) continue;
+        const size_t pb = (size_t)S.capacity * 4;
+        EMPIC_HIP(hipMemcpyAsync(dst->tiles[i], src->tiles[i], tw, hipMemcpyDeviceToDevice, s->stream));
+        if (dst->id[i] != src->id[i])
+            EMPIC_HIP(hipMemcpyAsync(dst->id[i], src->id[i], pb, hipMemcpyDeviceToDevice, s->stream));
+        if (S.desc.per_particle_w && dst->w[i] != src->w[i])
+            EMPIC_HIP(hipMemcpyAsync(dst->w[i], src->w[i], pb, hipMemcpyDeviceToDevice, s->stream));
+    }
+    one_step<float>(s, s->xtable, 0, (int)((1u << s->nsp) - 1u));
+    for (int a = 0; a < 3; ++a) {
+        EMPIC_HIP(hipMemcpyAsync(dst->E[a], s->E[a], fb, hipMemcpyDeviceToDevice, s->stream));
+        EMPIC_HIP(hipMemcpyAsync(dst->B[a], s->B[a], fb, hipMemcpyDeviceToDevice, s->stream));
+    }
+    s->rho_prev_step = -1;
+    return check_launch(s, "step_state");
 }
 
 void empic_tile_shape(int32_t out[3]) {

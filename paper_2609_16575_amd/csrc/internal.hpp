@@ -155,7 +155,7 @@ void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *p
 // kernel, true the follow-up pass over particles that left their tile window.
 void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
                        float *const Bbar[3], float *const J[3], const DevSpecies *tbl, int nsp,
-                       unsigned cur_mask, uint32_t *fault, unsigned long long *fallback,
+                       unsigned cur_mask, unsigned wr_mask, uint32_t *fault, unsigned long long *fallback,
                        int2 *fb_list, unsigned *fb_count, long long fb_cap, double jscale,
                        bool fallback_pass, hipStream_t s, hipEvent_t ev_start = nullptr,
                        hipEvent_t ev_stop = nullptr);

@@ -5,11 +5,11 @@
 // per-particle weight).  Offsets relative to the cell keep the rounding of a
 // position at 2^-24 of a cell wherever the particle is in the grid.
 //
-// k_push_fused: one workgroup (512 threads) per 8x8x8 tile of cells
+// k_push_fused: one workgroup (512 threads) per 8x8x4 tile of cells
 // (particles counting-sorted by tile, then cell).  The workgroup
 //   1. stages E^n and the centred B^n of the tile plus a halo into LDS
-//      (12^3 cells x 6 components),
-//   2. zeroes an LDS current window (13^3 x 3),
+//      (12 x 12 x 8 cells x 6 components),
+//   2. zeroes an LDS current window (13 x 13 x 9 edges x 3),
 //   3. streams its particles: each thread owns PPT = 4 consecutive particles,
 //      one 16-byte access per array, and for each does the staggered CIC
 //      gather from LDS (Sec. 2.5), the relativistic Boris push (Sec. 2.4), the
@@ -18,6 +18,9 @@
 //   4. adds the non-zero LDS current to global J with float atomics.
 // Particles that drifted more than MARGIN cells out of their tile since the
 // last sort are handled entirely through global memory (rare, counted).
+// Particles are read from one buffer set and written to another (the same
+// one for a step in place; a saved state and the next one when the states
+// between checkpoints of a differentiable run are re-computed).
 //
 // Algorithmic bytes per particle: 28 read + 28 written.
 #include <hip/hip_ext.h>
@@ -37,7 +40,8 @@ struct FusedArgs {
     float *J[3];
     const DevSpecies *tbl;  // species parameters (device memory)
     int nsp;
-    unsigned cur_mask;      // bit s: buffer set of species s
+    unsigned cur_mask;      // bit s: buffer set species s is read from
+    unsigned wr_mask;       // bit s: buffer set species s is written to (the same for a step in place)
     float dtd[3];           // dt / d_a
     double jscale, jinv;    // fixed-point scale of the LDS current window and its inverse
     uint32_t *fault;
@@ -195,6 +199,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     for (int s = 0; s < A.nsp; ++s) {
         const DevSpecies &D = A.tbl[s];
         const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
+        const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
         const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
         if (beg >= end) continue;
         const float r = D.r;
@@ -203,6 +208,9 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
         guint *CP = (guint *)S.cell;
         gfloat *OXP = (gfloat *)S.pos[0], *OYP = (gfloat *)S.pos[1], *OZP = (gfloat *)S.pos[2];
         gfloat *UXP = (gfloat *)S.u[0], *UYP = (gfloat *)S.u[1], *UZP = (gfloat *)S.u[2];
+        guint *CQ = (guint *)Wr.cell;
+        gfloat *OXQ = (gfloat *)Wr.pos[0], *OYQ = (gfloat *)Wr.pos[1], *OZQ = (gfloat *)Wr.pos[2];
+        gfloat *UXQ = (gfloat *)Wr.u[0], *UYQ = (gfloat *)Wr.u[1], *UZQ = (gfloat *)Wr.u[2];
         const int base0 = beg & ~(PPT - 1);
         for (int base = base0 + tid * PPT; base < end; base += PUSH_THREADS * PPT) {
             // one 16-byte (non-temporal) access per array: PPT = 4 consecutive particles
@@ -222,13 +230,11 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
             // pushed by k_push_fallback.
             float nux[PPT], nuy[PPT], nuz[PPT], nox[PPT], noy[PPT], noz[PPT];
             uint32_t ncell[PPT];
-            bool live[PPT];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int p = base + k;
                 const uint32_t c = c4[k];
                 const bool valid = p >= beg && p < end && c != DEAD;
-                live[k] = valid;
                 const int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
                 const float ox = ox4[k], oy = oy4[k], oz = oz4[k];
                 ncell[k] = c;
@@ -306,25 +312,27 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
             }
             if (base >= beg && base + PPT <= end) {
                 __builtin_nontemporal_store((vu4){ncell[0], ncell[1], ncell[2], ncell[3]},
-                                            (vu4 *)(CP + base));
-                __builtin_nontemporal_store((vf4){nox[0], nox[1], nox[2], nox[3]}, (vf4 *)(OXP + base));
-                __builtin_nontemporal_store((vf4){noy[0], noy[1], noy[2], noy[3]}, (vf4 *)(OYP + base));
-                __builtin_nontemporal_store((vf4){noz[0], noz[1], noz[2], noz[3]}, (vf4 *)(OZP + base));
-                __builtin_nontemporal_store((vf4){nux[0], nux[1], nux[2], nux[3]}, (vf4 *)(UXP + base));
-                __builtin_nontemporal_store((vf4){nuy[0], nuy[1], nuy[2], nuy[3]}, (vf4 *)(UYP + base));
-                __builtin_nontemporal_store((vf4){nuz[0], nuz[1], nuz[2], nuz[3]}, (vf4 *)(UZP + base));
+                                            (vu4 *)(CQ + base));
+                __builtin_nontemporal_store((vf4){nox[0], nox[1], nox[2], nox[3]}, (vf4 *)(OXQ + base));
+                __builtin_nontemporal_store((vf4){noy[0], noy[1], noy[2], noy[3]}, (vf4 *)(OYQ + base));
+                __builtin_nontemporal_store((vf4){noz[0], noz[1], noz[2], noz[3]}, (vf4 *)(OZQ + base));
+                __builtin_nontemporal_store((vf4){nux[0], nux[1], nux[2], nux[3]}, (vf4 *)(UXQ + base));
+                __builtin_nontemporal_store((vf4){nuy[0], nuy[1], nuy[2], nuy[3]}, (vf4 *)(UYQ + base));
+                __builtin_nontemporal_store((vf4){nuz[0], nuz[1], nuz[2], nuz[3]}, (vf4 *)(UZQ + base));
             } else {
+                // every slot of this tile, removed ones too (a step into another
+                // buffer set carries the whole record)
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    if (!live[k]) continue;
                     const int p = base + k;
-                    CP[p] = ncell[k];
-                    OXP[p] = nox[k];
-                    OYP[p] = noy[k];
-                    OZP[p] = noz[k];
-                    UXP[p] = nux[k];
-                    UYP[p] = nuy[k];
-                    UZP[p] = nuz[k];
+                    if (p < beg || p >= end) continue;
+                    CQ[p] = ncell[k];
+                    OXQ[p] = nox[k];
+                    OYQ[p] = noy[k];
+                    OZQ[p] = noz[k];
+                    UXQ[p] = nux[k];
+                    UYQ[p] = nuy[k];
+                    UZQ[p] = nuz[k];
                 }
             }
         }
@@ -362,19 +370,20 @@ __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
         const int2 e = A.fb_list[t];
         const DevSpecies &D = A.tbl[e.x];
         const SpeciesP &S = D.p[(A.cur_mask >> e.x) & 1u];
+        const SpeciesP &Wr = D.p[(A.wr_mask >> e.x) & 1u];
         const int p = e.y;
         uint32_t c = S.cell[p];
         float ox = ((float *)S.pos[0])[p], oy = ((float *)S.pos[1])[p], oz = ((float *)S.pos[2])[p];
         float ux = ((float *)S.u[0])[p], uy = ((float *)S.u[1])[p], uz = ((float *)S.u[2])[p];
         const float wq = (S.per_particle_w && S.w) ? ((const float *)S.w)[p] : 1.f;
         particle_global(A, D, c, ox, oy, oz, ux, uy, uz, wq, fbits);
-        S.cell[p] = c;
-        ((float *)S.pos[0])[p] = ox;
-        ((float *)S.pos[1])[p] = oy;
-        ((float *)S.pos[2])[p] = oz;
-        ((float *)S.u[0])[p] = ux;
-        ((float *)S.u[1])[p] = uy;
-        ((float *)S.u[2])[p] = uz;
+        Wr.cell[p] = c;
+        ((float *)Wr.pos[0])[p] = ox;
+        ((float *)Wr.pos[1])[p] = oy;
+        ((float *)Wr.pos[2])[p] = oz;
+        ((float *)Wr.u[0])[p] = ux;
+        ((float *)Wr.u[1])[p] = uy;
+        ((float *)Wr.u[2])[p] = uz;
     }
     if (fbits) atomicOr(A.fault, fbits);
     // reset the list once every workgroup has read the count
@@ -691,7 +700,7 @@ void launch_write_species(DevSpecies *dst, const DevSpecies &v, hipStream_t s) {
 
 void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
                        float *const Bbar[3], float *const J[3], const DevSpecies *tbl, int nsp,
-                       unsigned cur_mask, uint32_t *fault, unsigned long long *fallback,
+                       unsigned cur_mask, unsigned wr_mask, uint32_t *fault, unsigned long long *fallback,
                        int2 *fb_list, unsigned *fb_count, long long fb_cap, double jscale,
                        bool fallback_pass, hipStream_t s, hipEvent_t ev_start,
                        hipEvent_t ev_stop) {
@@ -707,6 +716,7 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
     A.tbl = tbl;
     A.nsp = nsp;
     A.cur_mask = cur_mask;
+    A.wr_mask = wr_mask;
     A.jscale = jscale;
     A.jinv = 1.0 / jscale;
     A.fault = fault;

@@ -201,8 +201,10 @@ class Sim:
         return n.value
 
     # -- differentiable runs (FP32 path, periodic grid) ----------------------------
-    def alloc_state(self):
-        """Device tensors for one saved state (fields + the full particle record)."""
+    def alloc_state(self, particle_record=True):
+        """Device tensors for one saved state (fields + the full particle record).
+        particle_record=False leaves out ids and weights (for states that borrow
+        another state's, which no step changes)."""
         t = self.torch
         if not hasattr(self, "_tile_words"):
             n = C.c_int64()
@@ -214,9 +216,10 @@ class Sim:
             st["cell"].append(t.empty(cap, dtype=t.int32, device=self.dev))
             st["pos"].append(t.empty((3, cap), dtype=self.dtype, device=self.dev))
             st["u"].append(t.empty((3, cap), dtype=self.dtype, device=self.dev))
-            st["id"].append(t.empty(cap, dtype=t.int32, device=self.dev))
             has_w = self.bufs[i][0]["w"] is not None
-            st["w"].append(t.empty(cap, dtype=self.dtype, device=self.dev) if has_w else None)
+            rec = particle_record
+            st["id"].append(t.empty(cap, dtype=t.int32, device=self.dev) if rec else None)
+            st["w"].append(t.empty(cap, dtype=self.dtype, device=self.dev) if has_w and rec else None)
             st["tiles"].append(t.empty(self._tile_words, dtype=t.int32, device=self.dev))
         return st
 
@@ -235,7 +238,7 @@ class Sim:
             S.B[a] = _ptr(st["B"][a])
         for i in range(len(self.caps)):
             S.cell[i] = _ptr(st["cell"][i])
-            S.id[i] = _ptr(st["id"][i])
+            S.id[i] = _ptr(st["id"][i]) if st["id"][i] is not None else None
             S.w[i] = _ptr(st["w"][i]) if st["w"][i] is not None else None
             S.tiles[i] = _ptr(st["tiles"][i])
             for a in range(3):
@@ -263,6 +266,11 @@ class Sim:
     def load_state(self, st):
         S = self._state_struct(st)
         LB.check(self.h, self.L.empic_load_state(self.h, C.byref(S)))
+
+    def step_state(self, src, dst):
+        """One step from state src into state dst (the Sim's particle buffers untouched)."""
+        S, D = self._state_struct(src), self._state_struct(dst)
+        LB.check(self.h, self.L.empic_step_state(self.h, C.byref(S), C.byref(D)))
 
     def step_vjp(self, st, lam):
         """In place: lam (adjoint after the step taken from st) -> adjoint of st."""

@@ -354,3 +354,88 @@ def test_gradients_with_sorts_at_checkpoints():
     assert abs(fdE[0] - fdE[1]) <= 3e-5 * abs(fdE[1]), ("piece switch inside +-h", fdE)
     assert abs(gU_s - fdU[1]) <= 1e-4 * abs(fdU[1]), (gU_s, fdU, L_s)
     assert abs(gE_s - fdE[1]) <= 1e-4 * abs(fdE[1]), (gE_s, fdE, L_s)
+
+
+def _hot_absorbing(seed=31):
+    """Hot electrons with per-particle weights in an absorbing 16 x 16 x 8
+    box: particles leave through the faces within a few steps."""
+    rng = np.random.default_rng(seed)
+    n, d = (16, 16, 8), (1.0, 1.0, 1.0)
+    N = 6000
+    pos = rng.random((N, 3)) * np.asarray(n, float)
+    u = 0.6 * rng.standard_normal((N, 3))
+    wpp = 0.5 + rng.random(N)
+    sp = W.SpeciesInit("e", -1.0, 1.0, 1.0, pos, u, wpp=wpp)
+    return W.Workload("hot_abs", n, d, W.courant_dt(d), (W.ABSORBING,) * 3, [sp], sort_every=0)
+
+
+def _global_cells(st, i, n):
+    """Positions in cell units (NaN for removed particles) of state st."""
+    c = st["cell"][i].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    ijk = np.stack([c & 0x7FF, (c >> 11) & 0x7FF, c >> 22], axis=1).astype(np.float64)
+    x = ijk + st["pos"][i].double().cpu().numpy().T
+    x[c == 0xFFFFFFFF] = np.nan
+    return x
+
+
+@pytest.mark.parametrize("case", ["periodic_two_species", "absorbing_weighted"])
+def test_step_state_matches_step_in_place(case):
+    """empic_step_state from a saved state equals loading it and stepping in
+    place: after one step the particle records bit for bit (the LDS deposit
+    sums are exact; only the order of J's float flush differs), after four
+    to rounding (the fields differ in that order), removed particles
+    included; the handle's own particle buffers stay untouched."""
+    w = W.thermal_two_species(n=(16, 16, 16), ppc=4) if case == "periodic_two_species" \
+        else _hot_absorbing()
+    g = _sim(w, sort_every=0)
+    g.sort()
+    g.step(2)
+    st0 = g.save_state()
+    own = [g.particles(i) for i in range(len(w.species))]
+    nsp = len(w.species)
+    a, b = g.save_state(), g.alloc_state()
+    g.step_state(a, b)
+    for i in range(nsp):  # own buffers untouched
+        P, U, I = g.particles(i)
+        assert np.array_equal(P, own[i][0]) and np.array_equal(U, own[i][1])
+    g.load_state(st0)
+    g.step(1)
+    ref = g.save_state()
+    for i in range(nsp):
+        N = int(ref["tiles"][i][-1].item())  # slot count; later slots are not state
+        assert torch_equal(b["tiles"][i], ref["tiles"][i]), (case, i)
+        for k in ("cell", "pos", "u", "id", "w"):
+            if b[k][i] is not None:
+                assert torch_equal(b[k][i][..., :N], ref[k][i][..., :N]), (case, k, i)
+    for k in ("E", "B"):
+        x, y = b[k].double().cpu().numpy(), ref[k].double().cpu().numpy()
+        assert np.abs(x - y).max() <= 1e-6 * max(np.abs(y).max(), 1e-30), (case, k)
+    # three more steps state to state, against the in-place run (which is
+    # reloaded: a state-to-state step leaves its fields in the handle)
+    for _ in range(3):
+        g.step_state(b, a)
+        a, b = b, a
+    g.load_state(ref)
+    g.step(3)
+    ref = g.save_state()
+    for i in range(nsp):
+        N = int(ref["tiles"][i][-1].item())
+        xa, xr = _global_cells(b, i, w.n)[:N], _global_cells(ref, i, w.n)[:N]
+        assert np.array_equal(np.isnan(xa), np.isnan(xr)), case
+        live = ~np.isnan(xr[:, 0])
+        dx = xa[live] - xr[live]
+        dx -= np.asarray(w.n) * np.round(dx / np.asarray(w.n))
+        assert np.abs(dx).max() <= 1e-5, (case, i, np.abs(dx).max())
+        ua, ur = b["u"][i][:, :N].double().cpu().numpy(), ref["u"][i][:, :N].double().cpu().numpy()
+        assert np.abs(ua - ur)[:, live].max() <= 1e-5 * np.abs(ur[:, live]).max(), (case, i)
+    if case == "absorbing_weighted":
+        N = int(ref["tiles"][0][-1].item())
+        assert int((ref["cell"][0][:N] == -1).sum().item()) > 100  # particles were removed
+    for k in ("E", "B"):
+        x, y = b[k].double().cpu().numpy(), ref[k].double().cpu().numpy()
+        assert np.abs(x - y).max() <= 1e-5 * max(np.abs(y).max(), 1e-30), (case, k)
+
+
+def torch_equal(x, y):
+    import torch
+    return bool(torch.equal(x, y))
