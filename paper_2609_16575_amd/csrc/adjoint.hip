@@ -8,20 +8,22 @@
 // with Cf / Cb the forward / backward difference curls of the Yee scheme
 // (Sec. 2.3; on a periodic grid Cf^T = Cb).  Given the adjoints of
 // (E', B', x', u') the kernels below return those of (E, B, x, u):
-//   k_adj_fused: one workgroup per tile of the particle sort, like the step's
-//     fused kernel.  Per particle it re-computes the forward step with the
-//     step kernel's own arithmetic (gather from the staged E, Bbar window,
-//     Boris, move), then reverses it: the ZigZag deposit adjoint gathers
-//     -dt lam_E' on the edges the particle touched (Sec. 2.5) from a staged
-//     lam_E' window, the position and Boris adjoints follow, and the gather
-//     adjoint scatters lam_Ep, lam_Bp onto the six Yee sub-grids while its
-//     derivative in x adds to lam_x.  The scatter accumulates in an LDS window
-//     in int64 fixed point (integer LDS atomics are ~20x cheaper than float
-//     ones here) whose scale follows the largest |lam| met so far in the tile
-//     (a block-wide exponent; the window is shifted down when it grows), and
-//     the window is added to global memory once per tile.  Each round gives
-//     the 64 lanes of a wave particles 32 apart in the tile, so that lanes
-//     seldom hit the same LDS word in one atomic instruction.
+//   k_adj_particles (pass 1): one workgroup per tile of the particle sort,
+//     like the step's fused kernel.  Per particle it re-computes the forward
+//     step with the step kernel's own arithmetic (gather from the staged E,
+//     Bbar window, Boris, move), then reverses it: the ZigZag deposit adjoint
+//     gathers -dt lam_E' on the edges the particle touched (Sec. 2.5) from a
+//     staged lam_E' window, the position and Boris adjoints follow, and the
+//     gather's derivative in x adds to lam_x.  lam_Ep, lam_Bp go to per-slot
+//     scratch, with a per-tile exponent bounding them.
+//   k_adj_scatter (pass 2): the gather adjoint, i.e. lam_Ep, lam_Bp scattered
+//     onto the six Yee sub-grids, accumulated per tile in an LDS window in
+//     int64 fixed point scaled by the tile's exponent (integer LDS atomics are
+//     an order of magnitude cheaper than float ones here), then added to
+//     global memory once per tile.  Lanes of a wave take particles in
+//     different cells, so that they seldom hit one LDS word together.
+//   k_adj_fallback: particles that drifted out of their tile window since the
+//     sort, through global memory.
 //   k_adj_bprime: lam_B'_t = lam_B' + dt Cf lam_E' + lam_Bbar / 2,
 //                 lam_B = lam_B'_t + lam_Bbar / 2;
 //   k_adj_e:      lam_E = lam_E' + lam_Egather - dt Cb lam_B'_t.
@@ -35,10 +37,15 @@ namespace empic {
 
 namespace {
 
-constexpr int ADJ_THREADS = 512;
-constexpr int APPT = 2;  // consecutive particles per thread and round
+constexpr int ADJ_THREADS = 256;   // particle pass
+constexpr int SCAT_THREADS = 512;  // scatter pass
+constexpr int APPT = 1;            // particles per thread and pass-1 iteration
+constexpr int SPPT = 2;            // consecutive particles per thread in pass 2
+constexpr int EB = 31;             // fixed point: contributions below 2^EB
 typedef float vfA __attribute__((ext_vector_type(APPT)));
 typedef uint32_t vuA __attribute__((ext_vector_type(APPT)));
+typedef float vfS __attribute__((ext_vector_type(SPPT)));
+typedef uint32_t vuS __attribute__((ext_vector_type(SPPT)));
 constexpr int NO_EXP = -100000;
 
 __device__ __forceinline__ int pwrap(int x, int n) {
@@ -154,6 +161,11 @@ struct AdjArgs {
     float dtd[3];
     float inv_d[3];
     float dt;
+    int *fb_list;        // slots of this species' particles outside their tile window
+    unsigned *fb_count;  // entries in fb_list
+    long long fb_cap;
+    float *l6[6];        // per slot: lam_Ep, lam_Bp from pass 1 (scratch)
+    int *tile_exp;       // per tile: exponent bound of its lam_Ep, lam_Bp
 };
 
 struct AdjSpecies {
@@ -215,14 +227,13 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
         move_axis_sel(o[a], dx[a], e[a], dc[a], no);
     }
     // ---- deposit adjoint: lam_J = -dt lam_E' on the touched edges ----
+    // Always as two ZigZag segments: a move inside one cell has its relay at
+    // the mid-point on every axis, and the line integral over the two halves
+    // equals the step kernel's single straight segment, so one code path
+    // serves every lane of a wave.
     const float ampc[3] = {S.qc[0] * wq, S.qc[1] * wq, S.qc[2] * wq};
-    float l1[3] = {0.f, 0.f, 0.f}, l2[3] = {0.f, 0.f, 0.f};
-    if ((dc[0] | dc[1] | dc[2]) == 0) {
-        // one straight segment; midpoint and displacement from the unrounded dx
-        const float W[3] = {fmaf(0.5f, dx[0], o[0]), fmaf(0.5f, dx[1], o[1]),
-                            fmaf(0.5f, dx[2], o[2])};
-        segment_vjp(acc, l, W, dx, ampc, l1, l2);
-    } else {
+    float l1[3], l2[3];
+    {
         float WA[3], DA[3], WB[3], DB[3];
         float lsA[3] = {0.f, 0.f, 0.f}, leA[3] = {0.f, 0.f, 0.f};
         float lsB[3] = {0.f, 0.f, 0.f}, leB[3] = {0.f, 0.f, 0.f};
@@ -303,16 +314,18 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
     }
 }
 
-__device__ __forceinline__ void tri_weights(const float f[3], float w[8]) {
-    const float gx = 1.f - f[0], gy = 1.f - f[1], gz = 1.f - f[2];
-    w[0] = gx * gy * gz;
-    w[1] = f[0] * gy * gz;
-    w[2] = gx * f[1] * gz;
-    w[3] = f[0] * f[1] * gz;
-    w[4] = gx * gy * f[2];
-    w[5] = f[0] * gy * f[2];
-    w[6] = gx * f[1] * f[2];
-    w[7] = f[0] * f[1] * f[2];
+// v times the 8 trilinear weights of fractions f (corner o: bit 0 x, 1 y, 2 z)
+__device__ __forceinline__ void tri_weights(const float f[3], float v, float w[8]) {
+    const float z0 = v * (1.f - f[2]), z1 = v * f[2];
+    const float y00 = z0 * (1.f - f[1]), y10 = z0 * f[1], y01 = z1 * (1.f - f[1]), y11 = z1 * f[1];
+    w[0] = y00 * (1.f - f[0]);
+    w[1] = y00 * f[0];
+    w[2] = y10 * (1.f - f[0]);
+    w[3] = y10 * f[0];
+    w[4] = y01 * (1.f - f[0]);
+    w[5] = y01 * f[0];
+    w[6] = y11 * (1.f - f[0]);
+    w[7] = y11 * f[0];
 }
 
 // gather-as-scatter of one particle straight into global memory (float atomics)
@@ -324,36 +337,17 @@ __device__ void scatter_global(const GlobAcc &G, float *const lEg[3], float *con
         int c[3];
         float f[3], w[8];
         stagger(q, l, o, c, f);
-        tri_weights(f, w);
+        tri_weights(f, l6[q], w);
         float *dst = q < 3 ? lEg[q] : lBb[q - 3];
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            atomicAdd(dst + G.idx(c[0] + (k & 1), c[1] + ((k >> 1) & 1), c[2] + (k >> 2)),
-                      l6[q] * w[k]);
+            atomicAdd(dst + G.idx(c[0] + (k & 1), c[1] + ((k >> 1) & 1), c[2] + (k >> 2)), w[k]);
     }
 }
 
-__global__ __launch_bounds__(ADJ_THREADS, 1) void k_adj_fused(AdjArgs A, AdjSpecies S) {
-    __shared__ float sF[6 * FW3];
-    __shared__ float sL[3 * JW3];
-    __shared__ unsigned long long sA[6 * FW3];
-    __shared__ int sG[3][16];
-    __shared__ int sE;
-
-    const GridP &g = A.g;
-    const int nb8 = gridDim.x >> 3;
-    const int tile = (blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);  // XCD-contiguous tiles
-    if (tile >= A.ti.ntiles) return;
-    const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
-    if (beg >= end) return;
-
-    const int tx = tile % A.ti.nt[0];
-    const int tyz = tile / A.ti.nt[0];
-    const int ty = tyz % A.ti.nt[1], tz = tyz / A.ti.nt[1];
-    const int wo[3] = {tx * TX - MARGIN - 1, ty * TY - MARGIN - 1, tz * TZ - MARGIN - 1};
+// window-row tables of a tile: global x index, y*ext0, z*ext0*ext1 (periodic)
+__device__ __forceinline__ void window_rows(const GridP &g, const int wo[3], int sG[3][16]) {
     const int tid = threadIdx.x;
-
-    // global index tables of the window rows: x index, y*ext0, z*ext0*ext1
     if (tid < 3 * 16) {
         const int a = tid / 16, r = tid % 16;
         const int wl = a == 0 ? JWX : (a == 1 ? JWY : JWZ);
@@ -362,6 +356,40 @@ __global__ __launch_bounds__(ADJ_THREADS, 1) void k_adj_fused(AdjArgs A, AdjSpec
             sG[a][r] = pwrap(wo[a] + r, g.n[a]) * mul;
         }
     }
+}
+
+__device__ __forceinline__ int tile_of_block(const TileInfo &ti, int wo[3]) {
+    const int nb8 = gridDim.x >> 3;
+    const int tile = (blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);  // XCD-contiguous tiles
+    const int tx = tile % ti.nt[0];
+    const int tyz = tile / ti.nt[0];
+    const int ty = tyz % ti.nt[1], tz = tyz / ti.nt[1];
+    wo[0] = tx * TX - MARGIN - 1;
+    wo[1] = ty * TY - MARGIN - 1;
+    wo[2] = tz * TZ - MARGIN - 1;
+    return tile;
+}
+
+// Pass 1, one workgroup per tile: every particle's adjoint up to the gather
+// scatter (lam_x, lam_u updated in place; lam_Ep, lam_Bp to the per-slot
+// arrays A.l6, zero for particles handled elsewhere) and the tile's exponent:
+// all its |lam_Ep|, |lam_Bp| < 2^tile_exp.
+// three waves per SIMD measure faster than two without spills
+__global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, AdjSpecies S) {
+    __shared__ float sF[6 * FW3];
+    __shared__ float sL[3 * JW3];
+    __shared__ int sG[3][16];
+    __shared__ int sE;
+
+    const GridP &g = A.g;
+    int wo[3];
+    const int tile = tile_of_block(A.ti, wo);
+    if (tile >= A.ti.ntiles) return;
+    const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
+    if (beg >= end) return;
+    const int tid = threadIdx.x;
+    window_rows(g, wo, sG);
+    if (tid == 0) sE = NO_EXP;
     __syncthreads();
     for (int e = tid; e < 6 * FW3; e += ADJ_THREADS) {
         const int comp = e / FW3;
@@ -371,7 +399,6 @@ __global__ __launch_bounds__(ADJ_THREADS, 1) void k_adj_fused(AdjArgs A, AdjSpec
         const int ly = r2 / FWX, lx = r2 - ly * FWX;
         const float *src = comp < 3 ? A.E[comp] : A.Bb[comp - 3];
         sF[e] = src[sG[0][lx] + sG[1][ly] + sG[2][lz]];
-        sA[e] = 0ull;
     }
     for (int e = tid; e < 3 * JW3; e += ADJ_THREADS) {
         const int comp = e / JW3;
@@ -381,147 +408,169 @@ __global__ __launch_bounds__(ADJ_THREADS, 1) void k_adj_fused(AdjArgs A, AdjSpec
         const int ly = r2 / JWX, lx = r2 - ly * JWX;
         sL[e] = A.lJ[comp][sG[0][lx] + sG[1][ly] + sG[2][lz]];
     }
+    __syncthreads();
 
     const LdsAcc lacc{sF, sL};
     const GlobAcc gacc{g.n[0], g.n[1], g.n[2], g.ext[0], g.ext[1],
                        {A.E[0], A.E[1], A.E[2]}, {A.Bb[0], A.Bb[1], A.Bb[2]},
                        {A.lJ[0], A.lJ[1], A.lJ[2]}};
     constexpr int LHI_X = TX + 2 * MARGIN, LHI_Y = TY + 2 * MARGIN, LHI_Z = TZ + 2 * MARGIN;
-    // fixed point: every contribution is below 2^EB in units of the scale and
-    // one entry takes at most one per particle of the tile, so |sum| < 2^61
-    int nbits = 0;
-    while (nbits < 31 && (1ll << nbits) <= (long long)(end - beg)) ++nbits;
-    const int EB = min(50, 61 - nbits);
-    int ecur = NO_EXP;  // block-uniform exponent of the window's scale
-    const int lane = tid & 63, wave = tid >> 6;
-    const int q0 = lane * (APPT * (ADJ_THREADS / 64)) + wave * APPT;
-    const int base0 = beg & ~(APPT - 1);
-
-    for (int rb = base0; rb < end; rb += ADJ_THREADS * APPT) {
-        if (tid == 0) sE = NO_EXP;
-        __syncthreads();
-        const int base = rb + q0;
-        float l6s[APPT][6], os[APPT][3];
-        int ls[APPT];  // window-local cell, packed; -1 = nothing to scatter here
-        int emax = NO_EXP;
+    int emax = NO_EXP;
+    for (int base = (beg & ~(APPT - 1)) + tid * APPT; base < end; base += ADJ_THREADS * APPT) {
+        const vuA c4 = *(const vuA *)(S.cell + base);
+        const vfA ox4 = *(const vfA *)(S.pos[0] + base), oy4 = *(const vfA *)(S.pos[1] + base),
+                  oz4 = *(const vfA *)(S.pos[2] + base);
+        const vfA ux4 = *(const vfA *)(S.u[0] + base), uy4 = *(const vfA *)(S.u[1] + base),
+                  uz4 = *(const vfA *)(S.u[2] + base);
+        vfA w4 = (vfA)(1.f);
+        if (S.w) w4 = *(const vfA *)(S.w + base);
+        vfA lx4[3], lu4[3], l64[6];
 #pragma unroll
-        for (int k = 0; k < APPT; ++k) ls[k] = -1;
-        if (base < end) {
-            const vuA c4 = *(const vuA *)(S.cell + base);
-            const vfA ox4 = *(const vfA *)(S.pos[0] + base), oy4 = *(const vfA *)(S.pos[1] + base),
-                      oz4 = *(const vfA *)(S.pos[2] + base);
-            const vfA ux4 = *(const vfA *)(S.u[0] + base), uy4 = *(const vfA *)(S.u[1] + base),
-                      uz4 = *(const vfA *)(S.u[2] + base);
-            vfA w4 = (vfA)(1.f);
-            if (S.w) w4 = *(const vfA *)(S.w + base);
-            vfA lx4[3], lu4[3];
+        for (int a = 0; a < 3; ++a) {
+            lx4[a] = *(const vfA *)(S.lx[a] + base);
+            lu4[a] = *(const vfA *)(S.lu[a] + base);
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) l64[q] = (vfA)(0.f);
+#pragma unroll
+        for (int k = 0; k < APPT; ++k) {
+            const int p = base + k;
+            const uint32_t c = c4[k];
+            if (p < beg || p >= end || c == DEAD) continue;
+            const float o[3] = {ox4[k], oy4[k], oz4[k]};
+            const float u[3] = {ux4[k], uy4[k], uz4[k]};
+            float lx[3] = {lx4[0][k], lx4[1][k], lx4[2][k]};
+            float lu[3] = {lu4[0][k], lu4[1][k], lu4[2][k]};
+            float l6[6];
+            const int gl[3] = {cell_i(c), cell_j(c), cell_k(c)};
+            const int wl[3] = {local_axis(g, 0, gl[0], wo[0]), local_axis(g, 1, gl[1], wo[1]),
+                               local_axis(g, 2, gl[2], wo[2])};
+            const bool inwin = wl[0] >= 1 && wl[0] <= LHI_X && wl[1] >= 1 && wl[1] <= LHI_Y &&
+                               wl[2] >= 1 && wl[2] <= LHI_Z;
+            if (inwin) {
+                particle_vjp(lacc, A, S, wl, o, u, w4[k], lx, lu, l6);
+                float m = 0.f;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) m = fmaxf(m, fabsf(l6[q]));
+                if (m > 0.f && m <= 3.0e38f) {
+                    int ex;
+                    frexpf(m, &ex);  // m < 2^ex
+                    emax = max(emax, ex);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) l64[q][k] = l6[q];
+                } else if (m != 0.f) {
+                    // not finite: let it reach the result through global memory
+                    scatter_global(gacc, A.lEg, A.lBb, gl, o, l6);
+                }
+            } else {
+                // drifted more than MARGIN cells out of its tile since the sort:
+                // listed for k_adj_fallback (its adjoints stay as loaded here)
+                const unsigned slot = atomicAdd(A.fb_count, 1u);
+                if (slot < (unsigned long long)A.fb_cap) {
+                    A.fb_list[slot] = p;
+                    continue;
+                }
+                particle_vjp(gacc, A, S, gl, o, u, w4[k], lx, lu, l6);
+                scatter_global(gacc, A.lEg, A.lBb, gl, o, l6);
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                lx4[a] = *(const vfA *)(S.lx[a] + base);
-                lu4[a] = *(const vfA *)(S.lu[a] + base);
+                lx4[a][k] = lx[a];
+                lu4[a][k] = lu[a];
             }
+        }
+        if (base >= beg && base + APPT <= end) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                *(vfA *)(S.lx[a] + base) = lx4[a];
+                *(vfA *)(S.lu[a] + base) = lu4[a];
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) *(vfA *)(A.l6[q] + base) = l64[q];
+        } else {
 #pragma unroll
             for (int k = 0; k < APPT; ++k) {
                 const int p = base + k;
-                const uint32_t c = c4[k];
-                if (p < beg || p >= end || c == DEAD) continue;
-                const float o[3] = {ox4[k], oy4[k], oz4[k]};
-                const float u[3] = {ux4[k], uy4[k], uz4[k]};
-                float lx[3] = {lx4[0][k], lx4[1][k], lx4[2][k]};
-                float lu[3] = {lu4[0][k], lu4[1][k], lu4[2][k]};
-                float l6[6];
-                const int gl[3] = {cell_i(c), cell_j(c), cell_k(c)};
-                const int wl[3] = {local_axis(g, 0, gl[0], wo[0]), local_axis(g, 1, gl[1], wo[1]),
-                                   local_axis(g, 2, gl[2], wo[2])};
-                const bool inwin = wl[0] >= 1 && wl[0] <= LHI_X && wl[1] >= 1 && wl[1] <= LHI_Y &&
-                                   wl[2] >= 1 && wl[2] <= LHI_Z;
-                if (inwin) {
-                    particle_vjp(lacc, A, S, wl, o, u, w4[k], lx, lu, l6);
-                    float m = 0.f;
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) m = fmaxf(m, fabsf(l6[q]));
-                    if (m > 0.f && m <= 3.0e38f) {
-                        int ex;
-                        frexpf(m, &ex);  // m < 2^ex
-                        emax = max(emax, ex);
-                        ls[k] = wl[0] | (wl[1] << 8) | (wl[2] << 16);
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) l6s[k][q] = l6[q];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) os[k][a] = o[a];
-                    } else if (m != 0.f) {
-                        // not finite: let it reach the result through global memory
-                        scatter_global(gacc, A.lEg, A.lBb, gl, o, l6);
-                    }
-                } else {
-                    // drifted more than MARGIN cells out of its tile since the sort
-                    particle_vjp(gacc, A, S, gl, o, u, w4[k], lx, lu, l6);
-                    scatter_global(gacc, A.lEg, A.lBb, gl, o, l6);
-                }
-                lx4[0][k] = lx[0];
-                lx4[1][k] = lx[1];
-                lx4[2][k] = lx[2];
-                lu4[0][k] = lu[0];
-                lu4[1][k] = lu[1];
-                lu4[2][k] = lu[2];
-            }
-            if (base >= beg && base + APPT <= end) {
+                if (p < beg || p >= end) continue;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    *(vfA *)(S.lx[a] + base) = lx4[a];
-                    *(vfA *)(S.lu[a] + base) = lu4[a];
+                    S.lx[a][p] = lx4[a][k];
+                    S.lu[a][p] = lu4[a][k];
                 }
-            } else {
 #pragma unroll
-                for (int k = 0; k < APPT; ++k) {
-                    const int p = base + k;
-                    if (p < beg || p >= end) continue;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        S.lx[a][p] = lx4[a][k];
-                        S.lu[a][p] = lu4[a][k];
-                    }
-                }
+                for (int q = 0; q < 6; ++q) A.l6[q][p] = l64[q][k];
             }
         }
-        if (emax != NO_EXP) atomicMax(&sE, emax);
-        __syncthreads();
-        const int enew = max(ecur, sE);
-        if (ecur != NO_EXP && enew > ecur) {
-            // the scale drops: shift what the window holds to the new one
-            const int sh = min(enew - ecur, 63);
-            for (int e = tid; e < 6 * FW3; e += ADJ_THREADS)
-                sA[e] = (unsigned long long)((long long)sA[e] >> sh);
-            __syncthreads();
-        }
-        ecur = enew;
-        if (ecur != NO_EXP) {
-            const double scale = ldexp(1.0, EB - ecur);
-#pragma unroll
-            for (int k = 0; k < APPT; ++k) {
-                if (ls[k] < 0) continue;
-                const int wl[3] = {ls[k] & 0xFF, (ls[k] >> 8) & 0xFF, ls[k] >> 16};
-#pragma unroll
-                for (int q = 0; q < 6; ++q) {
-                    int c[3];
-                    float f[3], w[8];
-                    stagger(q, wl, os[k], c, f);
-                    tri_weights(f, w);
-                    const float v = l6s[k][q];
-                    unsigned long long *dst = sA + q * FW3 + c[0] + FWX * (c[1] + FWY * c[2]);
-#pragma unroll
-                    for (int o = 0; o < 8; ++o)
-                        atomicAdd(dst + (o & 1) + FWX * (((o >> 1) & 1) + FWY * (o >> 2)),
-                                  (unsigned long long)to_fixed(v * w[o], scale));
-                }
-            }
-        }
-        __syncthreads();
     }
-    if (ecur == NO_EXP) return;
+    if (emax != NO_EXP) atomicMax(&sE, emax);
+    __syncthreads();
+    if (tid == 0) A.tile_exp[tile] = sE;
+}
+
+// Pass 2, one workgroup per tile: the gather scatter of pass 1's lam_Ep,
+// lam_Bp onto the six Yee sub-grids, accumulated in an int64 LDS window in
+// units of 2^(tile_exp - 31): every contribution is below 2^31 there and is
+// rounded to an int32 (error <= 2^-32 of the tile's largest |lam|); one
+// entry takes at most one contribution per particle, so the sum cannot
+// overflow.  Lanes of a wave take particles 16 apart, in different cells.
+__global__ __launch_bounds__(SCAT_THREADS) void k_adj_scatter(AdjArgs A, AdjSpecies S) {
+    __shared__ unsigned long long sA[6 * FW3];
+    __shared__ int sG[3][16];
+
+    const GridP &g = A.g;
+    int wo[3];
+    const int tile = tile_of_block(A.ti, wo);
+    if (tile >= A.ti.ntiles) return;
+    const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
+    if (beg >= end) return;
+    const int et = A.tile_exp[tile];
+    if (et == NO_EXP) return;
+    const int ee = max(et, -96);  // keeps the scale a finite float
+    const int tid = threadIdx.x;
+    window_rows(g, wo, sG);
+    for (int e = tid; e < 6 * FW3; e += SCAT_THREADS) sA[e] = 0ull;
+    __syncthreads();
+    constexpr int LHI_X = TX + 2 * MARGIN, LHI_Y = TY + 2 * MARGIN, LHI_Z = TZ + 2 * MARGIN;
+    const float scale = ldexpf(1.f, EB - ee);  // at most 2^127
+    const int q0 = (tid & 63) * (SPPT * (SCAT_THREADS / 64)) + (tid >> 6) * SPPT;
+    for (int base = (beg & ~(SPPT - 1)) + q0; base < end; base += SCAT_THREADS * SPPT) {
+        const vuS c4 = *(const vuS *)(S.cell + base);
+        const vfS ox4 = *(const vfS *)(S.pos[0] + base), oy4 = *(const vfS *)(S.pos[1] + base),
+                  oz4 = *(const vfS *)(S.pos[2] + base);
+        vfS l64[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) l64[q] = *(const vfS *)(A.l6[q] + base);
+#pragma unroll
+        for (int k = 0; k < SPPT; ++k) {
+            const int p = base + k;
+            const uint32_t c = c4[k];
+            if (p < beg || p >= end || c == DEAD) continue;
+            const int wl[3] = {local_axis(g, 0, cell_i(c), wo[0]), local_axis(g, 1, cell_j(c), wo[1]),
+                               local_axis(g, 2, cell_k(c), wo[2])};
+            if (!(wl[0] >= 1 && wl[0] <= LHI_X && wl[1] >= 1 && wl[1] <= LHI_Y && wl[2] >= 1 &&
+                  wl[2] <= LHI_Z))
+                continue;  // handled by k_adj_fallback
+            const float o[3] = {ox4[k], oy4[k], oz4[k]};
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const float v = l64[q][k];
+                if (v == 0.f) continue;
+                int cq[3];
+                float f[3], w[8];
+                stagger(q, wl, o, cq, f);
+                tri_weights(f, v * scale, w);  // exact power-of-two scaling
+                unsigned long long *dst = sA + q * FW3 + cq[0] + FWX * (cq[1] + FWY * cq[2]);
+#pragma unroll
+                for (int oo = 0; oo < 8; ++oo)
+                    atomicAdd(dst + (oo & 1) + FWX * (((oo >> 1) & 1) + FWY * (oo >> 2)),
+                              (unsigned long long)(long long)__float2int_rn(w[oo]));
+            }
+        }
+    }
+    __syncthreads();
     // add the window to the global gather adjoints (non-zero entries only)
-    const double inv = ldexp(1.0, ecur - EB);
-    for (int e = tid; e < 6 * FW3; e += ADJ_THREADS) {
+    const double inv = ldexp(1.0, ee - EB);
+    for (int e = tid; e < 6 * FW3; e += SCAT_THREADS) {
         const long long fx = (long long)sA[e];
         if (fx == 0) continue;
         const int comp = e / FW3;
@@ -531,6 +580,33 @@ __global__ __launch_bounds__(ADJ_THREADS, 1) void k_adj_fused(AdjArgs A, AdjSpec
         const int ly = r2 / FWX, lx = r2 - ly * FWX;
         float *dst = comp < 3 ? A.lEg[comp] : A.lBb[comp - 3];
         atomicAdd(dst + sG[0][lx] + sG[1][ly] + sG[2][lz], (float)((double)fx * inv));
+    }
+}
+
+// Listed out-of-window particles, entirely through global memory.
+__global__ __launch_bounds__(256) void k_adj_fallback(AdjArgs A, AdjSpecies S) {
+    const unsigned n = *(volatile unsigned *)A.fb_count;
+    const unsigned m = n < (unsigned long long)A.fb_cap ? n : (unsigned)A.fb_cap;
+    const GlobAcc gacc{A.g.n[0], A.g.n[1], A.g.n[2], A.g.ext[0], A.g.ext[1],
+                       {A.E[0], A.E[1], A.E[2]}, {A.Bb[0], A.Bb[1], A.Bb[2]},
+                       {A.lJ[0], A.lJ[1], A.lJ[2]}};
+    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        const int p = A.fb_list[t];
+        const uint32_t c = S.cell[p];
+        const int gl[3] = {cell_i(c), cell_j(c), cell_k(c)};
+        const float o[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
+        const float u[3] = {S.u[0][p], S.u[1][p], S.u[2][p]};
+        const float wq = S.w ? S.w[p] : 1.f;
+        float lx[3] = {S.lx[0][p], S.lx[1][p], S.lx[2][p]};
+        float lu[3] = {S.lu[0][p], S.lu[1][p], S.lu[2][p]};
+        float l6[6];
+        particle_vjp(gacc, A, S, gl, o, u, wq, lx, lu, l6);
+        scatter_global(gacc, A.lEg, A.lBb, gl, o, l6);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            S.lx[a][p] = lx[a];
+            S.lu[a][p] = lu[a];
+        }
     }
 }
 
@@ -623,7 +699,8 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
                      float *const lE[3], float *const lB[3], float *const lEg[3],
                      float *const lBb[3], float *const tB[3], const SpeciesP *sp,
                      const int32_t *const *tile_off, float *const (*lx)[3],
-                     float *const (*lu)[3], int nsp, hipStream_t s) {
+                     float *const (*lu)[3], int nsp, int *fb_list, unsigned *fb_count,
+                     long long fb_cap, float *const (*l6)[6], int *tile_exp, hipStream_t s) {
     for (int a = 0; a < 3; ++a) {
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, lEg[a], g.V);
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, lBb[a], g.V);
@@ -641,6 +718,9 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
         A.inv_d[a] = (float)(1.0 / g.d[a]);
     }
     A.dt = (float)g.dt;
+    A.fb_list = fb_list;
+    A.fb_count = fb_count;
+    A.tile_exp = tile_exp;
     const double dV = g.d[0] * g.d[1] * g.d[2];
     // one workgroup per tile; a multiple of 8 for the XCD-contiguous tile map
     const unsigned nblocks = (unsigned)(8 * ((ti.ntiles + 7) / 8));
@@ -659,7 +739,13 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
         S.r = (float)(sp[i].q * g.dt / (2.0 * sp[i].m));
         const double w = sp[i].per_particle_w ? 1.0 : sp[i].w_species;
         for (int a = 0; a < 3; ++a) S.qc[a] = (float)(sp[i].q * w * g.d[a] / (g.dt * dV));
-        hipLaunchKernelGGL(k_adj_fused, dim3(nblocks), dim3(ADJ_THREADS), 0, s, A, S);
+        A.fb_cap = fb_cap < sp[i].capacity ? fb_cap : sp[i].capacity;
+        for (int q = 0; q < 6; ++q) A.l6[q] = l6[i][q];
+        launch_fill_i32((int32_t *)fb_count, 1, 0, s);
+        hipLaunchKernelGGL(k_adj_particles, dim3(nblocks), dim3(ADJ_THREADS), 0, s, A, S);
+        hipLaunchKernelGGL(k_adj_fallback, dim3(64), dim3(256), 0, s, A, S);
+        launch_fill_i32((int32_t *)fb_count, 1, 0, s);  // the step kernels expect it empty
+        hipLaunchKernelGGL(k_adj_scatter, dim3(nblocks), dim3(SCAT_THREADS), 0, s, A, S);
     }
     const dim3 grid((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]);
     hipLaunchKernelGGL(k_adj_bprime, grid, dim3(64, 4), 0, s, g, lE[0], lE[1], lE[2], lB[0], lB[1],

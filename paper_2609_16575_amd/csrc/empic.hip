@@ -876,7 +876,23 @@ empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adj
                 return fail(s, EMPIC_E_ARG, "null particle array in state or adjoint");
         }
     }
-    launch_step_vjp(s->g, s->ti, E, Bb, lE, lB, lEg, lBb, tB, sp, tiles, lx, lu, s->nsp, s->stream);
+    // scratch free between steps and sorts: the step kernels' out-of-window
+    // list, each species' second buffer set (its offsets and momenta) for the
+    // per-particle gather adjoints, the sort-key counters for tile exponents
+    float *l6[EMPIC_MAX_SPECIES][6] = {};
+    for (int i = 0; i < s->nsp; ++i) {
+        const SpeciesState &S = s->sp[i];
+        if (S.capacity == 0) continue;
+        if (!S.has_alt) return fail(s, EMPIC_E_ARG, "the adjoint needs the second buffer set");
+        const empic_particle_buffers &alt = S.buf[1 - S.cur];
+        for (int a = 0; a < 3; ++a) {
+            l6[i][a] = (float *)alt.pos[a];
+            l6[i][3 + a] = (float *)alt.u[a];
+        }
+    }
+    launch_step_vjp(s->g, s->ti, E, Bb, lE, lB, lEg, lBb, tB, sp, tiles, lx, lu, s->nsp,
+                    (int *)s->fb_list, s->fb_count,
+                    2 * (long long)s->max_capacity * s->max_species, l6, s->counts, s->stream);
     return check_launch(s, "step_vjp");
 }
 

@@ -89,9 +89,13 @@ def test_sort_vjp_moves_adjoints_back():
     assert np.array_equal(pre, expect)
 
 
-def test_one_step_vjp_matches_oracle():
+@pytest.mark.parametrize("drift_steps", [0, 25])
+def test_one_step_vjp_matches_oracle(drift_steps):
+    """One-step VJP against the oracle's; with drift_steps unsorted steps
+    first, some particles are outside their tile window and take the
+    global-memory path."""
     import torch
-    n, d = (8, 8, 8), (1.0, 0.9, 1.1)
+    n, d = (16, 16, 8), (1.0, 0.9, 1.1)
     rng = np.random.default_rng(5)
     L = np.asarray(n) * np.asarray(d)
     sp = []
@@ -102,6 +106,9 @@ def test_one_step_vjp_matches_oracle():
     w.E0, w.B0 = W.random_fields(n, scale=0.1, seed=6)
     g = _sim(w)
     g.sort()
+    if drift_steps:
+        g.step(drift_steps)
+        assert g.diagnostics()["fallback_particles"] > 0
     st = g.save_state()
     o, ids = _storage_state(g, w)
     lam = g.alloc_adjoint()
