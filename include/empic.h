@@ -297,6 +297,12 @@ empic_status empic_sort_recorded(empic_sim *s, int32_t *const perm[EMPIC_MAX_SPE
 empic_status empic_sort_vjp(empic_sim *s, int32_t *const perm[EMPIC_MAX_SPECIES],
                             const empic_adjoint *lam);
 
+/* FP64 sum over i < n of a[i] * b[i] for FP32 device arrays a, b (e.g. a
+ * gradient's projection on a direction summed over all particles), in a
+ * fixed order (the same result on every call); *out on the host.
+ * Synchronizes the handle's stream. */
+empic_status empic_dot_f64(empic_sim *s, const float *a, const float *b, int64_t n, double *out);
+
 /* Cells per tile of the FP32 path's sort order and fused kernel (x, y, z):
  * particles are stored tile by tile (tiles x-fastest), cell by cell inside a
  * tile (x-fastest).  Host-only; needs no handle. */

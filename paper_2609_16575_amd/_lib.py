@@ -98,6 +98,7 @@ SIGNATURES = {
     "empic_step_vjp": (C.c_int, [_P, C.POINTER(State), C.POINTER(Adjoint)]),
     "empic_state_tile_words": (C.c_int, [_P, C.POINTER(C.c_int64)]),
     "empic_step_state": (C.c_int, [_P, C.POINTER(State), C.POINTER(State)]),
+    "empic_dot_f64": (C.c_int, [_P, _P, _P, C.c_int64, C.POINTER(C.c_double)]),
     "empic_sort_recorded": (C.c_int, [_P, C.c_void_p * MAX_SPECIES]),
     "empic_sort_vjp": (C.c_int, [_P, C.c_void_p * MAX_SPECIES, C.POINTER(Adjoint)]),
     "empic_tile_shape": (None, [C.POINTER(C.c_int32)]),

@@ -91,6 +91,25 @@ __global__ void k_final_reduce(const double *partials, double *result) {
     if (threadIdx.x == 0) result[q] = r;
 }
 
+// grid-stride FP64 products, one partial per workgroup, then a fixed-order sum
+__global__ void k_dot_f64(const float *a, const float *b, long long n, double *partials) {
+    __shared__ double sm[16];
+    double v = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        v += (double)a[i] * (double)b[i];
+    const double r = block_reduce<false>(v, sm);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+__global__ void k_sum_partials(const double *partials, int n, double *out) {
+    __shared__ double sm[16];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
+    const double r = block_reduce<false>(v, sm);
+    if (threadIdx.x == 0) *out = r;
+}
+
 __global__ void k_absmax_f64(const double *x, long long n, double *out) {
     __shared__ double sm[16];
     double m = 0.0;
@@ -127,6 +146,12 @@ void launch_continuity(const GridP &g, T *const J[3], const double *rho_now,
 
 void launch_absmax_f64(const double *x, long long n, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_absmax_f64, dim3(1), dim3(1024), 0, s, x, n, out);
+}
+
+void launch_dot_f64(const float *a, const float *b, long long n, double *partials,
+                    double *result, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_f64, dim3(RED_BLOCKS), dim3(256), 0, s, a, b, n, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, RED_BLOCKS, result);
 }
 
 void launch_final_reduce(const double *partials, double *result, hipStream_t s) {

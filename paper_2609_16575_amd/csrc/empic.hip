@@ -966,6 +966,19 @@ empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_
     return check_launch(s, "step_state");
 }
 
+empic_status empic_dot_f64(empic_sim *s, const float *a, const float *b, int64_t n, double *out) {
+    EMPIC_GUARD(s);
+    if (!out || n < 0 || (n > 0 && (!a || !b))) return fail(s, EMPIC_E_ARG, "bad dot arguments");
+    static_assert(RED_BLOCKS <= PSTRIDE, "dot partials fit one slot");
+    double *partials = s->partials + (size_t)Q_DOT * PSTRIDE;
+    launch_dot_f64(a, b, (long long)n, partials, s->result + Q_DOT, s->stream);
+    const empic_status st = check_launch(s, "dot_f64");
+    if (st != EMPIC_OK) return st;
+    EMPIC_HIP(hipMemcpyAsync(out, s->result + Q_DOT, 8, hipMemcpyDeviceToHost, s->stream));
+    EMPIC_HIP(hipStreamSynchronize(s->stream));
+    return EMPIC_OK;
+}
+
 void empic_tile_shape(int32_t out[3]) {
     if (!out) return;
     out[0] = TX;

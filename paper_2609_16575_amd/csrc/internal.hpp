@@ -89,7 +89,8 @@ void launch_write_species(DevSpecies *dst, const DevSpecies &v, hipStream_t s);
 constexpr int NQ = 16;       // reduction slots
 constexpr int RED_BLOCKS = 1024;  // grid-stride particle reductions
 enum Slot {
-    Q_EE = 0, Q_BB = 1, Q_KM = 2, Q_KP = 6, Q_GMAX = 10, Q_G2 = 11, Q_CMAX = 12, Q_RMAX = 13
+    Q_EE = 0, Q_BB = 1, Q_KM = 2, Q_KP = 6, Q_GMAX = 10, Q_G2 = 11, Q_CMAX = 12, Q_RMAX = 13,
+    Q_DOT = 14
 };
 
 __host__ __device__ inline bool slot_is_max(int q) {
@@ -214,6 +215,9 @@ void launch_continuity(const GridP &g, T *const J[3], const double *rho_now,
 void launch_final_reduce(const double *partials, double *result, hipStream_t s);
 void launch_fill_i32(int32_t *p, long long n, int32_t v, hipStream_t s);
 // largest |x| of n doubles into *out (one workgroup; set-up path only)
+// FP64 sum of a[i] * b[i] into *result (fixed order: RED_BLOCKS partials)
+void launch_dot_f64(const float *a, const float *b, long long n, double *partials,
+                    double *result, hipStream_t s);
 void launch_absmax_f64(const double *x, long long n, double *out, hipStream_t s);
 
 }  // namespace empic

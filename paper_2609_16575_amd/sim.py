@@ -277,6 +277,18 @@ class Sim:
         S, A = self._state_struct(st), self._adjoint_struct(lam)
         LB.check(self.h, self.L.empic_step_vjp(self.h, C.byref(S), C.byref(A)))
 
+    def dot_f64(self, a, b):
+        """FP64 sum of a * b over two FP32 device tensors of equal size (fixed order)."""
+        t = self.torch
+        if a.dtype != t.float32 or b.dtype != t.float32 or a.numel() != b.numel():
+            raise ValueError("dot_f64 takes two float32 tensors of the same size")
+        dev = self.E.device
+        if not (a.is_contiguous() and b.is_contiguous()) or a.device != dev or b.device != dev:
+            raise ValueError("dot_f64 takes contiguous tensors on the Sim's device")
+        out = C.c_double()
+        LB.check(self.h, self.L.empic_dot_f64(self.h, _ptr(a), _ptr(b), a.numel(), C.byref(out)))
+        return out.value
+
     def alloc_perm(self):
         """One int32 permutation array per species, for sort_recorded."""
         t = self.torch

@@ -167,13 +167,16 @@ def _adjoint_gradients(w, steps, K, eps, dirU=None, probe=None):
     dV = w.d[0] * w.d[1] * w.d[2]
     loss = 0.5 * dV * ((EN * EN)[:, m].sum() + (BN * BN)[:, m].sum())
     loss.backward()
+    # dL/d eps = sum over all particles of S . dL/dU0, summed in FP64 on the GPU
+    geps = g.dot_f64(Sd, dU.grad)
+    assert abs(geps - float(e.grad.item())) <= 1e-4 * abs(geps) + 1e-30, (geps, e.grad.item())
     dir_grad = None
     if dirU is not None:
         gU = dU.grad[:, :N].double().cpu().numpy().T      # storage order
         gU_by_id = np.empty_like(gU)
         gU_by_id[I] = gU
         dir_grad = float(np.sum(gU_by_id * dirU))
-    return float(loss.item()), float(e.grad.item()), dir_grad
+    return float(loss.item()), geps, dir_grad
 
 
 def _fp64_loss(w_fn, eps, dirU=None, h=0.0, steps=500, track=False):
@@ -446,3 +449,18 @@ def test_step_state_matches_step_in_place(case):
 def torch_equal(x, y):
     import torch
     return bool(torch.equal(x, y))
+
+
+def test_dot_f64_matches_numpy_and_repeats():
+    import torch
+    w = W.thermal_two_species(n=(8, 8, 8), ppc=1)
+    g = _sim(w)
+    rng = np.random.default_rng(9)
+    for n in (0, 1, 1000, 3 * 1000 * 1000 + 17):
+        a = rng.standard_normal(n).astype(np.float32)
+        b = rng.standard_normal(n).astype(np.float32)
+        ta, tb = torch.from_numpy(a).to(g.dev), torch.from_numpy(b).to(g.dev)
+        r1, r2 = g.dot_f64(ta, tb), g.dot_f64(ta, tb)
+        ref = float(np.dot(a.astype(np.float64), b.astype(np.float64)))
+        assert r1 == r2  # fixed summation order
+        assert abs(r1 - ref) <= 1e-12 * max(np.sum(np.abs(a.astype(np.float64) * b)), 1e-300), (n, r1, ref)
