@@ -29,10 +29,11 @@
 
 #define ORC_PERIODIC 0
 #define ORC_ABSORBING 1
+#define ORC_PEC 2
 
 typedef struct {
     int32_t n[3];  /* cells per axis */
-    int32_t bc[3]; /* ORC_PERIODIC or ORC_ABSORBING, per axis */
+    int32_t bc[3]; /* ORC_PERIODIC, ORC_ABSORBING or ORC_PEC, per axis */
     double d[3];   /* cell size */
     double dt;     /* time step */
 } orc_grid;
@@ -48,19 +49,30 @@ typedef struct {
     int32_t pad;
 } orc_laser;
 
+typedef struct {
+    int32_t axis;      /* normal of the port plane */
+    int32_t plane;     /* node index of the plane along axis */
+    int32_t comp;      /* driven E component (transverse to axis) */
+    int32_t prof_axis; /* transverse axis of the half-sine profile */
+    double e0;         /* amplitude */
+    double omega;      /* angular frequency */
+    double tau;        /* time constant of the envelope 1 - exp(-t/tau) */
+} orc_port;
+
 /* ------------------------------------------------------------------------ */
 /* indexing helpers                                                          */
 /* ------------------------------------------------------------------------ */
 
+/* walled (absorbing or PEC) axes store n+1 node planes */
 static int64_t ext_of(const orc_grid *g, int a) {
-    return (int64_t)g->n[a] + (g->bc[a] == ORC_ABSORBING ? 1 : 0);
+    return (int64_t)g->n[a] + (g->bc[a] != ORC_PERIODIC ? 1 : 0);
 }
 
 static int64_t vol_of(const orc_grid *g) {
     return ext_of(g, 0) * ext_of(g, 1) * ext_of(g, 2);
 }
 
-/* Linear index of (i,j,k); periodic axes wrap, absorbing axes return -1 when
+/* Linear index of (i,j,k); periodic axes wrap, walled axes return -1 when
  * the point lies outside the stored array. */
 static int64_t at(const orc_grid *g, int64_t i, int64_t j, int64_t k) {
     int64_t p[3] = {i, j, k};
@@ -81,7 +93,7 @@ static int stag_E(int c, int a) { return a == c ? 1 : 0; }
 static int stag_B(int c, int a) { return a == c ? 0 : 1; }
 
 /* Number of stored values of a component along axis a: periodic axes hold n,
- * absorbing axes hold n+1 node values or n half-cell values. */
+ * walled axes hold n+1 node values or n half-cell values. */
 static int64_t count_along(const orc_grid *g, int a, int half) {
     if (g->bc[a] == ORC_PERIODIC) return g->n[a];
     return half ? g->n[a] : (int64_t)g->n[a] + 1;
@@ -124,11 +136,11 @@ void orc_faraday(const orc_grid *g, const double *E, double *B, double *Bbar) {
     }
 }
 
-/* Is the E_c value at (i,j,k) on a face of an absorbing axis where it is a   */
+/* Is the E_c value at (i,j,k) on a face of a walled axis where it is a      */
 /* tangential component (its update then belongs to the boundary condition)? */
-static int e_on_absorbing_face(const orc_grid *g, int c, const int64_t p[3]) {
+static int e_on_wall_face(const orc_grid *g, int c, const int64_t p[3]) {
     for (int a = 0; a < 3; ++a) {
-        if (a == c || g->bc[a] != ORC_ABSORBING) continue;
+        if (a == c || g->bc[a] == ORC_PERIODIC) continue;
         if (p[a] == 0 || p[a] == g->n[a]) return 1;
     }
     return 0;
@@ -137,7 +149,7 @@ static int e_on_absorbing_face(const orc_grid *g, int c, const int64_t p[3]) {
 /* ------------------------------------------------------------------------ */
 /* Sec. 2.3, Ampere-Maxwell: the E_x equation of the paper and its cyclic      */
 /* permutations.  E^{n+1} = E^n + dt curl B^{n+1/2} - dt J^{n+1/2}, backward   */
-/* differences.  Tangential E on absorbing faces is left to orc_mur.          */
+/* differences.  Tangential E on walled faces is left to orc_mur / orc_pec.   */
 /* ------------------------------------------------------------------------ */
 void orc_ampere(const orc_grid *g, double *E, const double *B, const double *J) {
     const int64_t V = vol_of(g);
@@ -149,7 +161,7 @@ void orc_ampere(const orc_grid *g, double *E, const double *B, const double *J) 
             for (int64_t j = 0; j < cnt[1]; ++j)
                 for (int64_t i = 0; i < cnt[0]; ++i) {
                     int64_t p[3] = {i, j, k};
-                    if (e_on_absorbing_face(g, c, p)) continue;
+                    if (e_on_wall_face(g, c, p)) continue;
                     int64_t q1[3] = {i, j, k}, q2[3] = {i, j, k};
                     q1[a1] -= 1;
                     q2[a2] -= 1;
@@ -201,6 +213,61 @@ void orc_mur(const orc_grid *g, double *E, const double *E_old) {
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Perfectly conducting walls (the waveguide walls of Sec. 3.2).  READING:    */
+/* tangential E is zero on the node planes 0 and n of a PEC axis; Ampere      */
+/* leaves those values alone and this sets them to zero after every step.     */
+/* Normal B on the walls then keeps its initial value (zero) by Faraday.      */
+/* Particles leaving through a PEC face are removed, as at an absorbing one.  */
+/* ------------------------------------------------------------------------ */
+void orc_pec(const orc_grid *g, double *E) {
+    const int64_t V = vol_of(g);
+    for (int a = 0; a < 3; ++a) {
+        if (g->bc[a] != ORC_PEC) continue;
+        for (int c = 0; c < 3; ++c) {
+            if (c == a) continue;
+            int64_t cnt[3];
+            for (int b = 0; b < 3; ++b) cnt[b] = count_along(g, b, stag_E(c, b));
+            cnt[a] = 1;
+            for (int64_t k = 0; k < cnt[2]; ++k)
+                for (int64_t j = 0; j < cnt[1]; ++j)
+                    for (int64_t i = 0; i < cnt[0]; ++i)
+                        for (int side = 0; side < 2; ++side) {
+                            int64_t p[3] = {i, j, k};
+                            p[a] = side ? g->n[a] : 0;
+                            E[c * V + at(g, p[0], p[1], p[2])] = 0.0;
+                        }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Port excitation of the waveguide benchmark (Sec. 3.2): a monochromatic     */
+/* field prescribed on the input plane, switched on with the envelope        */
+/* g(t) = 1 - exp(-t/tau).  READING: a hard source on the node plane `plane`  */
+/* of axis `axis`: E_comp = e0 sin(pi s / L) g(t) sin(omega t) with s the    */
+/* component's position along prof_axis and L that axis' length (the TE10   */
+/* profile), at t = t^{n+1}, written after the other boundary updates.       */
+/* ------------------------------------------------------------------------ */
+void orc_port_apply(const orc_grid *g, double *E, const orc_port *P, double t) {
+    const int64_t V = vol_of(g);
+    const int c = P->comp, a = P->axis, pa = P->prof_axis;
+    const double L = g->n[pa] * g->d[pa];
+    const double amp = P->e0 * (1.0 - exp(-t / P->tau)) * sin(P->omega * t);
+    int64_t cnt[3];
+    for (int b = 0; b < 3; ++b) cnt[b] = count_along(g, b, stag_E(c, b));
+    cnt[a] = 1;
+    for (int64_t k = 0; k < cnt[2]; ++k)
+        for (int64_t j = 0; j < cnt[1]; ++j)
+            for (int64_t i = 0; i < cnt[0]; ++i) {
+                int64_t p[3] = {i, j, k};
+                p[a] = P->plane;
+                const double spos = ((double)p[pa] + 0.5 * stag_E(c, pa)) * g->d[pa];
+                const int64_t ip = at(g, p[0], p[1], p[2]);
+                if (ip >= 0) E[c * V + ip] = amp * sin(acos(-1.0) * spos / L);
+            }
+}
+
 /* READING (laser injection, configuration with a0 = 2): a soft current sheet */
 /* J_y on the x-node plane i_s radiating the incident field                   */
 /*   E_inc = a0 exp(-r^2/w0^2) exp(-2 ln2 (t-t0)^2/tau^2) sin(omega0 (t-t0))   */
@@ -221,7 +288,7 @@ void orc_laser_apply(const orc_grid *g, double *E, const orc_laser *L, double t_
     for (int64_t k = 0; k < cnt[2]; ++k)
         for (int64_t j = 0; j < cnt[1]; ++j) {
             int64_t p[3] = {L->i_s, j, k};
-            if (e_on_absorbing_face(g, 1, p)) continue;
+            if (e_on_wall_face(g, 1, p)) continue;
             const double y = ((double)j + 0.5) * g->d[1];
             const double z = (double)k * g->d[2];
             const double Jy = -2.0 * orc_laser_field(L, t_half, y, z) / g->d[0];
@@ -331,11 +398,11 @@ void orc_particle_uniform(double r, const double E[3], const double B[3], double
 static void add_edge(const orc_grid *g, double *J, int c, int64_t i, int64_t j, int64_t k,
                      double v) {
     const int64_t ip = at(g, i, j, k);
-    if (ip < 0) return; /* absorbing axis: edge outside the array */
+    if (ip < 0) return; /* walled axis: edge outside the array */
     int64_t p[3] = {i, j, k};
-    /* an absorbing axis' half-cell components stop at index n-1 */
+    /* a walled axis' half-cell components stop at index n-1 */
     for (int a = 0; a < 3; ++a)
-        if (g->bc[a] == ORC_ABSORBING && stag_E(c, a) && p[a] >= g->n[a]) return;
+        if (g->bc[a] != ORC_PERIODIC && stag_E(c, a) && p[a] >= g->n[a]) return;
     J[c * vol_of(g) + ip] += v;
 }
 

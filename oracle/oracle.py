@@ -25,6 +25,7 @@ _lib = None
 
 PERIODIC = 0
 ABSORBING = 1
+PEC = 2
 
 
 class _Grid(C.Structure):
@@ -36,6 +37,12 @@ class _Laser(C.Structure):
     _fields_ = [("a0", C.c_double), ("w0", C.c_double), ("tau", C.c_double),
                 ("t0", C.c_double), ("omega0", C.c_double), ("yc", C.c_double),
                 ("zc", C.c_double), ("i_s", C.c_int32), ("pad", C.c_int32)]
+
+
+class _Port(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("plane", C.c_int32), ("comp", C.c_int32),
+                ("prof_axis", C.c_int32), ("e0", C.c_double), ("omega", C.c_double),
+                ("tau", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -55,6 +62,8 @@ def lib():
     L.orc_faraday.argtypes = [G, _D, _D, _D]
     L.orc_ampere.argtypes = [G, _D, _D, _D]
     L.orc_mur.argtypes = [G, _D, _D]
+    L.orc_pec.argtypes = [G, _D]
+    L.orc_port_apply.argtypes = [G, _D, C.POINTER(_Port), C.c_double]
     L.orc_laser_apply.argtypes = [G, _D, C.POINTER(_Laser), C.c_double]
     L.orc_laser_field.argtypes = [C.POINTER(_Laser), C.c_double, C.c_double, C.c_double]
     L.orc_laser_field.restype = C.c_double
@@ -129,7 +138,8 @@ class OracleSim:
         self.dt = float(dt)
         self.bc = tuple(int(x) for x in bc)
         self.g = make_grid(self.n, self.d, self.dt, self.bc)
-        self.ext = tuple(self.n[a] + (1 if self.bc[a] == ABSORBING else 0) for a in range(3))
+        # walled (absorbing or PEC) axes hold n+1 node planes
+        self.ext = tuple(self.n[a] + (1 if self.bc[a] != PERIODIC else 0) for a in range(3))
         shape = (3, self.ext[2], self.ext[1], self.ext[0])
         self.E = np.zeros(shape)
         self.B = np.zeros(shape)
@@ -137,6 +147,7 @@ class OracleSim:
         self.Bbar = np.zeros(shape)
         self.species: list[Species] = []
         self.laser = None
+        self.port = None
         self.rho_bg = 0.0
         self.nstep = 0
         self.midpoint_only = False
@@ -147,7 +158,7 @@ class OracleSim:
         return self.d[0] * self.d[1] * self.d[2]
 
     def add_species(self, q, m, w, pos, u, wpp=None, ids=None) -> int:
-        absorbing = any(b == ABSORBING for b in self.bc)
+        absorbing = any(b != PERIODIC for b in self.bc)  # particles leave through walls
         self.species.append(Species(q, m, w, pos, u, wpp, ids, absorbing))
         return len(self.species) - 1
 
@@ -156,6 +167,13 @@ class OracleSim:
         L.a0, L.w0, L.tau, L.t0, L.omega0 = a0, w0, tau, t0, omega0
         L.yc, L.zc, L.i_s = yc, zc, int(i_s)
         self.laser = L
+
+    def set_port(self, axis, plane, comp, prof_axis, e0, omega, tau):
+        """Hard TE10-like source on a node plane (Sec. 3.2; see orc_port_apply)."""
+        P = _Port()
+        P.axis, P.plane, P.comp, P.prof_axis = int(axis), int(plane), int(comp), int(prof_axis)
+        P.e0, P.omega, P.tau = float(e0), float(omega), float(tau)
+        self.port = P
 
     # -- the PIC cycle (Sec. 2.2) --------------------------------------------
     def step(self, nsteps: int = 1):
@@ -176,6 +194,10 @@ class OracleSim:
                                   (self.nstep + 0.5) * self.dt)
             if absorbing:
                 L.orc_mur(g, _p(self.E), _p(E_old))
+            if any(b == PEC for b in self.bc):
+                L.orc_pec(g, _p(self.E))
+            if self.port is not None:
+                L.orc_port_apply(g, _p(self.E), C.byref(self.port), (self.nstep + 1) * self.dt)
             self.nstep += 1
 
     # -- adjoint of one step (periodic grids) ----------------------------------
