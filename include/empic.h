@@ -10,11 +10,11 @@
  *     update, Sec. 2.3).  Momenta are u = gamma v.
  *   - Time levels (Sec. 2.3, 2.4): E and particle positions at t^n, B and
  *     momenta at t^{n-1/2}.  empic_step advances all four by whole steps.
- *   - Grid arrays are [k][j][i] (x fastest) with ext[a] = n[a] + 1 on an
- *     absorbing axis, n[a] on a periodic one.  Component locations in cell
+ *   - Grid arrays are [k][j][i] (x fastest) with ext[a] = n[a] + 1 on a
+ *     walled (absorbing or PEC) axis, n[a] on a periodic one.  Component locations in cell
  *     units: Ex(i+1/2,j,k) Ey(i,j+1/2,k) Ez(i,j,k+1/2), Bx(i,j+1/2,k+1/2)
- *     By(i+1/2,j,k+1/2) Bz(i+1/2,j+1/2,k); J like E; rho at nodes.  On an
- *     absorbing axis the entry n of a half-cell component is padding and
+ *     By(i+1/2,j,k+1/2) Bz(i+1/2,j+1/2,k); J like E; rho at nodes.  On a
+ *     walled axis the entry n of a half-cell component is padding and
  *     stays zero.
  *   - All device memory is owned by the caller (fields, particle buffers,
  *     workspace).  The library keeps raw pointers only; the caller keeps the
@@ -54,7 +54,11 @@ typedef enum {
     EMPIC_E_UNSUPPORTED = 7  /* valid request this build does not implement */
 } empic_status;
 
-enum { EMPIC_BC_PERIODIC = 0, EMPIC_BC_ABSORBING = 1 };
+/* Boundaries per axis.  ABSORBING: first-order Mur on tangential E of both
+ * faces.  PEC: perfectly conducting walls (the waveguide of Sec. 3.2),
+ * tangential E zero on both faces.  Particles leaving a walled axis are
+ * removed. */
+enum { EMPIC_BC_PERIODIC = 0, EMPIC_BC_ABSORBING = 1, EMPIC_BC_PEC = 2 };
 
 /* Arithmetic of the step. */
 enum {
@@ -78,7 +82,7 @@ enum {
 /* Grid and time step (Sec. 2.3).  dt must satisfy
  *   dt <= 1 / sqrt(1/d0^2 + 1/d1^2 + 1/d2^2)              (c = 1)
  * FP32_CELLREL additionally limits n to <= 2047 x 2047 x 1023 cells (the
- * packed cell index).  sort_every = S > 0 re-sorts particles by tile and cell
+ * packed cell index) unless the handle holds no particles (max_capacity 0).  sort_every = S > 0 re-sorts particles by tile and cell
  * at the start of every S-th step (FP32 path); 0 sorts only on request and
  * once before the first step. */
 typedef struct {
@@ -123,6 +127,22 @@ typedef struct {
     int32_t i_s;
     int32_t enabled;
 } empic_laser_desc;
+
+/* Waveguide port (the excitation of the field-solver benchmark, Sec. 3.2):
+ * a hard source on the node plane `plane` of axis `axis` that sets, after
+ * every step,  E_comp = e0 sin(pi s / L) (1 - exp(-t/tau)) sin(omega t)  at
+ * t = t^{n+1}, s being the component's position along prof_axis and L that
+ * axis' length (the TE10 profile).  comp and prof_axis are transverse to
+ * axis; tau > 0. */
+typedef struct {
+    int32_t enabled;
+    int32_t axis;
+    int32_t plane;
+    int32_t comp;
+    int32_t prof_axis;
+    int32_t pad;
+    double e0, omega, tau;
+} empic_port_desc;
 
 /* FP64 diagnostics of the current state (Sec. 3.3).  U_E = dV/2 sum |E^n|^2,
  * U_B = dV/2 sum B^{n-1/2}.B^{n+1/2} (B^{n+1/2} formed from the state),
@@ -199,10 +219,14 @@ empic_status empic_set_background(empic_sim *s, double rho_bg);
 /* External laser source (see empic_laser_desc); enabled = 0 removes it. */
 empic_status empic_set_laser(empic_sim *s, const empic_laser_desc *laser);
 
+/* Waveguide port (see empic_port_desc); enabled = 0 removes it.  EMPIC_E_ARG
+ * for an axis, component or plane outside the grid. */
+empic_status empic_set_port(empic_sim *s, const empic_port_desc *port);
+
 /* Advance the state by nsteps PIC cycles (Sec. 2.2): Faraday with temporal
  * centring of B -> gather, Boris, move, ZigZag deposit for every species ->
- * Ampere-Maxwell -> laser source -> Mur faces.  FP32 path: counting sort
- * every sort_every steps.  Asynchronous. */
+ * Ampere-Maxwell -> laser source -> Mur faces -> PEC walls -> port.  FP32
+ * path: counting sort every sort_every steps.  Asynchronous. */
 empic_status empic_step(empic_sim *s, int32_t nsteps);
 
 /* Sort (FP32 path) by tile and cell now, dropping removed particles. */

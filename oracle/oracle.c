@@ -264,7 +264,9 @@ void orc_port_apply(const orc_grid *g, double *E, const orc_port *P, double t) {
                 p[a] = P->plane;
                 const double spos = ((double)p[pa] + 0.5 * stag_E(c, pa)) * g->d[pa];
                 const int64_t ip = at(g, p[0], p[1], p[2]);
-                if (ip >= 0) E[c * V + ip] = amp * sin(acos(-1.0) * spos / L);
+                /* sin(pi s/L) evaluated from the nearer wall: exactly 0 on both */
+                const double sw = spos < L - spos ? spos : L - spos;
+                if (ip >= 0) E[c * V + ip] = amp * sin(acos(-1.0) * sw / L);
             }
 }
 

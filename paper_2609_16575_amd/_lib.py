@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libempic.so")
 
 MAX_SPECIES = 4
-BC_PERIODIC, BC_ABSORBING = 0, 1
+BC_PERIODIC, BC_ABSORBING, BC_PEC = 0, 1, 2
 FP32_CELLREL, FP64_PLAIN = 0, 1
 
 STATUS = {0: "EMPIC_OK", 1: "EMPIC_E_ARG", 2: "EMPIC_E_STATE", 3: "EMPIC_E_HIP", 4: "EMPIC_E_CFL",
@@ -39,6 +39,12 @@ class LaserDesc(C.Structure):
     _fields_ = [("a0", C.c_double), ("w0", C.c_double), ("tau", C.c_double), ("t0", C.c_double),
                 ("omega0", C.c_double), ("yc", C.c_double), ("zc", C.c_double),
                 ("i_s", C.c_int32), ("enabled", C.c_int32)]
+
+
+class PortDesc(C.Structure):
+    _fields_ = [("enabled", C.c_int32), ("axis", C.c_int32), ("plane", C.c_int32),
+                ("comp", C.c_int32), ("prof_axis", C.c_int32), ("pad", C.c_int32),
+                ("e0", C.c_double), ("omega", C.c_double), ("tau", C.c_double)]
 
 
 class Diag(C.Structure):
@@ -83,6 +89,7 @@ SIGNATURES = {
     "empic_current_buffer": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32)]),
     "empic_set_background": (C.c_int, [_P, C.c_double]),
     "empic_set_laser": (C.c_int, [_P, C.POINTER(LaserDesc)]),
+    "empic_set_port": (C.c_int, [_P, C.POINTER(PortDesc)]),
     "empic_step": (C.c_int, [_P, C.c_int32]),
     "empic_sort": (C.c_int, [_P]),
     "empic_deposit_rho": (C.c_int, [_P, C.c_int32, _P]),

@@ -32,7 +32,7 @@ void grid_info(const empic_grid_desc *d, GridP &g, TileInfo &ti) {
     for (int a = 0; a < 3; ++a) {
         g.n[a] = d->n[a];
         g.bc[a] = d->bc[a];
-        g.ext[a] = d->n[a] + (d->bc[a] == EMPIC_BC_ABSORBING ? 1 : 0);
+        g.ext[a] = d->n[a] + (d->bc[a] != EMPIC_BC_PERIODIC ? 1 : 0);  // walled: n+1 planes
         g.d[a] = d->d[a];
         g.inv_d[a] = 1.0 / d->d[a];
         ti.nt[a] = (d->n[a] + (a == 0 ? TX : a == 1 ? TY : TZ) - 1) / (a == 0 ? TX : a == 1 ? TY : TZ);
@@ -85,7 +85,8 @@ Layout layout(const empic_grid_desc *d, int max_species, long long max_capacity)
     }
     L.mur_stride = ps;
     L.mur = o;
-    const bool absorbing = d->bc[0] || d->bc[1] || d->bc[2];
+    const bool absorbing = d->bc[0] == EMPIC_BC_ABSORBING || d->bc[1] == EMPIC_BC_ABSORBING ||
+                           d->bc[2] == EMPIC_BC_ABSORBING;
     o += absorbing ? up_align((size_t)3 * 2 * 4 * ps * es) : 0;
     L.total = o;
     return L;
@@ -136,6 +137,7 @@ struct empic_sim {
     long long max_capacity = 0;
     double rho_bg = 0.0;
     empic_laser_desc laser{};
+    empic_port_desc port{};
     long long nstep = 0, rho_prev_step = -1;
     bool need_sort = true;
     double jscale = 1099511627776.0;  // fixed-point scale of the fused kernel's current window
@@ -245,7 +247,10 @@ template <typename T>
 void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, int wr_mask = -1) {
     T *E[3], *B[3], *J[3], *Bb[3];
     field_ptrs<T>(s, E, B, J, Bb);
-    const bool absorbing = s->g.bc[0] || s->g.bc[1] || s->g.bc[2];
+    const bool absorbing = s->g.bc[0] == EMPIC_BC_ABSORBING || s->g.bc[1] == EMPIC_BC_ABSORBING ||
+                           s->g.bc[2] == EMPIC_BC_ABSORBING;
+    const bool pec = s->g.bc[0] == EMPIC_BC_PEC || s->g.bc[1] == EMPIC_BC_PEC ||
+                     s->g.bc[2] == EMPIC_BC_PEC;
     TimedEvent t;
     ev_begin(s, t, 1);
     // 1. Faraday + temporal centring of B; J zeroed for this step's deposit
@@ -284,6 +289,8 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
     launch_ampere<T>(s->g, E, B, J, s->stream);
     if (s->laser.enabled) launch_laser<T>(s->g, E, s->laser, (s->nstep + 0.5) * s->g.dt, s->stream);
     if (absorbing) launch_mur_apply<T>(s->g, E, (const T *)s->mur, s->L.mur_stride, s->stream);
+    if (pec) launch_pec<T>(s->g, E, s->stream);
+    if (s->port.enabled) launch_port<T>(s->g, E, s->port, (s->nstep + 1) * s->g.dt, s->stream);
     ev_end(s, t);
     s->nstep += 1;
 }
@@ -354,10 +361,12 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
     long long V = 1;
     for (int a = 0; a < 3; ++a) {
         if (g->n[a] < 1 || !(g->d[a] > 0.0) || !std::isfinite(g->d[a])) return EMPIC_E_ARG;
-        if (g->bc[a] != EMPIC_BC_PERIODIC && g->bc[a] != EMPIC_BC_ABSORBING) return EMPIC_E_ARG;
-        if (g->bc[a] == EMPIC_BC_ABSORBING && g->n[a] < 2) return EMPIC_E_ARG;
+        if (g->bc[a] != EMPIC_BC_PERIODIC && g->bc[a] != EMPIC_BC_ABSORBING &&
+            g->bc[a] != EMPIC_BC_PEC)
+            return EMPIC_E_ARG;
+        if (g->bc[a] != EMPIC_BC_PERIODIC && g->n[a] < 2) return EMPIC_E_ARG;
         inv2 += 1.0 / (g->d[a] * g->d[a]);
-        V *= g->n[a] + (g->bc[a] == EMPIC_BC_ABSORBING ? 1 : 0);
+        V *= g->n[a] + (g->bc[a] != EMPIC_BC_PERIODIC ? 1 : 0);
     }
     if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return EMPIC_E_ARG;
     if (g->dt > (1.0 + 1e-12) / std::sqrt(inv2)) return EMPIC_E_CFL;  // 3D CFL, c = 1
@@ -365,7 +374,10 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
     if (V >= (1LL << 31)) return EMPIC_E_UNSUPPORTED;
     for (int a = 0; a < 3; ++a)  // launch grids put one axis in a grid dimension
         if (g->n[a] + 1 > 65535) return EMPIC_E_UNSUPPORTED;
-    if (g->precision == EMPIC_FP32_CELLREL && (g->n[0] > 2047 || g->n[1] > 2047 || g->n[2] > 1023))
+    // the packed cell index of the FP32 particles (a handle without particles
+    // has no such limit)
+    if (g->precision == EMPIC_FP32_CELLREL && max_capacity > 0 &&
+        (g->n[0] > 2047 || g->n[1] > 2047 || g->n[2] > 1023))
         return EMPIC_E_UNSUPPORTED;
     if (g->precision == EMPIC_FP64_PLAIN && (g->bc[0] || g->bc[1] || g->bc[2]))
         return EMPIC_E_UNSUPPORTED;
@@ -560,6 +572,22 @@ empic_status empic_set_laser(empic_sim *s, const empic_laser_desc *laser) {
         if (!(laser->tau > 0.0) || !(laser->w0 > 0.0)) return fail(s, EMPIC_E_ARG, "laser needs tau, w0 > 0");
     }
     s->laser = *laser;
+    return EMPIC_OK;
+}
+
+empic_status empic_set_port(empic_sim *s, const empic_port_desc *port) {
+    EMPIC_GUARD(s);
+    if (!port) return fail(s, EMPIC_E_ARG, "null port");
+    if (port->enabled) {
+        const int a = port->axis, c = port->comp, pa = port->prof_axis;
+        if (a < 0 || a > 2 || c < 0 || c > 2 || pa < 0 || pa > 2 || c == a || pa == a)
+            return fail(s, EMPIC_E_ARG, "port axis, component and profile axis must be transverse");
+        if (port->plane < 0 || port->plane >= s->g.ext[a])
+            return fail(s, EMPIC_E_ARG, "port plane outside the grid");
+        if (!(port->tau > 0.0) || !std::isfinite(port->e0) || !std::isfinite(port->omega))
+            return fail(s, EMPIC_E_ARG, "port needs tau > 0 and finite e0, omega");
+    }
+    s->port = *port;
     return EMPIC_OK;
 }
 

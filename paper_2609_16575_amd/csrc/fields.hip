@@ -2,11 +2,14 @@
 //
 // One thread per grid point, x fastest across a wavefront so that every
 // component load and store is coalesced; a thread updates all three
-// components at its point.  Periodic neighbours wrap; on an absorbing axis
-// the validity rules below keep every neighbour inside the stored array.
+// components at its point.  Periodic neighbours wrap; on a walled (absorbing
+// or PEC) axis the validity rules below keep every neighbour inside the
+// stored array.
 //
 // Bytes per cell (FP32): Faraday reads E, B (24) and writes B, Bbar (24) and
 // zeroes J (12); Ampere reads E, B, J (36) and writes E (12).
+#include <cmath>
+
 #include "internal.hpp"
 
 namespace empic {
@@ -41,16 +44,17 @@ __device__ inline long long dn(const GridP &g, const Pt &q, int a) {
                                                            : -q.st[a];
 }
 
-// A component half-staggered along absorbing axis a has n values: entry n is padding.
+// A component half-staggered along walled axis a has n values: entry n is padding.
 __device__ inline bool valid_B(const GridP &g, const Pt &q, int c) {
     for (int a = 0; a < 3; ++a)
-        if (g.bc[a] == EMPIC_BC_ABSORBING && a != c && q.idx[a] == g.n[a]) return false;
+        if (g.bc[a] != EMPIC_BC_PERIODIC && a != c && q.idx[a] == g.n[a]) return false;
     return true;
 }
-// E_c updated by Ampere: valid and not tangential on an absorbing face.
+// E_c updated by Ampere: valid and not tangential on a walled face (those
+// belong to the Mur or PEC condition).
 __device__ inline bool ampere_E(const GridP &g, const Pt &q, int c) {
     for (int a = 0; a < 3; ++a) {
-        if (g.bc[a] != EMPIC_BC_ABSORBING) continue;
+        if (g.bc[a] == EMPIC_BC_PERIODIC) continue;
         if (a == c && q.idx[a] == g.n[a]) return false;
         if (a != c && (q.idx[a] == 0 || q.idx[a] == g.n[a])) return false;
     }
@@ -183,10 +187,10 @@ __global__ void k_laser(GridP g, T *Ey, empic_laser_desc L, double t_half) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
     const int cy = g.n[1];                                              // E_y half along y
-    const int cz = g.bc[2] == EMPIC_BC_ABSORBING ? g.n[2] + 1 : g.n[2];  // node along z
+    const int cz = g.bc[2] != EMPIC_BC_PERIODIC ? g.n[2] + 1 : g.n[2];  // node along z
     if (j >= cy || k >= cz) return;
-    if (g.bc[0] == EMPIC_BC_ABSORBING && (L.i_s == 0 || L.i_s == g.n[0])) return;
-    if (g.bc[2] == EMPIC_BC_ABSORBING && (k == 0 || k == g.n[2])) return;
+    if (g.bc[0] != EMPIC_BC_PERIODIC && (L.i_s == 0 || L.i_s == g.n[0])) return;
+    if (g.bc[2] != EMPIC_BC_PERIODIC && (k == 0 || k == g.n[2])) return;
     const double y = ((double)j + 0.5) * g.d[1];
     const double z = (double)k * g.d[2];
     const double r2 = (y - L.yc) * (y - L.yc) + (z - L.zc) * (z - L.zc);
@@ -196,6 +200,50 @@ __global__ void k_laser(GridP g, T *Ey, empic_laser_desc L, double t_half) {
     const double Jy = -2.0 * einc / g.d[0];
     const long long p = L.i_s + (long long)g.ext[0] * (j + (long long)g.ext[1] * k);
     Ey[p] -= (T)(g.dt * Jy);
+}
+
+// Perfectly conducting walls: tangential E on both faces of axis a set to
+// zero (after Ampere, which leaves them alone).  One thread per face point.
+template <typename T>
+__global__ void k_pec(GridP g, int a, T *Ex, T *Ey, T *Ez) {
+    const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= (long long)g.ext[b1] * g.ext[b2]) return;
+    int idx[3];
+    idx[b1] = (int)(t % g.ext[b1]);
+    idx[b2] = (int)(t / g.ext[b1]);
+    const long long st[3] = {1, g.ext[0], (long long)g.ext[0] * g.ext[1]};
+    T *E[3] = {Ex, Ey, Ez};
+    for (int side = 0; side < 2; ++side) {
+        idx[a] = side ? g.n[a] : 0;
+        const long long p = idx[0] + st[1] * idx[1] + st[2] * idx[2];
+        E[b1][p] = T(0);
+        E[b2][p] = T(0);
+    }
+}
+
+// Waveguide port (hard source): E_comp = e0 sin(pi s/L) g(t) sin(omega t) on
+// the node plane of axis P.axis, s the component's position along
+// P.prof_axis, with the amplitude factor computed on the host in FP64.
+template <typename T>
+__global__ void k_port(GridP g, T *Ec, empic_port_desc P, double amp) {
+    const int a = P.axis, c = P.comp, pa = P.prof_axis;
+    const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    // E_c holds ext values along a transverse axis, n where it is
+    // half-staggered on a walled axis (entry n is padding)
+    const int n1 = (g.bc[b1] == EMPIC_BC_PERIODIC || c != b1) ? g.ext[b1] : g.n[b1];
+    const int n2 = (g.bc[b2] == EMPIC_BC_PERIODIC || c != b2) ? g.ext[b2] : g.n[b2];
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (t >= (long long)n1 * n2) return;
+    int idx[3];
+    idx[a] = P.plane;
+    idx[b1] = (int)(t % n1);
+    idx[b2] = (int)(t / n1);
+    const double s = ((double)idx[pa] + (c == pa ? 0.5 : 0.0)) * g.d[pa];
+    const double L = g.n[pa] * g.d[pa];
+    const long long p = idx[0] + (long long)g.ext[0] * (idx[1] + (long long)g.ext[1] * idx[2]);
+    const double sw = fmin(s, L - s);  // sin(pi s/L) from the nearer wall: exactly 0 on both
+    Ec[p] = (T)(amp * sin(3.14159265358979323846 * sw / L));
 }
 
 // FP64 partial sums of |E|^2 and B^{n-1/2}.B^{n+1/2} (B^{n+1/2} formed on the fly)
@@ -298,9 +346,31 @@ void launch_mur_apply(const GridP &g, T *const E[3], const T *planes, long long 
 }
 
 template <typename T>
+void launch_pec(const GridP &g, T *const E[3], hipStream_t s) {
+    for (int a = 0; a < 3; ++a) {
+        if (g.bc[a] != EMPIC_BC_PEC) continue;
+        const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+        const long long npt = (long long)g.ext[b1] * g.ext[b2];
+        hipLaunchKernelGGL(k_pec<T>, dim3((unsigned)((npt + 255) / 256)), dim3(256), 0, s, g, a,
+                           E[0], E[1], E[2]);
+    }
+}
+
+template <typename T>
+void launch_port(const GridP &g, T *const E[3], const empic_port_desc &P, double t,
+                 hipStream_t s) {
+    const double amp = P.e0 * (1.0 - std::exp(-t / P.tau)) * std::sin(P.omega * t);
+    const int a = P.axis;
+    const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+    const long long npt = (long long)g.ext[b1] * g.ext[b2];
+    hipLaunchKernelGGL(k_port<T>, dim3((unsigned)((npt + 255) / 256)), dim3(256), 0, s, g,
+                       E[P.comp], P, amp);
+}
+
+template <typename T>
 void launch_laser(const GridP &g, T *const E[3], const empic_laser_desc &L, double t_half,
                   hipStream_t s) {
-    const int cz = g.bc[2] == EMPIC_BC_ABSORBING ? g.n[2] + 1 : g.n[2];
+    const int cz = g.bc[2] != EMPIC_BC_PERIODIC ? g.n[2] + 1 : g.n[2];
     hipLaunchKernelGGL(k_laser<T>, dim3((g.n[1] + 63) / 64, cz), dim3(64), 0, s, g, E[1], L,
                        t_half);
 }
@@ -322,6 +392,9 @@ void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *p
                                       hipStream_t);                                            \
     template void launch_laser<T>(const GridP &, T *const[3], const empic_laser_desc &, double, \
                                   hipStream_t);                                                \
+    template void launch_pec<T>(const GridP &, T *const[3], hipStream_t);                      \
+    template void launch_port<T>(const GridP &, T *const[3], const empic_port_desc &, double,  \
+                                 hipStream_t);                                                 \
     template void launch_field_energy<T>(const GridP &, T *const[3], T *const[3], double *,    \
                                          hipStream_t);
 EMPIC_INST(float)

@@ -149,6 +149,10 @@ template <typename T>
 void launch_laser(const GridP &g, T *const E[3], const empic_laser_desc &L, double t_half,
                   hipStream_t s);
 template <typename T>
+void launch_pec(const GridP &g, T *const E[3], hipStream_t s);
+template <typename T>
+void launch_port(const GridP &g, T *const E[3], const empic_port_desc &P, double t, hipStream_t s);
+template <typename T>
 void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *partials,
                          hipStream_t s);
 

@@ -66,7 +66,7 @@ __device__ void deposit_global(const GridP &g, float *const J[3], int ci, int cj
             const int gx = gaxis(g, 0, p[0]), gy = gaxis(g, 1, p[1]), gz = gaxis(g, 2, p[2]);
             if (gx < 0 || gy < 0 || gz < 0) continue;
             const int gc = c == 0 ? gx : (c == 1 ? gy : gz);
-            if (g.bc[c] == EMPIC_BC_ABSORBING && gc >= g.n[c]) continue;  // padding
+            if (g.bc[c] != EMPIC_BC_PERIODIC && gc >= g.n[c]) continue;  // padding
             atomicAdd(J[c] + gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz),
                       v[4 * c + q]);
         }
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
             const int gi = gaxis(g, a, wo[a] + l);
             const int mul = a == 0 ? 1 : (a == 1 ? g.ext[0] : g.ext[0] * g.ext[1]);
             sG[a][l] = gi < 0 ? -1 : gi * mul;
-            sPad[a][l] = (gi >= 0 && g.bc[a] == EMPIC_BC_ABSORBING && gi >= g.n[a]) ? 1 : 0;
+            sPad[a][l] = (gi >= 0 && g.bc[a] != EMPIC_BC_PERIODIC && gi >= g.n[a]) ? 1 : 0;
         }
     }
     __syncthreads();

@@ -89,7 +89,7 @@ __device__ inline void add_edge(const GridP &g, double *J, int c, long long i, l
     const long long ip = at64(g, i, j, k);
     if (ip < 0) return;
     const long long p[3] = {i, j, k};
-    if (g.bc[c] == EMPIC_BC_ABSORBING && p[c] >= g.n[c]) return;  // half-cell padding
+    if (g.bc[c] != EMPIC_BC_PERIODIC && p[c] >= g.n[c]) return;  // half-cell padding
     atomicAdd(J + ip, v);
 }
 

@@ -44,7 +44,7 @@ class Sim:
             raise ValueError(precision)
         self.dtype = torch.float64 if self.fp64 else torch.float32
         n, bc = workload.n, workload.bc
-        self.ext = tuple(n[a] + (1 if bc[a] == LB.BC_ABSORBING else 0) for a in range(3))
+        self.ext = tuple(n[a] + (1 if bc[a] != LB.BC_PERIODIC else 0) for a in range(3))
         shape = (3, self.ext[2], self.ext[1], self.ext[0])
         self.E = torch.zeros(shape, dtype=self.dtype, device=self.dev)
         self.B = torch.zeros(shape, dtype=self.dtype, device=self.dev)
@@ -57,7 +57,7 @@ class Sim:
         nsp = len(workload.species)
         self.caps = [_round_up(max(8, int(s.pos.shape[0] * (1.0 + capacity_slack))), 64)
                      for s in workload.species]
-        max_cap = max(self.caps) if self.caps else 64
+        max_cap = max(self.caps) if self.caps else 0
         d = LB.GridDesc()
         for a in range(3):
             d.n[a], d.bc[a], d.d[a] = int(n[a]), int(bc[a]), float(workload.d[a])
@@ -89,6 +89,11 @@ class Sim:
             Ls = workload.laser
             ld = LB.LaserDesc(Ls.a0, Ls.w0, Ls.tau, Ls.t0, Ls.omega0, Ls.yc, Ls.zc, int(Ls.i_s), 1)
             LB.check(h, self.L.empic_set_laser(h, C.byref(ld)))
+        if getattr(workload, "port", None) is not None:
+            P = workload.port
+            pd = LB.PortDesc(1, int(P.axis), int(P.plane), int(P.comp), int(P.prof_axis), 0,
+                             float(P.e0), float(P.omega), float(P.tau))
+            LB.check(h, self.L.empic_set_port(h, C.byref(pd)))
         torch.cuda.synchronize(self.dev)
 
     # -- set-up -----------------------------------------------------------------

@@ -22,6 +22,7 @@ import numpy as np
 
 PERIODIC = 0
 ABSORBING = 1
+PEC = 2
 M_PROTON = 1836.0
 
 
@@ -49,6 +50,18 @@ class LaserInit:
 
 
 @dataclass
+class PortInit:
+    """Hard source E_comp = e0 sin(pi s/L) (1 - exp(-t/tau)) sin(omega t) on a node plane."""
+    axis: int
+    plane: int
+    comp: int
+    prof_axis: int
+    e0: float
+    omega: float
+    tau: float
+
+
+@dataclass
 class Workload:
     name: str
     n: tuple
@@ -58,6 +71,7 @@ class Workload:
     species: list = field(default_factory=list)
     rho_bg: float = 0.0
     laser: Optional[LaserInit] = None
+    port: Optional[PortInit] = None
     steps: int = 1
     sort_every: int = 10
     E0: Optional[np.ndarray] = None   # (3, ext_z, ext_y, ext_x) or None -> zero
@@ -216,14 +230,14 @@ def weibel_bimaxwellian(n=(256, 256, 256), ppc=16, vth_x=0.25, vth_perp=0.05, st
 
 
 def random_fields(n, bc=(PERIODIC,) * 3, scale=1e-2, seed=7):
-    """Random E and B arrays (valid entries only; absorbing padding left zero)."""
+    """Random E and B arrays (valid entries only; walled-axis padding left zero)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    ext = [n[a] + (1 if bc[a] == ABSORBING else 0) for a in range(3)]
+    ext = [n[a] + (1 if bc[a] != PERIODIC else 0) for a in range(3)]
     E = scale * rng.standard_normal((3, ext[2], ext[1], ext[0]))
     B = scale * rng.standard_normal((3, ext[2], ext[1], ext[0]))
     for c in range(3):
         for a in range(3):
-            if bc[a] != ABSORBING:
+            if bc[a] == PERIODIC:
                 continue
             # E_c is half-staggered along a == c; B_c along a != c: index n is padding
             sl = [slice(None)] * 3
@@ -233,3 +247,54 @@ def random_fields(n, bc=(PERIODIC,) * 3, scale=1e-2, seed=7):
             else:
                 B[c][tuple(sl)] = 0.0
     return E, B
+
+
+# speed of light in cm/ns: lengths in cm, c = 1
+C_CM_PER_NS = 29.9792458
+
+
+def waveguide_te10(nodes=(12, 6, 376), a=3.0, b=1.5, Lz=100.0, f0_ghz=9.0, e0=1.0,
+                   tau_periods=2.0, steps=None):
+    """The field-solver benchmark of Sec. 3.2: a PEC rectangular guide a x b x Lz
+    (cm; a = 3, b = a/2, Lz = 1 m) driven at z = 0 by the TE10 field
+    E_y = e0 sin(pi x/a) (1 - exp(-t/tau)) sin(2 pi f0 t), f0 = 9 GHz, tau = 2
+    periods; Courant 0.5.  `nodes` counts grid points per axis as the paper's
+    convergence table does (cells = nodes - 1).  Units: c = 1, lengths in cm.
+    x and y are PEC walls; the far end z = Lz is absorbing (Mur).  No
+    particles.  steps defaults to 30 periods (the table's n_t)."""
+    n = tuple(int(v) - 1 for v in nodes)
+    d = (a / n[0], b / n[1], Lz / n[2])
+    dt = courant_dt(d)
+    omega = 2.0 * np.pi * f0_ghz / C_CM_PER_NS
+    T0 = 2.0 * np.pi / omega
+    port = PortInit(axis=2, plane=0, comp=1, prof_axis=0, e0=e0, omega=omega,
+                    tau=tau_periods * T0)
+    nsteps = int(round(30.0 * T0 / dt)) if steps is None else int(steps)
+    return Workload("waveguide_te10_%dx%dx%d" % tuple(nodes), n, d, dt, (PEC, PEC, ABSORBING),
+                    [], rho_bg=0.0, port=port, steps=nsteps, sort_every=0)
+
+
+def pec_cavity_plasma(n=(16, 12, 8), d=(1.0, 0.9, 1.1), ppc=4, vth=0.3, seed=1006):
+    """Hot electrons with per-particle weights in a closed PEC box: particles
+    reach the walls (and are removed) within a few steps; for parity of the
+    wall treatment.  Random initial fields with tangential E zero on the
+    walls."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = _uniform_in_cells(rng, n, d, ppc)
+    u = vth * rng.standard_normal(pos.shape)
+    wpp = 0.5 + rng.random(pos.shape[0])
+    sp = SpeciesInit("electron", -1.0, 1.0, 1.0, pos, u, wpp=wpp / ppc)
+    w = Workload("pec_cavity_%dx%dx%d" % tuple(n), tuple(n), tuple(d), courant_dt(d), (PEC,) * 3,
+                 [sp], rho_bg=0.0, steps=20, sort_every=5)
+    E, B = random_fields(n, bc=(PEC,) * 3, scale=0.05, seed=seed + 1)
+    for a in range(3):  # tangential E is zero on the walls
+        for c in range(3):
+            if c == a:
+                continue
+            for side in (0, n[a]):
+                sl = [slice(None)] * 3
+                sl[2 - a] = side
+                E[c][tuple(sl)] = 0.0
+    w.E0, w.B0 = E, B
+    return w
+

@@ -141,3 +141,30 @@ def test_te10_port_drives_the_discrete_guided_mode():
     # the continuous guide's beta differs at second order in the cell size
     beta_c = np.sqrt(w ** 2 - (np.pi / a_cells) ** 2)
     assert abs(beta - beta_c) > 1e-3 * beta_c
+
+
+def test_convergence_table_fixture_matches_the_papers_fit():
+    """The transcribed table reproduces the paper's own fit: slope 2.136 and
+    R^2 0.972 of log eps against log dh (Sec. 3.2), and its dh column follows
+    from the node counts (a = 3 cm, b = 1.5 cm, L_z = 100 cm, n nodes)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "te10_convergence.json")))
+    rows = gold["rows"]
+    dh = np.array([r["dh"] for r in rows])
+    eps = np.array([r["eps_E0"] for r in rows])
+    x, y = np.log(dh), np.log(eps)
+    slope, icpt = np.polyfit(x, y, 1)
+    r2 = 1.0 - np.sum((y - (slope * x + icpt)) ** 2) / np.sum((y - y.mean()) ** 2)
+    assert abs(slope - gold["fit"]["rate"]) < 5e-3 and abs(r2 - gold["fit"]["r2"]) < 5e-3, (slope, r2)
+    for k, r in enumerate(rows):
+        nx, ny, nz = r["nodes"]
+        h = np.sqrt((3.0 / (nx - 1)) ** 2 + (1.5 / (ny - 1)) ** 2 + (100.0 / (nz - 1)) ** 2) / 100.0
+        assert abs(h - r["dh"]) <= 2e-3 * r["dh"], (r, h)
+        # the time step halves with every refinement: n_t - 1 = 1250 * 2^k
+        assert r["nt"] - 1 == 1250 * 2 ** k
+    # the coarsest run covers 30 periods of 9 GHz at Courant 0.5
+    nx, ny, nz = rows[0]["nodes"]
+    dt = 0.5 / np.sqrt((((nx - 1) / 3.0) ** 2 + ((ny - 1) / 1.5) ** 2 + ((nz - 1) / 100.0) ** 2))
+    periods = (rows[0]["nt"] - 1) * dt / (29.9792458 / 9.0)
+    assert abs(periods - 30.0) < 0.3, periods
