@@ -63,6 +63,7 @@ def lib():
     L.orc_ampere.argtypes = [G, _D, _D, _D]
     L.orc_mur.argtypes = [G, _D, _D]
     L.orc_pec.argtypes = [G, _D]
+    L.orc_filter_J.argtypes = [G, _D, C.c_int32, C.c_int32]
     L.orc_port_apply.argtypes = [G, _D, C.POINTER(_Port), C.c_double]
     L.orc_laser_apply.argtypes = [G, _D, C.POINTER(_Laser), C.c_double]
     L.orc_laser_field.argtypes = [C.POINTER(_Laser), C.c_double, C.c_double, C.c_double]
@@ -148,6 +149,7 @@ class OracleSim:
         self.species: list[Species] = []
         self.laser = None
         self.port = None
+        self.filter = (0, 0)  # (binomial passes, compensate)
         self.rho_bg = 0.0
         self.nstep = 0
         self.midpoint_only = False
@@ -187,6 +189,8 @@ class OracleSim:
                 L.orc_push_deposit(g, _p(self.E), _p(self.Bbar), _p(self.J), s.np, _p(s.pos),
                                    _p(s.u), _p8(s.alive), _p(s.wpp), s.q, s.m, s.w,
                                    int(self.midpoint_only), 0, None)
+            if self.filter[0] or self.filter[1]:
+                L.orc_filter_J(g, _p(self.J), int(self.filter[0]), int(self.filter[1]))
             E_old = self.E.copy() if absorbing else None
             L.orc_ampere(g, _p(self.E), _p(self.B), _p(self.J))
             if self.laser is not None:
