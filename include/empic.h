@@ -223,10 +223,20 @@ empic_status empic_set_laser(empic_sim *s, const empic_laser_desc *laser);
  * for an axis, component or plane outside the grid. */
 empic_status empic_set_port(empic_sim *s, const empic_port_desc *port);
 
+/* Current filter (READING of the compensated smoothing module, Sec. 2.2):
+ * after the deposit, along x, then y, then z, each J component on its own
+ * sub-grid gets `passes` applications of the binomial stencil (1/4, 1/2,
+ * 1/4) and, if compensate = 1, one of (-1/4, 3/2, -1/4).  Periodic axes wrap;
+ * on a walled axis values beyond the array count as zero.  Charge is then
+ * conserved for the filtered density.  passes = compensate = 0 (the default)
+ * turns it off; EMPIC_E_ARG outside 0..16 / 0..1.  The step adjoint takes
+ * the filter into account. */
+empic_status empic_set_filter(empic_sim *s, int32_t passes, int32_t compensate);
+
 /* Advance the state by nsteps PIC cycles (Sec. 2.2): Faraday with temporal
  * centring of B -> gather, Boris, move, ZigZag deposit for every species ->
- * Ampere-Maxwell -> laser source -> Mur faces -> PEC walls -> port.  FP32
- * path: counting sort every sort_every steps.  Asynchronous. */
+ * current filter -> Ampere-Maxwell -> laser source -> Mur faces -> PEC walls
+ * -> port.  FP32 path: counting sort every sort_every steps.  Asynchronous. */
 empic_status empic_step(empic_sim *s, int32_t nsteps);
 
 /* Sort (FP32 path) by tile and cell now, dropping removed particles. */

@@ -219,6 +219,10 @@ class OracleSim:
         Bbar = np.zeros_like(self.B)
         L.orc_faraday(g, _p(self.E), _p(Bh), _p(Bbar))
         lJ = np.ascontiguousarray(-self.dt * lamE)
+        if self.filter[0] or self.filter[1]:
+            # E^{n+1} takes F J with F the (symmetric) filter: the deposit's
+            # adjoint is F^T lam_J = F lam_J
+            L.orc_filter_J(g, _p(lJ), int(self.filter[0]), int(self.filter[1]))
         lE = np.ascontiguousarray(lamE, dtype=np.float64).copy()
         lB = np.ascontiguousarray(lamB, dtype=np.float64).copy()
         lEg = np.zeros_like(lE)

@@ -90,6 +90,7 @@ SIGNATURES = {
     "empic_set_background": (C.c_int, [_P, C.c_double]),
     "empic_set_laser": (C.c_int, [_P, C.POINTER(LaserDesc)]),
     "empic_set_port": (C.c_int, [_P, C.POINTER(PortDesc)]),
+    "empic_set_filter": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "empic_step": (C.c_int, [_P, C.c_int32]),
     "empic_sort": (C.c_int, [_P]),
     "empic_deposit_rho": (C.c_int, [_P, C.c_int32, _P]),

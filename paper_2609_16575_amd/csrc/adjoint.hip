@@ -696,7 +696,8 @@ __global__ void k_zero_f32(float *p, long long n) {
 }  // namespace
 
 void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], float *const Bbar[3],
-                     float *const lE[3], float *const lB[3], float *const lEg[3],
+                     float *const lE[3], float *const lJdep[3], float *const lB[3],
+                     float *const lEg[3],
                      float *const lBb[3], float *const tB[3], const SpeciesP *sp,
                      const int32_t *const *tile_off, float *const (*lx)[3],
                      float *const (*lu)[3], int nsp, int *fb_list, unsigned *fb_count,
@@ -711,7 +712,7 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
     for (int a = 0; a < 3; ++a) {
         A.E[a] = E[a];
         A.Bb[a] = Bbar[a];
-        A.lJ[a] = lE[a];
+        A.lJ[a] = lJdep[a];
         A.lEg[a] = lEg[a];
         A.lBb[a] = lBb[a];
         A.dtd[a] = (float)(g.dt / g.d[a]);

@@ -23,7 +23,7 @@ inline size_t up_align(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t Bbar, fault, table, partials, result, rho_cur, rho_prev, tile_off, counts, scan, rank,
-        fb_list, adj, mur, total;
+        fb_list, adj, filt, mur, total;
     size_t tile_off_stride;
     long long mur_stride;
 };
@@ -77,6 +77,8 @@ Layout layout(const empic_grid_desc *d, int max_species, long long max_capacity)
     o += up_align((size_t)max_capacity * max_species * 8);
     L.adj = o;      // adjoint accumulators (FP32 path): gather lam_E, lam_Bbar, lam_B'
     o += d->precision == EMPIC_FP64_PLAIN ? 0 : up_align((size_t)9 * g.V * 4);
+    L.filt = o;     // current filter: the second buffer of its passes
+    o += up_align((size_t)3 * g.V * es);
     long long ps = 0;
     for (int a = 0; a < 3; ++a) {
         const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
@@ -138,6 +140,8 @@ struct empic_sim {
     double rho_bg = 0.0;
     empic_laser_desc laser{};
     empic_port_desc port{};
+    int filter_passes = 0, filter_comp = 0;
+    void *filt = nullptr;
     long long nstep = 0, rho_prev_step = -1;
     bool need_sort = true;
     double jscale = 1099511627776.0;  // fixed-point scale of the fused kernel's current window
@@ -283,8 +287,13 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
                             species_params(s, i, 0), s->sp[i].host_count, s->fault, s->stream);
         ev_end(s, t);
     }
-    // 3. Ampere-Maxwell, external source, absorbing faces
+    // 3. current filter, Ampere-Maxwell, external source, absorbing faces
     ev_begin(s, t, 1);
+    if (s->filter_passes || s->filter_comp) {
+        T *tmp[3];
+        for (int c = 0; c < 3; ++c) tmp[c] = (T *)s->filt + (size_t)c * s->g.V;
+        launch_filter<T>(s->g, J, tmp, s->filter_passes, s->filter_comp, s->stream);
+    }
     if (absorbing) launch_mur_save<T>(s->g, E, (T *)s->mur, s->L.mur_stride, s->stream);
     launch_ampere<T>(s->g, E, B, J, s->stream);
     if (s->laser.enabled) launch_laser<T>(s->g, E, s->laser, (s->nstep + 0.5) * s->g.dt, s->stream);
@@ -397,6 +406,7 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
     s->fault = (uint32_t *)(s->ws + L.fault);
     s->fallback = (unsigned long long *)(s->ws + L.fault + 8);
     s->table = (DevSpecies *)(s->ws + L.table);
+    s->filt = s->ws + L.filt;
     s->xtable = s->table + EMPIC_MAX_SPECIES;
     s->partials = (double *)(s->ws + L.partials);
     s->result = (double *)(s->ws + L.result);
@@ -588,6 +598,15 @@ empic_status empic_set_port(empic_sim *s, const empic_port_desc *port) {
             return fail(s, EMPIC_E_ARG, "port needs tau > 0 and finite e0, omega");
     }
     s->port = *port;
+    return EMPIC_OK;
+}
+
+empic_status empic_set_filter(empic_sim *s, int32_t passes, int32_t compensate) {
+    EMPIC_GUARD(s);
+    if (passes < 0 || passes > 16 || (compensate != 0 && compensate != 1))
+        return fail(s, EMPIC_E_ARG, "filter: 0..16 binomial passes, compensate 0 or 1");
+    s->filter_passes = passes;
+    s->filter_comp = compensate;
     return EMPIC_OK;
 }
 
@@ -918,7 +937,21 @@ empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adj
             l6[i][3 + a] = (float *)alt.u[a];
         }
     }
-    launch_step_vjp(s->g, s->ti, E, Bb, lE, lB, lEg, lBb, tB, sp, tiles, lx, lu, s->nsp,
+    // with a current filter F between deposit and Ampere the deposit's adjoint
+    // is F^T lam_E' = F lam_E' (the stencils are symmetric); tB is free until
+    // the transposed curls, so it serves as the filter's second buffer
+    float *lJdep[3] = {lE[0], lE[1], lE[2]};
+    if (s->filter_passes || s->filter_comp) {
+        float *fl[3];
+        for (int a = 0; a < 3; ++a) {
+            fl[a] = (float *)s->filt + (size_t)a * s->g.V;
+            EMPIC_HIP(hipMemcpyAsync(fl[a], lE[a], (size_t)s->g.V * 4, hipMemcpyDeviceToDevice,
+                                     s->stream));
+        }
+        launch_filter<float>(s->g, fl, tB, s->filter_passes, s->filter_comp, s->stream);
+        for (int a = 0; a < 3; ++a) lJdep[a] = fl[a];
+    }
+    launch_step_vjp(s->g, s->ti, E, Bb, lE, lJdep, lB, lEg, lBb, tB, sp, tiles, lx, lu, s->nsp,
                     (int *)s->fb_list, s->fb_count,
                     2 * (long long)s->max_capacity * s->max_species, l6, s->counts, s->stream);
     return check_launch(s, "step_vjp");

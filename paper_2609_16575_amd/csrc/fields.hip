@@ -9,6 +9,7 @@
 // Bytes per cell (FP32): Faraday reads E, B (24) and writes B, Bbar (24) and
 // zeroes J (12); Ampere reads E, B, J (36) and writes E (12).
 #include <cmath>
+#include <utility>
 
 #include "internal.hpp"
 
@@ -246,6 +247,41 @@ __global__ void k_port(GridP g, T *Ec, empic_port_desc P, double amp) {
     Ec[p] = (T)(amp * sin(3.14159265358979323846 * sw / L));
 }
 
+// One pass of the current filter along axis ax: dst = a src[-1] + b src + a src[+1]
+// per component on its own sub-grid; periodic axes wrap, on a walled axis
+// values beyond the stored ones (entry n of a half-cell component is
+// padding) count as zero.
+template <typename T>
+__global__ void k_filter_pass(GridP g, int ax, const T *__restrict__ s0, const T *__restrict__ s1,
+                              const T *__restrict__ s2, T *__restrict__ d0, T *__restrict__ d1,
+                              T *__restrict__ d2, T a, T b) {
+    Pt q;
+    if (!make_point(g, q)) return;
+    const T *src[3] = {s0, s1, s2};
+    T *dst[3] = {d0, d1, d2};
+    const long long p = q.p;
+    const bool per = g.bc[ax] == EMPIC_BC_PERIODIC;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        // stored values of component c along every axis
+        bool valid = true;
+        for (int a2 = 0; a2 < 3; ++a2)
+            if (g.bc[a2] != EMPIC_BC_PERIODIC && a2 == c && q.idx[a2] == g.n[a2]) valid = false;
+        if (!valid) {
+            dst[c][p] = T(0);
+            continue;
+        }
+        const int L = (!per && ax == c) ? g.n[ax] : g.ext[ax];
+        const int i = q.idx[ax];
+        T lo = T(0), hi = T(0);
+        if (i > 0) lo = src[c][p - q.st[ax]];
+        else if (per) lo = src[c][p + (long long)(L - 1) * q.st[ax]];
+        if (i < L - 1) hi = src[c][p + q.st[ax]];
+        else if (per) hi = src[c][p - (long long)(L - 1) * q.st[ax]];
+        dst[c][p] = a * lo + b * src[c][p] + a * hi;
+    }
+}
+
 // FP64 partial sums of |E|^2 and B^{n-1/2}.B^{n+1/2} (B^{n+1/2} formed on the fly)
 template <typename T>
 __global__ void k_field_energy(GridP g, const T *__restrict__ Ex, const T *__restrict__ Ey,
@@ -346,6 +382,23 @@ void launch_mur_apply(const GridP &g, T *const E[3], const T *planes, long long 
 }
 
 template <typename T>
+void launch_filter(const GridP &g, T *const F[3], T *const tmp[3], int passes, int compensate,
+                   hipStream_t s) {
+    T *cur[3] = {F[0], F[1], F[2]}, *oth[3] = {tmp[0], tmp[1], tmp[2]};
+    for (int ax = 0; ax < 3; ++ax)
+        for (int k = 0; k < passes + (compensate ? 1 : 0); ++k) {
+            const bool comp = k == passes;
+            const T a = comp ? T(-0.25) : T(0.25), b = comp ? T(1.5) : T(0.5);
+            hipLaunchKernelGGL(k_filter_pass<T>, point_grid(g), dim3(64, 4), 0, s, g, ax, cur[0],
+                               cur[1], cur[2], oth[0], oth[1], oth[2], a, b);
+            for (int c = 0; c < 3; ++c) std::swap(cur[c], oth[c]);
+        }
+    if (cur[0] != F[0])
+        for (int c = 0; c < 3; ++c)
+            (void)hipMemcpyAsync(F[c], cur[c], (size_t)g.V * sizeof(T), hipMemcpyDeviceToDevice, s);
+}
+
+template <typename T>
 void launch_pec(const GridP &g, T *const E[3], hipStream_t s) {
     for (int a = 0; a < 3; ++a) {
         if (g.bc[a] != EMPIC_BC_PEC) continue;
@@ -393,6 +446,8 @@ void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *p
     template void launch_laser<T>(const GridP &, T *const[3], const empic_laser_desc &, double, \
                                   hipStream_t);                                                \
     template void launch_pec<T>(const GridP &, T *const[3], hipStream_t);                      \
+    template void launch_filter<T>(const GridP &, T *const[3], T *const[3], int, int,          \
+                                   hipStream_t);                                               \
     template void launch_port<T>(const GridP &, T *const[3], const empic_port_desc &, double,  \
                                  hipStream_t);                                                 \
     template void launch_field_energy<T>(const GridP &, T *const[3], T *const[3], double *,    \

@@ -150,6 +150,11 @@ void launch_laser(const GridP &g, T *const E[3], const empic_laser_desc &L, doub
                   hipStream_t s);
 template <typename T>
 void launch_pec(const GridP &g, T *const E[3], hipStream_t s);
+// current filter: `passes` binomial passes per axis, then the compensator;
+// tmp: three more arrays of the grid's size
+template <typename T>
+void launch_filter(const GridP &g, T *const F[3], T *const tmp[3], int passes, int compensate,
+                   hipStream_t s);
 template <typename T>
 void launch_port(const GridP &g, T *const E[3], const empic_port_desc &P, double t, hipStream_t s);
 template <typename T>
@@ -198,8 +203,11 @@ void launch_store_f64(const SpeciesP &sp, long long count, double *pos, double *
                       hipStream_t s);
 
 // adjoint of one FP32 step (periodic)
+// lJdep: the adjoint the deposit sees, lE' itself or the filtered lE' when a
+// (symmetric) current filter acts between deposit and Ampere
 void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], float *const Bbar[3],
-                     float *const lE[3], float *const lB[3], float *const lEg[3],
+                     float *const lE[3], float *const lJdep[3], float *const lB[3],
+                     float *const lEg[3],
                      float *const lBb[3], float *const tB[3], const SpeciesP *sp,
                      const int32_t *const *tile_off, float *const (*lx)[3],
                      float *const (*lu)[3], int nsp, int *fb_list, unsigned *fb_count,

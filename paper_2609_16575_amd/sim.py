@@ -89,6 +89,8 @@ class Sim:
             Ls = workload.laser
             ld = LB.LaserDesc(Ls.a0, Ls.w0, Ls.tau, Ls.t0, Ls.omega0, Ls.yc, Ls.zc, int(Ls.i_s), 1)
             LB.check(h, self.L.empic_set_laser(h, C.byref(ld)))
+        if getattr(workload, "filter", None):
+            LB.check(h, self.L.empic_set_filter(h, int(workload.filter[0]), int(workload.filter[1])))
         if getattr(workload, "port", None) is not None:
             P = workload.port
             pd = LB.PortDesc(1, int(P.axis), int(P.plane), int(P.comp), int(P.prof_axis), 0,

@@ -72,6 +72,7 @@ class Workload:
     rho_bg: float = 0.0
     laser: Optional[LaserInit] = None
     port: Optional[PortInit] = None
+    filter: Optional[tuple] = None    # (binomial passes, compensate) of the current filter
     steps: int = 1
     sort_every: int = 10
     E0: Optional[np.ndarray] = None   # (3, ext_z, ext_y, ext_x) or None -> zero

@@ -16,6 +16,8 @@ def oracle_from(w, E0=None, B0=None):
     if w.laser is not None:
         L = w.laser
         sim.set_laser(L.a0, L.w0, L.tau, L.t0, L.omega0, L.yc, L.zc, L.i_s)
+    if getattr(w, "filter", None):
+        sim.filter = tuple(w.filter)
     if getattr(w, "port", None) is not None:
         P = w.port
         sim.set_port(P.axis, P.plane, P.comp, P.prof_axis, P.e0, P.omega, P.tau)

@@ -59,9 +59,11 @@ def _dot(a, b, L):
     return tot
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_one_step_vjp_matches_central_differences(seed):
+@pytest.mark.parametrize("seed,filt", [(0, (0, 0)), (1, (0, 0)), (2, (0, 0)), (0, (1, 1)), (1, (2, 0))])
+def test_one_step_vjp_matches_central_differences(seed, filt):
+    """filt: current filter (binomial passes, compensate) inside the step."""
     sim, rng = _random_sim(seed)
+    sim.filter = filt
     Lbox = np.asarray(sim.n) * np.asarray(sim.d)
     s0 = sim.state()
     lam = (rng.standard_normal(sim.E.shape), rng.standard_normal(sim.B.shape),
