@@ -214,6 +214,39 @@ void orc_mur(const orc_grid *g, double *E, const double *E_old) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Moving window (a module of Sec. 2.2; used by the wakefield run of Sec. 4; */
+/* its algorithm is not given).  READING: the window advances `cells` cells  */
+/* along the walled axis `axis` at once: every E and B value moves `cells`   */
+/* planes toward index 0, planes leaving at index 0 are dropped and the new  */
+/* planes at the far end start at zero.  (Particles are shifted, removed and  */
+/* injected by the caller.)                                                   */
+/* ------------------------------------------------------------------------ */
+void orc_window_shift(const orc_grid *g, double *E, double *B, int32_t axis, int32_t cells) {
+    const int64_t V = vol_of(g);
+    double *F[2] = {E, B};
+    for (int f = 0; f < 2; ++f)
+        for (int c = 0; c < 3; ++c) {
+            int64_t cnt[3];
+            for (int b = 0; b < 3; ++b)
+                cnt[b] = count_along(g, b, f == 0 ? stag_E(c, b) : stag_B(c, b));
+            const int64_t L = cnt[axis];
+            for (int64_t k = 0; k < cnt[2]; ++k)
+                for (int64_t j = 0; j < cnt[1]; ++j)
+                    for (int64_t i = 0; i < cnt[0]; ++i) {
+                        int64_t p[3] = {i, j, k};
+                        const int64_t m = p[axis];
+                        const int64_t dst = at(g, p[0], p[1], p[2]);
+                        double v = 0.0;
+                        if (m + cells < L) {
+                            p[axis] = m + cells;
+                            v = F[f][c * V + at(g, p[0], p[1], p[2])];
+                        }
+                        F[f][c * V + dst] = v;
+                    }
+        }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Current filtering (the "compensated smoothing" module of Sec. 2.2/2.5;     */
 /* its stencil is not given).  READING: along each axis in turn (x, y, z) and */
 /* for each J component on its own sub-grid, `passes` applications of the    */

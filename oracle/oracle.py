@@ -64,6 +64,7 @@ def lib():
     L.orc_mur.argtypes = [G, _D, _D]
     L.orc_pec.argtypes = [G, _D]
     L.orc_filter_J.argtypes = [G, _D, C.c_int32, C.c_int32]
+    L.orc_window_shift.argtypes = [G, _D, _D, C.c_int32, C.c_int32]
     L.orc_port_apply.argtypes = [G, _D, C.POINTER(_Port), C.c_double]
     L.orc_laser_apply.argtypes = [G, _D, C.POINTER(_Laser), C.c_double]
     L.orc_laser_field.argtypes = [C.POINTER(_Laser), C.c_double, C.c_double, C.c_double]
@@ -150,6 +151,7 @@ class OracleSim:
         self.laser = None
         self.port = None
         self.filter = (0, 0)  # (binomial passes, compensate)
+        self.window = None    # moving window (see set_window)
         self.rho_bg = 0.0
         self.nstep = 0
         self.midpoint_only = False
@@ -177,12 +179,65 @@ class OracleSim:
         P.e0, P.omega, P.tau = float(e0), float(omega), float(tau)
         self.port = P
 
+    def set_window(self, axis, cells, velocity, t_start, inject=()):
+        """Moving window along walled axis `axis` (READING of the module of
+        Sec. 2.2 used in Sec. 4): at the start of a step, whenever the window
+        has travelled (t - t_start) * velocity >= (shifts + 1) * cells * d,
+        fields move `cells` planes back (zeros enter at the front), particles
+        move by -cells * d, those behind the window are removed, and cold
+        particles are injected into the new cells on a quiet lattice:
+        inject = [(species, (px, py, pz), w), ...], offsets (m + 1/2)/p."""
+        self.window = dict(axis=int(axis), cells=int(cells), v=float(velocity),
+                           t0=float(t_start), shifts=0, inject=list(inject))
+
+    def _window_step(self):
+        W_ = self.window
+        a, cells = W_["axis"], W_["cells"]
+        t = self.nstep * self.dt
+        if (t - W_["t0"]) * W_["v"] < (W_["shifts"] + 1) * cells * self.d[a]:
+            return False
+        W_["shifts"] += 1
+        lib().orc_window_shift(C.byref(self.g), _p(self.E), _p(self.B), a, cells)
+        shift = cells * self.d[a]
+        for s in self.species:
+            s.pos[:, a] -= shift
+            out = s.pos[:, a] < 0.0
+            s.alive[out] = 0
+        for sp, per, w in W_["inject"]:
+            s = self.species[sp]
+            lo = [0] * 3
+            hi = list(self.n)
+            lo[a] = self.n[a] - cells
+            axes = []
+            for b in range(3):
+                cellsb = np.arange(lo[b], hi[b])
+                offs = (np.arange(per[b]) + 0.5) / per[b]
+                axes.append(((cellsb[:, None] + offs[None, :]).reshape(-1)) * self.d[b])
+            zz, yy, xx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+            pos = np.stack([xx.reshape(-1), yy.reshape(-1), zz.reshape(-1)], axis=1)
+            m = pos.shape[0]
+            s.pos = np.concatenate([s.pos, pos])
+            s.u = np.concatenate([s.u, np.zeros((m, 3))])
+            wpp_new = np.full(m, float(w))
+            if s.wpp is None:
+                if abs(float(w) - s.w) > 0:
+                    raise ValueError("injected weight differs from the species weight")
+            else:
+                s.wpp = np.concatenate([s.wpp, wpp_new])
+            start = int(s.ids.max()) + 1 if len(s.ids) else 0
+            s.ids = np.concatenate([s.ids, start + np.arange(m)])
+            s.alive = np.concatenate([s.alive, np.ones(m, dtype=np.int8)])
+            s.np = s.pos.shape[0]
+        return True
+
     # -- the PIC cycle (Sec. 2.2) --------------------------------------------
     def step(self, nsteps: int = 1):
         L = lib()
         g = C.byref(self.g)
         absorbing = any(b == ABSORBING for b in self.bc)
         for _ in range(int(nsteps)):
+            if self.window is not None:
+                self._window_step()
             L.orc_faraday(g, _p(self.E), _p(self.B), _p(self.Bbar))
             self.J[...] = 0.0
             for s in self.species:
