@@ -28,7 +28,9 @@
  *     EMPIC_E_UNSUPPORTED the handle is unchanged and usable.  After
  *     EMPIC_E_HIP the handle is poisoned: only empic_destroy and
  *     empic_last_error are allowed.  EMPIC_E_NONFINITE / EMPIC_E_STATE
- *     report a fault word raised by the kernels (bits EMPIC_FAULT_*).
+ *     report a fault word raised by the kernels (bits EMPIC_FAULT_*), as
+ *     does EMPIC_E_CAPACITY when empic_diagnostics returns it
+ *     (EMPIC_FAULT_CAPACITY).
  *   - A handle is not thread-safe; use one handle per stream.
  */
 #ifndef EMPIC_H
@@ -75,8 +77,10 @@ enum {
     EMPIC_FAULT_FAST = 2u,        /* |dxi| >= 1 cell in one step (impossible under CFL) */
     EMPIC_FAULT_OFFSET = 4u,      /* stored in-cell offset outside [0,1) */
     EMPIC_FAULT_CELL = 8u,        /* stored cell index outside the grid */
-    EMPIC_FAULT_FALLBACK = 16u    /* info: a particle left its tile window and was
+    EMPIC_FAULT_FALLBACK = 16u,   /* info: a particle left its tile window and was
                                      handled through global memory (not an error) */
+    EMPIC_FAULT_CAPACITY = 32u    /* moving-window injection would exceed the
+                                     species' capacity: nothing was injected */
 };
 
 /* Grid and time step (Sec. 2.3).  dt must satisfy
@@ -222,6 +226,34 @@ empic_status empic_set_laser(empic_sim *s, const empic_laser_desc *laser);
 /* Waveguide port (see empic_port_desc); enabled = 0 removes it.  EMPIC_E_ARG
  * for an axis, component or plane outside the grid. */
 empic_status empic_set_port(empic_sim *s, const empic_port_desc *port);
+
+/* Moving window (READING of the module of Sec. 2.2 used by the wakefield run
+ * of Sec. 4).  FP32 path, along an absorbing axis.  At the start of a step,
+ * once (t - t_start) velocity >= (shifts + 1) cells d[axis], E and B move
+ * `cells` planes toward index 0 (zeros enter at the front), particles move
+ * the same number of cells (those behind the window are removed), species
+ * with an injection (empic_set_injection) receive cold particles in the new
+ * cells, and the particles are re-sorted.  Sources stay fixed in the window
+ * frame (start the window after a laser pulse has been injected).  A shift
+ * of the tile size along the axis keeps sorts rare. */
+typedef struct {
+    int32_t enabled;
+    int32_t axis;
+    int32_t cells;
+    int32_t pad;
+    double velocity;
+    double t_start;
+} empic_window_desc;
+
+empic_status empic_set_window(empic_sim *s, const empic_window_desc *w);
+
+/* Cold plasma injected by the moving window into species sp: per_cell[a]
+ * particles per axis at offsets (m + 1/2)/per_cell[a], u = 0, weight w (a
+ * species without per-particle weights injects its own w); ids continue
+ * from the loaded count.  per_cell = {0,0,0} turns it off.  A shift that
+ * would exceed the species' capacity injects nothing and raises
+ * EMPIC_FAULT_CAPACITY. */
+empic_status empic_set_injection(empic_sim *s, int32_t sp, const int32_t per_cell[3], double w);
 
 /* Current filter (READING of the compensated smoothing module, Sec. 2.2):
  * after the deposit, along x, then y, then z, each J component on its own

@@ -47,6 +47,11 @@ class PortDesc(C.Structure):
                 ("e0", C.c_double), ("omega", C.c_double), ("tau", C.c_double)]
 
 
+class WindowDesc(C.Structure):
+    _fields_ = [("enabled", C.c_int32), ("axis", C.c_int32), ("cells", C.c_int32),
+                ("pad", C.c_int32), ("velocity", C.c_double), ("t_start", C.c_double)]
+
+
 class Diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("t", C.c_double), ("U_E", C.c_double), ("U_B", C.c_double),
                 ("U_tot", C.c_double), ("K", C.c_double * MAX_SPECIES),
@@ -91,6 +96,8 @@ SIGNATURES = {
     "empic_set_laser": (C.c_int, [_P, C.POINTER(LaserDesc)]),
     "empic_set_port": (C.c_int, [_P, C.POINTER(PortDesc)]),
     "empic_set_filter": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "empic_set_window": (C.c_int, [_P, C.POINTER(WindowDesc)]),
+    "empic_set_injection": (C.c_int, [_P, C.c_int32, C.c_int32 * 3, C.c_double]),
     "empic_step": (C.c_int, [_P, C.c_int32]),
     "empic_sort": (C.c_int, [_P]),
     "empic_deposit_rho": (C.c_int, [_P, C.c_int32, _P]),

@@ -105,6 +105,10 @@ struct SpeciesState {
     long long host_count = 0;
     bool tiles_valid = false;     // particles grouped by the tile offsets of a previous sort
     double wmax = 0.0;            // largest |weight| (species w, or the loaded per-particle max)
+    long long next_id = 0;        // id of the next injected particle
+    bool inject = false;          // moving-window injection of this species
+    int inj_per[3] = {1, 1, 1};
+    double inj_w = 0.0;
 };
 
 struct TimedEvent {
@@ -141,6 +145,8 @@ struct empic_sim {
     empic_laser_desc laser{};
     empic_port_desc port{};
     int filter_passes = 0, filter_comp = 0;
+    empic_window_desc window{};
+    long long window_shifts = 0;
     void *filt = nullptr;
     long long nstep = 0, rho_prev_step = -1;
     bool need_sort = true;
@@ -304,6 +310,44 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
     s->nstep += 1;
 }
 
+// Moving window (FP32 path): at the start of a step, once the window has
+// travelled (t - t_start) v >= (shifts + 1) cells d, fields and particles
+// move `cells` cells back along the window axis, particles behind it are
+// removed, cold plasma is injected into the new cells, and the next sort
+// regroups everything.
+void window_step(empic_sim *s) {
+    const empic_window_desc &W = s->window;
+    const int a = W.axis;
+    const double t = s->nstep * s->g.dt;
+    if ((t - W.t_start) * W.velocity < (double)(s->window_shifts + 1) * W.cells * s->g.d[a]) return;
+    s->window_shifts += 1;
+    float *E[3], *B[3], *tmp[3];
+    for (int c = 0; c < 3; ++c) {
+        E[c] = (float *)s->E[c];
+        B[c] = (float *)s->B[c];
+        tmp[c] = (float *)s->filt + (size_t)c * s->g.V;
+    }
+    launch_window_shift<float>(s->g, E, tmp, a, W.cells, false, s->stream);
+    launch_window_shift<float>(s->g, B, tmp, a, W.cells, true, s->stream);
+    int32_t *reserve = (int32_t *)((char *)s->fault + 32);
+    for (int i = 0; i < s->nsp; ++i) {
+        SpeciesState &S = s->sp[i];
+        const SpeciesP cur = species_params(s, i, S.cur);
+        launch_window_particles(cur, a, W.cells, s->stream);
+        if (S.inject) {
+            int lo[3] = {0, 0, 0}, nc[3] = {s->g.n[0], s->g.n[1], s->g.n[2]};
+            lo[a] = s->g.n[a] - W.cells;
+            nc[a] = W.cells;
+            launch_inject(cur, lo, nc, S.inj_per, (float)S.inj_w, (int)S.next_id, reserve, s->fault,
+                          s->stream);
+            S.next_id += (long long)nc[0] * S.inj_per[0] * nc[1] * S.inj_per[1] * nc[2] * S.inj_per[2];
+        }
+        S.tiles_valid = false;
+    }
+    s->need_sort = true;
+    s->rho_prev_step = -1;
+}
+
 empic_status check_launch(empic_sim *s, const char *what) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(s, e, what);
@@ -324,6 +368,8 @@ empic_status fault_status(empic_sim *s, uint32_t w) {
         snprintf(buf, sizeof buf, "corrupted particle state (fault word 0x%x)", w);
         return fail(s, EMPIC_E_STATE, buf);
     }
+    if (w & EMPIC_FAULT_CAPACITY)
+        return fail(s, EMPIC_E_CAPACITY, "moving-window injection skipped: species capacity");
     return EMPIC_OK;
 }
 
@@ -522,6 +568,7 @@ empic_status empic_load_particles_f64(empic_sim *s, int32_t sp, int64_t count,
         launch_load_f32(s->g, p, count, pos_xyz, u_xyz, w, ids, s->fault, s->stream);
     }
     S.host_count = count;
+    S.next_id = count;
     S.tiles_valid = false;
     s->need_sort = true;
     s->rho_prev_step = -1;
@@ -601,6 +648,46 @@ empic_status empic_set_port(empic_sim *s, const empic_port_desc *port) {
     return EMPIC_OK;
 }
 
+empic_status empic_set_window(empic_sim *s, const empic_window_desc *w) {
+    EMPIC_GUARD(s);
+    if (!w) return fail(s, EMPIC_E_ARG, "null window");
+    if (w->enabled) {
+        if (fp64(s)) return fail(s, EMPIC_E_UNSUPPORTED, "the moving window is for the FP32 path");
+        if (w->axis < 0 || w->axis > 2 || s->g.bc[w->axis] != EMPIC_BC_ABSORBING)
+            return fail(s, EMPIC_E_ARG, "the window moves along an absorbing axis");
+        if (w->cells < 1 || w->cells >= s->g.n[w->axis])
+            return fail(s, EMPIC_E_ARG, "window shift must be 1 .. n-1 cells");
+        if (!(w->velocity > 0.0) || !std::isfinite(w->velocity) || !std::isfinite(w->t_start))
+            return fail(s, EMPIC_E_ARG, "window needs a finite velocity > 0 and start time");
+    }
+    s->window = *w;
+    s->window_shifts = 0;
+    return EMPIC_OK;
+}
+
+empic_status empic_set_injection(empic_sim *s, int32_t sp, const int32_t per_cell[3], double w) {
+    EMPIC_GUARD(s);
+    if (sp < 0 || sp >= s->nsp || !per_cell) return fail(s, EMPIC_E_ARG, "bad injection species");
+    SpeciesState &S = s->sp[sp];
+    if (per_cell[0] == 0 && per_cell[1] == 0 && per_cell[2] == 0) {
+        S.inject = false;
+        return EMPIC_OK;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (per_cell[a] < 1 || per_cell[a] > 64) return fail(s, EMPIC_E_ARG, "1..64 particles per axis");
+    if (!(w > 0.0) || !std::isfinite(w)) return fail(s, EMPIC_E_ARG, "injection weight must be > 0");
+    if (!S.desc.per_particle_w && std::fabs(w - S.desc.w) > 1e-12 * std::fabs(S.desc.w))
+        return fail(s, EMPIC_E_ARG, "a species without per-particle weights injects its own weight");
+    S.inject = true;
+    for (int a = 0; a < 3; ++a) S.inj_per[a] = per_cell[a];
+    S.inj_w = w;
+    if (w > S.wmax) {
+        S.wmax = w;
+        update_jscale(s);
+    }
+    return EMPIC_OK;
+}
+
 empic_status empic_set_filter(empic_sim *s, int32_t passes, int32_t compensate) {
     EMPIC_GUARD(s);
     if (passes < 0 || passes > 16 || (compensate != 0 && compensate != 1))
@@ -626,6 +713,7 @@ empic_status empic_step(empic_sim *s, int32_t nsteps) {
         if (fp64(s)) {
             one_step<double>(s);
         } else {
+            if (s->window.enabled) window_step(s);
             const int S = s->desc.sort_every;
             if (s->nsp > 0 && (s->need_sort || (S > 0 && s->nstep % S == 0))) do_sort(s);
             one_step<float>(s);

@@ -282,6 +282,31 @@ __global__ void k_filter_pass(GridP g, int ax, const T *__restrict__ s0, const T
     }
 }
 
+// Moving window: every value moves `cells` planes toward index 0 along axis
+// ax; values that would come from beyond the stored ones are zero (the new
+// front planes); padding entries stay zero.  isB selects the B staggering.
+template <typename T>
+__global__ void k_window_shift(GridP g, int ax, int cells, int isB, const T *__restrict__ s0,
+                               const T *__restrict__ s1, const T *__restrict__ s2,
+                               T *__restrict__ d0, T *__restrict__ d1, T *__restrict__ d2) {
+    Pt q;
+    if (!make_point(g, q)) return;
+    const T *src[3] = {s0, s1, s2};
+    T *dst[3] = {d0, d1, d2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        bool pad = false;
+        for (int b = 0; b < 3; ++b) {
+            const bool half = isB ? (b != c) : (b == c);
+            if (g.bc[b] != EMPIC_BC_PERIODIC && half && q.idx[b] == g.n[b]) pad = true;
+        }
+        const bool half_ax = isB ? (ax != c) : (ax == c);
+        const int L = (g.bc[ax] != EMPIC_BC_PERIODIC && half_ax) ? g.n[ax] : g.ext[ax];
+        const int m = q.idx[ax];
+        dst[c][q.p] = (!pad && m + cells < L) ? src[c][q.p + (long long)cells * q.st[ax]] : T(0);
+    }
+}
+
 // FP64 partial sums of |E|^2 and B^{n-1/2}.B^{n+1/2} (B^{n+1/2} formed on the fly)
 template <typename T>
 __global__ void k_field_energy(GridP g, const T *__restrict__ Ex, const T *__restrict__ Ey,
@@ -399,6 +424,15 @@ void launch_filter(const GridP &g, T *const F[3], T *const tmp[3], int passes, i
 }
 
 template <typename T>
+void launch_window_shift(const GridP &g, T *const F[3], T *const tmp[3], int ax, int cells,
+                         bool isB, hipStream_t s) {
+    hipLaunchKernelGGL(k_window_shift<T>, point_grid(g), dim3(64, 4), 0, s, g, ax, cells,
+                       isB ? 1 : 0, F[0], F[1], F[2], tmp[0], tmp[1], tmp[2]);
+    for (int c = 0; c < 3; ++c)
+        (void)hipMemcpyAsync(F[c], tmp[c], (size_t)g.V * sizeof(T), hipMemcpyDeviceToDevice, s);
+}
+
+template <typename T>
 void launch_pec(const GridP &g, T *const E[3], hipStream_t s) {
     for (int a = 0; a < 3; ++a) {
         if (g.bc[a] != EMPIC_BC_PEC) continue;
@@ -446,6 +480,8 @@ void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *p
     template void launch_laser<T>(const GridP &, T *const[3], const empic_laser_desc &, double, \
                                   hipStream_t);                                                \
     template void launch_pec<T>(const GridP &, T *const[3], hipStream_t);                      \
+    template void launch_window_shift<T>(const GridP &, T *const[3], T *const[3], int, int,    \
+                                         bool, hipStream_t);                                   \
     template void launch_filter<T>(const GridP &, T *const[3], T *const[3], int, int,          \
                                    hipStream_t);                                               \
     template void launch_port<T>(const GridP &, T *const[3], const empic_port_desc &, double,  \

@@ -150,6 +150,16 @@ void launch_laser(const GridP &g, T *const E[3], const empic_laser_desc &L, doub
                   hipStream_t s);
 template <typename T>
 void launch_pec(const GridP &g, T *const E[3], hipStream_t s);
+// moving window: fields `cells` planes back along ax (tmp: three arrays)
+template <typename T>
+void launch_window_shift(const GridP &g, T *const F[3], T *const tmp[3], int ax, int cells,
+                         bool isB, hipStream_t s);
+// moving window: particle cells `cells` back along ax, removed below 0; cold
+// lattice injection into the cells [lo, lo + nc) after the slot count
+// (capacity exceeded: EMPIC_FAULT_CAPACITY, nothing injected)
+void launch_window_particles(const SpeciesP &sp, int ax, int cells, hipStream_t s);
+void launch_inject(const SpeciesP &sp, const int lo[3], const int nc[3], const int per[3],
+                   float w, int next_id, int32_t *reserve, uint32_t *fault, hipStream_t s);
 // current filter: `passes` binomial passes per axis, then the compensator;
 // tmp: three more arrays of the grid's size
 template <typename T>

@@ -688,10 +688,70 @@ inline unsigned nblk(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 __global__ void k_write_species(DevSpecies *dst, DevSpecies v) { *dst = v; }
 
+// moving window: the cell index of every particle moves `cells` back along
+// ax (offsets are relative to the cell and do not change); below 0: removed
+__global__ void k_window_particles(SpeciesP sp, int ax, int cells) {
+    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (p >= *sp.count) return;
+    const uint32_t c = sp.cell[p];
+    if (c == DEAD) return;
+    int v[3] = {cell_i(c), cell_j(c), cell_k(c)};
+    v[ax] -= cells;
+    sp.cell[p] = v[ax] < 0 ? DEAD : pack_cell(v[0], v[1], v[2]);
+}
+
+// reserve m slots after the current count (one thread)
+__global__ void k_inject_reserve(int32_t *count, long long cap, long long m, int32_t *reserve,
+                                 uint32_t *fault) {
+    const long long base = *count;
+    if (base + m <= cap) {
+        *count = (int32_t)(base + m);
+        *reserve = (int32_t)base;
+    } else {
+        *reserve = -1;
+        atomicOr(fault, (uint32_t)EMPIC_FAULT_CAPACITY);
+    }
+}
+
+// cold particles on a quiet lattice in cells [lo, lo + nc): per axis
+// (m + 1/2)/per offsets; x fastest, then y, then z over the lattice points
+__global__ void k_inject(SpeciesP sp, int lo0, int lo1, int lo2, int nx, int ny, int nz, int px,
+                         int py, int pz, float w, int next_id, const int32_t *reserve) {
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long NX = (long long)nx * px, NY = (long long)ny * py, NZ = (long long)nz * pz;
+    const int32_t base = *reserve;
+    if (base < 0 || t >= NX * NY * NZ) return;
+    const int ix = (int)(t % NX), iy = (int)((t / NX) % NY), iz = (int)(t / (NX * NY));
+    const long long p = base + t;
+    sp.cell[p] = pack_cell(lo0 + ix / px, lo1 + iy / py, lo2 + iz / pz);
+    ((float *)sp.pos[0])[p] = ((float)(ix % px) + 0.5f) / (float)px;
+    ((float *)sp.pos[1])[p] = ((float)(iy % py) + 0.5f) / (float)py;
+    ((float *)sp.pos[2])[p] = ((float)(iz % pz) + 0.5f) / (float)pz;
+    for (int a = 0; a < 3; ++a) ((float *)sp.u[a])[p] = 0.f;
+    sp.id[p] = next_id + (int32_t)t;
+    if (sp.per_particle_w && sp.w) ((float *)sp.w)[p] = w;
+}
+
 }  // namespace
 
 void launch_fill_i32(int32_t *p, long long n, int32_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_i32, dim3(1024), dim3(256), 0, s, p, n, v);
+}
+
+void launch_window_particles(const SpeciesP &sp, int ax, int cells, hipStream_t s) {
+    if (sp.capacity <= 0) return;
+    hipLaunchKernelGGL(k_window_particles, dim3(nblk(sp.capacity, 256)), dim3(256), 0, s, sp, ax,
+                       cells);
+}
+
+void launch_inject(const SpeciesP &sp, const int lo[3], const int nc[3], const int per[3],
+                   float w, int next_id, int32_t *reserve, uint32_t *fault, hipStream_t s) {
+    const long long m = (long long)nc[0] * per[0] * nc[1] * per[1] * nc[2] * per[2];
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_inject_reserve, dim3(1), dim3(1), 0, s, sp.count, sp.capacity, m, reserve,
+                       fault);
+    hipLaunchKernelGGL(k_inject, dim3(nblk(m, 256)), dim3(256), 0, s, sp, lo[0], lo[1], lo[2],
+                       nc[0], nc[1], nc[2], per[0], per[1], per[2], w, next_id, reserve);
 }
 
 void launch_write_species(DevSpecies *dst, const DevSpecies &v, hipStream_t s) {

@@ -55,8 +55,18 @@ class Sim:
             self.B.copy_(torch.from_numpy(np.asarray(workload.B0)).to(self.dev, self.dtype))
 
         nsp = len(workload.species)
-        self.caps = [_round_up(max(8, int(s.pos.shape[0] * (1.0 + capacity_slack))), 64)
-                     for s in workload.species]
+        win = getattr(workload, "window", None)
+        extra = [0] * nsp
+        if win is not None:
+            # room for a full window of injected plasma plus one shift in flight
+            # (removed particles are compacted by the sort after the injection)
+            for sp, per, _w in win.inject:
+                ppc = int(np.prod(per))
+                full = int(np.prod(n)) * ppc
+                m = full // int(n[win.axis]) * int(win.cells)
+                extra[sp] = m + max(0, full - workload.species[sp].pos.shape[0])
+        self.caps = [_round_up(max(8, int(s.pos.shape[0] * (1.0 + capacity_slack)) + extra[i]), 64)
+                     for i, s in enumerate(workload.species)]
         max_cap = max(self.caps) if self.caps else 0
         d = LB.GridDesc()
         for a in range(3):
@@ -96,6 +106,12 @@ class Sim:
             pd = LB.PortDesc(1, int(P.axis), int(P.plane), int(P.comp), int(P.prof_axis), 0,
                              float(P.e0), float(P.omega), float(P.tau))
             LB.check(h, self.L.empic_set_port(h, C.byref(pd)))
+        if win is not None:
+            wd = LB.WindowDesc(1, int(win.axis), int(win.cells), 0, float(win.velocity),
+                               float(win.t_start))
+            LB.check(h, self.L.empic_set_window(h, C.byref(wd)))
+            for sp, per, wi in win.inject:
+                LB.check(h, self.L.empic_set_injection(h, int(sp), (C.c_int32 * 3)(*per), float(wi)))
         torch.cuda.synchronize(self.dev)
 
     # -- set-up -----------------------------------------------------------------

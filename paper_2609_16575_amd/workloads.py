@@ -62,6 +62,18 @@ class PortInit:
 
 
 @dataclass
+class WindowInit:
+    """Moving window along a walled axis: shifts of `cells` cells once the
+    window has travelled (t - t_start) velocity; cold plasma injected into the
+    new cells: inject = [(species, (px, py, pz) per cell, weight), ...]."""
+    axis: int
+    cells: int
+    velocity: float
+    t_start: float
+    inject: list = field(default_factory=list)
+
+
+@dataclass
 class Workload:
     name: str
     n: tuple
@@ -73,6 +85,7 @@ class Workload:
     laser: Optional[LaserInit] = None
     port: Optional[PortInit] = None
     filter: Optional[tuple] = None    # (binomial passes, compensate) of the current filter
+    window: Optional[WindowInit] = None
     steps: int = 1
     sort_every: int = 10
     E0: Optional[np.ndarray] = None   # (3, ext_z, ext_y, ext_x) or None -> zero

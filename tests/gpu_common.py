@@ -21,6 +21,9 @@ def oracle_from(w, E0=None, B0=None):
     if getattr(w, "port", None) is not None:
         P = w.port
         sim.set_port(P.axis, P.plane, P.comp, P.prof_axis, P.e0, P.omega, P.tau)
+    if getattr(w, "window", None) is not None:
+        Wn = w.window
+        sim.set_window(Wn.axis, Wn.cells, Wn.velocity, Wn.t_start, Wn.inject)
     return sim
 
 

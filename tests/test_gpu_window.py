@@ -1,0 +1,129 @@
+"""Moving window on the GPU (FP32 path) against the oracle's window run.
+
+A reduced laser-wakefield box (Mur faces, laser sheet, cold slab with
+per-particle weights) whose window moves along x at c in shifts of 8 cells
+(one tile) and injects cold plasma on a (2, 1, 1) lattice.  Between
+comparisons the oracle takes the GPU's FP32-rounded state, so every
+comparison measures the steps since the last one; the steps that cross a
+shift are compared on their own at the one-step tolerance.
+"""
+import numpy as np
+import pytest
+
+from paper_2609_16575_amd import _lib as LB
+from paper_2609_16575_amd import workloads as W
+
+from gpu_common import compare_state, oracle_from
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(w, prec="fp32"):
+    from paper_2609_16575_amd.sim import Sim
+    return Sim(w, precision=prec)
+
+
+def _window_slab(cells=8, t_start=0.3, per=(2, 1, 1)):
+    w = W.lwfa_slab(n=(64, 16, 16), x_start=24, ramp=8, n_plasma=0.05, w0=1.5, tau=2.0)
+    w.laser.t0 = 0.0
+    w.E0, w.B0 = W.random_fields(w.n, w.bc, scale=0.02, seed=13)
+    w.window = W.WindowInit(axis=0, cells=cells, velocity=1.0, t_start=t_start,
+                            inject=[(0, per, w.species[0].w)])
+    return w
+
+
+def _sync(g, o):
+    """The oracle takes the GPU's state: fields, and live particles by id."""
+    E, B, _ = g.fields()
+    o.E[...] = E
+    o.B[...] = B
+    for i, s in enumerate(o.species):
+        P, U, I = g.particles_by_id(i)
+        s.pos[I] = P
+        s.u[I] = U
+
+
+def _shift_steps(w, nsteps):
+    """Steps at whose start the window shifts (the rule both sides apply)."""
+    Wn, out, k = w.window, [], 0
+    for n in range(nsteps):
+        if (n * w.dt - Wn.t_start) * Wn.velocity >= (k + 1) * Wn.cells * w.d[Wn.axis]:
+            out.append(n)
+            k += 1
+    return out
+
+
+def test_window_tracks_oracle():
+    w = _window_slab()
+    nsteps = 70
+    shifts = _shift_steps(w, nsteps)
+    assert len(shifts) >= 3, shifts
+    g, o = _sim(w), oracle_from(w, w.E0, w.B0)
+    _sync(g, o)
+    n = 0
+    for s in shifts:
+        if s > n:  # up to the step before the shift
+            g.step(s - n)
+            o.step(s - n)
+            compare_state(g, o, w, sp_tol=1e-4, f_tol=1e-4, label="to step %d" % s)
+            _sync(g, o)
+        g.step(1)  # the step that starts with the shift
+        o.step(1)
+        compare_state(g, o, w, sp_tol=2e-5, f_tol=2e-5, label="shift at step %d" % s)
+        _sync(g, o)
+        n = s + 1
+    g.step(nsteps - n)
+    o.step(nsteps - n)
+    compare_state(g, o, w, sp_tol=1e-4, f_tol=1e-4, label="end")
+    assert o.window["shifts"] == len(shifts)
+    # the injected plasma fills the new cells: the front cells hold particles
+    P, _, I = g.particles_by_id(0)
+    L = w.n[0] * w.d[0]
+    front = P[:, 0] >= L - w.window.cells * w.d[0]
+    assert front.sum() > 0 and I.max() >= w.species[0].pos.shape[0]
+    d = g.diagnostics()
+    assert d["fault_word"] & ~LB.FAULT_FALLBACK == 0, d["fault_word"]
+
+
+def test_window_continuity_between_shifts():
+    """Charge continuity holds on the steps that do not shift (the shift
+    itself moves charge with the grid, so it resets the residual)."""
+    w = _window_slab(t_start=0.0)
+    g = _sim(w)
+    shifts = set(_shift_steps(w, 40))
+    checked = 0
+    for n in range(40):
+        g.step(1)
+        d = g.diagnostics()
+        if n in shifts:
+            assert not d["cont_valid"], n
+            continue
+        if d["cont_valid"]:
+            assert d["cont_max"] <= 1e-5 * d["rho_max"], (n, d["cont_max"], d["rho_max"])
+            checked += 1
+    assert checked >= 30
+
+
+def test_window_rejected_on_fp64_path():
+    w = _window_slab()
+    with pytest.raises(LB.EmpicError) as e:
+        _sim(w, "fp64")
+    assert e.value.status == 7  # EMPIC_E_UNSUPPORTED
+
+
+def test_window_capacity_fault():
+    """An injection larger than the species' room raises the capacity fault
+    and injects nothing."""
+    import ctypes as C
+    w = _window_slab(t_start=0.0)
+    g = _sim(w)
+    LB.check(g.h, g.L.empic_set_injection(g.h, 0, (C.c_int32 * 3)(8, 8, 8), float(w.species[0].w)))
+    first = _shift_steps(w, 200)[0]
+    g.step(first)
+    n_before = g.count(0)
+    g.step(1)
+    g.sort()
+    assert g.count(0) <= n_before
+    with pytest.raises(LB.EmpicError) as e:
+        g.diagnostics()
+    assert e.value.status == 5  # EMPIC_E_CAPACITY
