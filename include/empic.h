@@ -125,11 +125,15 @@ typedef struct {
 /* Soft current-sheet laser source (READING of the paper's external-source
  * module, Sec. 2.5 and 3.2): J_y on x-node plane i_s radiating
  * E_inc = a0 exp(-r^2/w0^2) exp(-2 ln2 (t-t0)^2/tau^2) sin(omega0 (t-t0)),
- * r^2 = (y-yc)^2 + (z-zc)^2, in both directions. */
+ * r^2 = (y-yc)^2 + (z-zc)^2, in both directions.  slab = 1 drops the y term
+ * (r^2 = (z-zc)^2): the spot of the two-dimensional runs of Sec. 4, whose y
+ * axis is periodic and two cells wide. */
 typedef struct {
     double a0, w0, tau, t0, omega0, yc, zc;
     int32_t i_s;
     int32_t enabled;
+    int32_t slab;
+    int32_t pad;
 } empic_laser_desc;
 
 /* Waveguide port (the excitation of the field-solver benchmark, Sec. 3.2):

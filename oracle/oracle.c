@@ -46,7 +46,7 @@ typedef struct {
     double omega0;  /* carrier frequency */
     double yc, zc;  /* transverse centre of the spot */
     int32_t i_s;    /* x node index of the current sheet */
-    int32_t pad;
+    int32_t slab;   /* 1: spot Gaussian in z only, uniform along y (2D slab runs) */
 } orc_laser;
 
 typedef struct {
@@ -364,7 +364,8 @@ void orc_port_apply(const orc_grid *g, double *E, const orc_port *P, double t) {
 /* by the x = 0 face.  Applied to E after Ampere as -dt * J_sheet at         */
 /* t = t^{n+1/2}.                                                              */
 double orc_laser_field(const orc_laser *L, double t, double y, double z) {
-    const double r2 = (y - L->yc) * (y - L->yc) + (z - L->zc) * (z - L->zc);
+    const double ry2 = L->slab ? 0.0 : (y - L->yc) * (y - L->yc);
+    const double r2 = ry2 + (z - L->zc) * (z - L->zc);
     const double tt = t - L->t0;
     return L->a0 * exp(-r2 / (L->w0 * L->w0)) *
            exp(-2.0 * log(2.0) * tt * tt / (L->tau * L->tau)) * sin(L->omega0 * tt);

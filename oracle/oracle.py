@@ -36,7 +36,7 @@ class _Grid(C.Structure):
 class _Laser(C.Structure):
     _fields_ = [("a0", C.c_double), ("w0", C.c_double), ("tau", C.c_double),
                 ("t0", C.c_double), ("omega0", C.c_double), ("yc", C.c_double),
-                ("zc", C.c_double), ("i_s", C.c_int32), ("pad", C.c_int32)]
+                ("zc", C.c_double), ("i_s", C.c_int32), ("slab", C.c_int32)]
 
 
 class _Port(C.Structure):
@@ -166,10 +166,10 @@ class OracleSim:
         self.species.append(Species(q, m, w, pos, u, wpp, ids, absorbing))
         return len(self.species) - 1
 
-    def set_laser(self, a0, w0, tau, t0, omega0, yc, zc, i_s=1):
+    def set_laser(self, a0, w0, tau, t0, omega0, yc, zc, i_s=1, slab=False):
         L = _Laser()
         L.a0, L.w0, L.tau, L.t0, L.omega0 = a0, w0, tau, t0, omega0
-        L.yc, L.zc, L.i_s = yc, zc, int(i_s)
+        L.yc, L.zc, L.i_s, L.slab = yc, zc, int(i_s), int(bool(slab))
         self.laser = L
 
     def set_port(self, axis, plane, comp, prof_axis, e0, omega, tau):

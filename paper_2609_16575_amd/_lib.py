@@ -38,7 +38,8 @@ class ParticleBuffers(C.Structure):
 class LaserDesc(C.Structure):
     _fields_ = [("a0", C.c_double), ("w0", C.c_double), ("tau", C.c_double), ("t0", C.c_double),
                 ("omega0", C.c_double), ("yc", C.c_double), ("zc", C.c_double),
-                ("i_s", C.c_int32), ("enabled", C.c_int32)]
+                ("i_s", C.c_int32), ("enabled", C.c_int32), ("slab", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class PortDesc(C.Structure):

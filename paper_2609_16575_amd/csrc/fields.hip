@@ -194,7 +194,8 @@ __global__ void k_laser(GridP g, T *Ey, empic_laser_desc L, double t_half) {
     if (g.bc[2] != EMPIC_BC_PERIODIC && (k == 0 || k == g.n[2])) return;
     const double y = ((double)j + 0.5) * g.d[1];
     const double z = (double)k * g.d[2];
-    const double r2 = (y - L.yc) * (y - L.yc) + (z - L.zc) * (z - L.zc);
+    const double ry2 = L.slab ? 0.0 : (y - L.yc) * (y - L.yc);
+    const double r2 = ry2 + (z - L.zc) * (z - L.zc);
     const double tt = t_half - L.t0;
     const double einc = L.a0 * exp(-r2 / (L.w0 * L.w0)) *
                         exp(-2.0 * log(2.0) * tt * tt / (L.tau * L.tau)) * sin(L.omega0 * tt);

@@ -58,13 +58,14 @@ class Sim:
         win = getattr(workload, "window", None)
         extra = [0] * nsp
         if win is not None:
-            # room for a full window of injected plasma plus one shift in flight
-            # (removed particles are compacted by the sort after the injection)
+            # room for a full window of injected plasma, a quarter more for plasma
+            # compressed by the fields, and one shift in flight (removed
+            # particles are compacted by the sort after the injection)
             for sp, per, _w in win.inject:
                 ppc = int(np.prod(per))
                 full = int(np.prod(n)) * ppc
                 m = full // int(n[win.axis]) * int(win.cells)
-                extra[sp] = m + max(0, full - workload.species[sp].pos.shape[0])
+                extra[sp] = m + max(0, full - workload.species[sp].pos.shape[0]) + full // 4
         self.caps = [_round_up(max(8, int(s.pos.shape[0] * (1.0 + capacity_slack)) + extra[i]), 64)
                      for i, s in enumerate(workload.species)]
         max_cap = max(self.caps) if self.caps else 0
@@ -97,7 +98,8 @@ class Sim:
         LB.check(h, self.L.empic_set_background(h, float(workload.rho_bg)))
         if workload.laser is not None:
             Ls = workload.laser
-            ld = LB.LaserDesc(Ls.a0, Ls.w0, Ls.tau, Ls.t0, Ls.omega0, Ls.yc, Ls.zc, int(Ls.i_s), 1)
+            ld = LB.LaserDesc(Ls.a0, Ls.w0, Ls.tau, Ls.t0, Ls.omega0, Ls.yc, Ls.zc, int(Ls.i_s), 1,
+                              int(bool(Ls.slab)), 0)
             LB.check(h, self.L.empic_set_laser(h, C.byref(ld)))
         if getattr(workload, "filter", None):
             LB.check(h, self.L.empic_set_filter(h, int(workload.filter[0]), int(workload.filter[1])))

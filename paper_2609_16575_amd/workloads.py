@@ -47,6 +47,7 @@ class LaserInit:
     yc: float
     zc: float
     i_s: int = 1
+    slab: bool = False        # spot Gaussian in z only (two-dimensional runs)
 
 
 @dataclass
@@ -312,3 +313,86 @@ def pec_cavity_plasma(n=(16, 12, 8), d=(1.0, 0.9, 1.1), ppc=4, vth=0.3, seed=100
     w.E0, w.B0 = E, B
     return w
 
+
+
+# SI constants (CODATA 2018) for the unit conversions of the wakefield run
+C_SI = 299792458.0
+E_SI = 1.602176634e-19
+ME_SI = 9.1093837015e-31
+EPS0_SI = 8.8541878128e-12
+
+
+@dataclass
+class LaserUnits:
+    """Laser units of a run: c = omega0 = 1, lengths in c/omega0, densities in
+    n_c = eps0 m omega0^2 / e^2, fields in m c omega0 / e."""
+    lambda0_m: float
+
+    @property
+    def omega0(self) -> float:            # rad/s
+        return 2.0 * np.pi * C_SI / self.lambda0_m
+
+    @property
+    def length_m(self) -> float:          # c / omega0
+        return C_SI / self.omega0
+
+    @property
+    def time_s(self) -> float:            # 1 / omega0
+        return 1.0 / self.omega0
+
+    @property
+    def n_crit_cm3(self) -> float:
+        return EPS0_SI * ME_SI * self.omega0 ** 2 / E_SI ** 2 * 1e-6
+
+    @property
+    def field_v_per_m(self) -> float:     # m c omega0 / e
+        return ME_SI * C_SI * self.omega0 / E_SI
+
+
+def lwfa_2d(per=(4, 2, 4), cells=(1400, 2, 300), n0_cm3=3.0e18, lambda0_um=0.8,
+            fwhm_fs=28.0, w0_um=12.0, a0=3.0, window_lp=(3.0, 1.0, 3.0), travel_lp=6.0,
+            window_start=0.75, shift_cells=8, sort_every=10, steps=None):
+    """The two-dimensional laser-wakefield run of Sec. 4 (its parameter table).
+
+    Our x is the paper's propagation axis z, our z its transverse x, y is the
+    periodic axis two cells wide; the pulse is polarised along y.  Cell sizes
+    come from the paper's window (L_x, L_y, L_z) = (3, 1, 3) lambda_p over
+    (1400, 2, 300) cells, i.e. its (301 x 2 x 1401) counts of grid nodes;
+    `cells` may shrink the box at those cell sizes (parity runs).  Laser
+    units (LaserUnits); Courant 0.5.  A cold homogeneous electron plasma of
+    density n0 fills the box on a quiet `per` lattice (offsets (m + 1/2)/p)
+    over an immobile neutralising background; the window moves at c once
+    the pulse peak has crossed `window_start` of the box, in shifts of
+    `shift_cells` cells, injecting the same lattice.  The laser sheet sits
+    at x node 1: E_inc = a0 exp(-(z - zc)^2/w0^2) exp(-2 ln2 (t-t0)^2/tau^2)
+    sin(t - t0), tau = the intensity FWHM, t0 = 2.5 tau.  `steps` defaults to
+    the pulse peak travelling `travel_lp` plasma wavelengths past the sheet.
+    Deterministic (no random draws).
+    """
+    U = LaserUnits(lambda0_um * 1e-6)
+    n_pl = n0_cm3 / U.n_crit_cm3
+    lam_p = 2.0 * np.pi / np.sqrt(n_pl)
+    d = (float(window_lp[2] * lam_p / 1400.0), float(window_lp[1] * lam_p / 2.0),
+         float(window_lp[0] * lam_p / 300.0))
+    n = tuple(int(c) for c in cells)
+    dt = courant_dt(d)
+    ppc = int(np.prod(per))
+    dV = d[0] * d[1] * d[2]
+    w = n_pl * dV / ppc
+    pos = _quiet_lattice(n, d, per)
+    sp = SpeciesInit("electron", -1.0, 1.0, w, pos, np.zeros_like(pos))
+    tau = fwhm_fs * 1e-15 / U.time_s
+    t0 = 2.5 * tau
+    Lx, Ly, Lz = (float(n[a] * d[a]) for a in range(3))
+    laser = LaserInit(a0=a0, w0=w0_um * 1e-6 / U.length_m, tau=tau, t0=t0, omega0=1.0,
+                      yc=0.5 * Ly, zc=0.5 * Lz, i_s=1, slab=True)
+    window = WindowInit(axis=0, cells=shift_cells, velocity=1.0, t_start=t0 + window_start * Lx,
+                        inject=[(0, tuple(per), w)])
+    nsteps = int(np.ceil((t0 + travel_lp * lam_p) / dt)) if steps is None else int(steps)
+    wl = Workload("lwfa2d_%dx%dx%d_ppc%d" % (*n, ppc), n, d, dt, (ABSORBING, PERIODIC, ABSORBING),
+                  [sp], rho_bg=n_pl, laser=laser, window=window, steps=nsteps,
+                  sort_every=sort_every)
+    wl.units = U
+    wl.n_plasma = n_pl
+    wl.lambda_p = lam_p
+    return wl

@@ -15,7 +15,7 @@ def oracle_from(w, E0=None, B0=None):
     sim.rho_bg = w.rho_bg
     if w.laser is not None:
         L = w.laser
-        sim.set_laser(L.a0, L.w0, L.tau, L.t0, L.omega0, L.yc, L.zc, L.i_s)
+        sim.set_laser(L.a0, L.w0, L.tau, L.t0, L.omega0, L.yc, L.zc, L.i_s, L.slab)
     if getattr(w, "filter", None):
         sim.filter = tuple(w.filter)
     if getattr(w, "port", None) is not None:

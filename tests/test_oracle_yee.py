@@ -171,3 +171,37 @@ def test_laser_sheet_radiates_incident_amplitude():
     env = np.max(np.abs(np.exp(-2 * np.log(2) * tt ** 2 / tau ** 2) * np.sin(tt)))
     peak = np.max(np.abs(trace))
     assert abs(peak / (a0 * env) - 1.0) < 0.02, peak / (a0 * env)
+
+
+def _sheet_run(slab):
+    """Laser sheet in a (x, periodic y, absorbing z) box; E_y near the sheet
+    at the time of its largest on-axis value."""
+    n, d = (60, 4, 40), (0.1, 0.5, 0.5)
+    dt = O.courant_dt(d)
+    sim = O.OracleSim(n, d, dt, bc=(O.ABSORBING, O.PERIODIC, O.ABSORBING))
+    w0, zc = 4.0, 10.0
+    sim.set_laser(a0=1.0, w0=w0, tau=6.0, t0=15.0, omega0=4.0, yc=0.3, zc=zc, i_s=2, slab=slab)
+    probe, kc = 6, int(round(zc / d[2]))
+    best, snap = -1.0, None
+    for _ in range(int(round(24.0 / dt))):
+        sim.step(1)
+        v = abs(sim.E[1, kc, 0, probe])
+        if v > best:
+            best, snap = v, sim.E[1, :, :, probe].copy()  # (z nodes, y halves)
+    return snap, w0, zc, d
+
+
+def test_slab_laser_spot_is_uniform_along_y():
+    """Spot of the two-dimensional runs (Sec. 4): with slab set the field is
+    the same on every y row and keeps the Gaussian along z; without it the
+    rows differ (the y term is there)."""
+    snap, w0, zc, d = _sheet_run(True)
+    for j in range(1, snap.shape[1]):
+        assert np.array_equal(snap[:, j], snap[:, 0])
+    z = np.arange(snap.shape[0]) * d[2]
+    kc = int(round(zc / d[2]))
+    near = np.abs(z - zc) <= w0
+    prof = snap[near, 0] / snap[kc, 0]
+    assert np.max(np.abs(prof - np.exp(-((z[near] - zc) / w0) ** 2))) < 0.01
+    round_spot, *_ = _sheet_run(False)
+    assert np.max(np.abs(round_spot[:, 0] - round_spot[:, 1])) > 1e-3 * np.max(np.abs(round_spot))
