@@ -203,6 +203,25 @@ class Sim:
         keep = I >= 0
         return P[keep], U[keep], I[keep]
 
+    def sample_particles(self, sp: int, ids):
+        """(positions, momenta, ids) of the live particles of `sp` whose id is
+        in `ids`, sorted by id.  The selection runs on the device, so only the
+        sample is copied to the host."""
+        t = self.torch
+        cap = self.caps[sp]
+        pos = t.empty((cap, 3), dtype=t.float64, device=self.dev)
+        u = t.empty((cap, 3), dtype=t.float64, device=self.dev)
+        idv = t.empty(cap, dtype=t.int32, device=self.dev)
+        cnt = C.c_int64()
+        LB.check(self.h, self.L.empic_store_particles_f64(self.h, sp, _ptr(pos), _ptr(u), _ptr(idv),
+                                                          C.byref(cnt)))
+        n = cnt.value
+        want = t.as_tensor(np.asarray(ids, dtype=np.int32), device=self.dev)
+        m = t.isin(idv[:n], want) & (idv[:n] >= 0)
+        I = idv[:n][m]
+        order = t.argsort(I)
+        return tuple(x.cpu().numpy() for x in (pos[:n][m][order], u[:n][m][order], I[order]))
+
     def particles_by_id(self, sp: int):
         P, U, I = self.particles(sp)
         order = np.argsort(I, kind="stable")

@@ -1,0 +1,73 @@
+"""The laser-wakefield box and the Weibel plasma at their full sizes.
+
+1024 x 128 x 128 cells with Mur faces, the laser sheet and 29.4M
+particles with per-particle weights; and 256^3 cells with 16 electrons per
+cell (268M particles).  Both run in the configuration the FP32 step uses
+at scale (sorted tiles, fused kernel, sort every 10 steps); the oracle
+cannot step them whole, so it pushes a sample of particles one step with
+the GPU's fields, and the GPU's FP64 diagnostics give continuity at every
+node.  Particles are selected by id on the device.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_16575_amd import workloads as W
+
+from gpu_common import pos_err_cells, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _sampled_step(g, w, sample_ids, tol):
+    d0 = g.diagnostics()
+    E, B, _ = g.fields()
+    st = [g.sample_particles(i, sample_ids[i]) for i in range(len(w.species))]
+    g.step(1)
+    d = g.diagnostics()
+    assert d0["fault_word"] & ~16 == 0 and d["fault_word"] & ~16 == 0, (d0, d)
+    assert d["cont_valid"] and d["cont_max"] <= 1e-5 * d["rho_max"], d
+    o = O.OracleSim(w.n, w.d, w.dt, w.bc)
+    o.E[...] = E
+    o.B[...] = B
+    for i, (P, U, I) in enumerate(st):
+        s = w.species[i]
+        wpp = None if s.wpp is None else s.wpp[I]
+        o.add_species(s.q, s.m, s.w, P, U, wpp=wpp, ids=I)
+    o.step(1)
+    for i in range(len(w.species)):
+        s = o.species[i]
+        alive = s.alive.astype(bool) if s.alive is not None else np.ones(s.np, bool)
+        Pg, Ug, Ig = g.sample_particles(i, s.ids[alive])
+        assert np.array_equal(Ig, s.ids[alive]), (i, len(Ig), int(alive.sum()))
+        assert len(Ig) > 1000
+        assert pos_err_cells(Pg, s.pos[alive], w) <= tol
+        assert rel(Ug, s.u[alive]) <= tol
+
+
+def test_full_size_lwfa_slab_sampled():
+    """The static-window wakefield box: 300 steps bring the pulse into the
+    slab; half of the sample sits at the slab's front."""
+    w = W.lwfa_slab()
+    from paper_2609_16575_amd.sim import Sim
+    g = Sim(w, precision="fp32")
+    g.step(300)
+    rng = np.random.default_rng(1)
+    x = w.species[0].pos[:, 0] / w.d[0]
+    front = np.nonzero(x < 136.0)[0]
+    ids = np.concatenate([rng.choice(front, 3000, replace=False),
+                          rng.choice(w.n_particles, 3000, replace=False)])
+    _sampled_step(g, w, [np.unique(ids)], 2e-5)
+    g.close()
+
+
+def test_full_size_weibel_sampled():
+    """The 256^3 anisotropic plasma, 268M particles (one GPU's share of a
+    domain-decomposed run)."""
+    w = W.weibel_bimaxwellian()
+    from paper_2609_16575_amd.sim import Sim
+    g = Sim(w, precision="fp32")
+    g.step(12)  # past the first periodic sort after the initial one
+    rng = np.random.default_rng(2)
+    _sampled_step(g, w, [rng.choice(w.n_particles, 6000, replace=False)], 2e-5)
+    g.close()
