@@ -152,6 +152,50 @@ def copy_calibration(torch, nbytes=1 << 30):
     torch.cuda.synchronize()
 
 
+def other_workload(args, torch):
+    """FP32 step time of the other workloads at their full sizes (not the
+    headline line): the static-window wakefield box, the 256^3 anisotropic
+    plasma, and the two-dimensional wakefield run with its moving window."""
+    from paper_2609_16575_amd import workloads as W
+    from paper_2609_16575_amd.sim import Sim
+    if args.workload == "lwfa":
+        w = W.lwfa_slab()
+        desc = ("laser-wakefield box 1024x128x128, Mur faces, laser a0=2, cold slab with ramp, "
+                "2 per cell, per-particle weights (%d particles), sort every 10" % w.n_particles)
+    elif args.workload == "weibel256":
+        w = W.weibel_bimaxwellian()
+        desc = ("anisotropic electron plasma T_x/T_perp=25, periodic 256^3, 16 per cell "
+                "(%d particles), sort every 10" % w.n_particles)
+    else:
+        w = W.lwfa_2d(per=(4, 2, 4))
+        w.laser.t0 = 0.0
+        w.window.t_start = 0.0
+        desc = ("two-dimensional wakefield 1400x2x300, ppc 32, a0=3, window moving from the start "
+                "(%d particles), sort every 10" % w.n_particles)
+    sim = Sim(w, precision="fp32")
+    wall, kt = time_steps(sim, args.steps, args.warmup, torch)
+    push_ms = kt["push_ms"] / max(kt["push_n"], 1)
+    wpp = any(s.wpp is not None for s in w.species)
+    nbytes = (60.0 if wpp else 56.0) * w.n_particles + 36.0 * w.n_cells
+    achieved = nbytes / (push_ms * 1e-3) / 1e9
+    d = sim.diagnostics()
+    out = {"metric": METRIC, "value": w.n_particles * args.steps / wall, "unit": "particle-pushes/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": desc, "particles": w.n_particles, "cells": w.n_cells},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_push_fused",
+                        "avg_ms": push_ms, "algorithmic_bytes_per_launch": nbytes},
+           "breakdown_ms_per_step": {"push_fused": kt["push_ms"] / args.steps,
+                                     "fields": kt["field_ms"] / args.steps,
+                                     "sort": kt["sort_ms"] / args.steps},
+           "fp32_checks": {"fault_word": d["fault_word"],
+                           "fallback_particles": d["fallback_particles"]}}
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +207,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "adjoint"], default=None)
+    ap.add_argument("--workload", choices=["thermal", "lwfa", "weibel256", "lwfa2d"],
+                    default="thermal", help="thermal (the benchmark) or another workload's FP32 step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; "
@@ -170,6 +216,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.workload != "thermal":
+        other_workload(args, torch)
+        return
     from paper_2609_16575_amd import workloads as W
     from paper_2609_16575_amd.sim import Sim
 

@@ -201,8 +201,7 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
     float um[3], t[3], s[3], up[3], un[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) um[a] = fmaf(r, F6[a], u[a]);
-    const float gm = sqrtf(fmaf(um[0], um[0], fmaf(um[1], um[1], fmaf(um[2], um[2], 1.f))));
-    const float igm = rcpf(gm);
+    const float igm = rsqf(fmaf(um[0], um[0], fmaf(um[1], um[1], fmaf(um[2], um[2], 1.f))));
 #pragma unroll
     for (int a = 0; a < 3; ++a) t[a] = r * F6[3 + a] * igm;
     const float den = fmaf(t[0], t[0], fmaf(t[1], t[1], fmaf(t[2], t[2], 1.f)));
@@ -216,8 +215,7 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
     un[0] = fmaf(r, F6[0], um[0] + (up[1] * s[2] - up[2] * s[1]));
     un[1] = fmaf(r, F6[1], um[1] + (up[2] * s[0] - up[0] * s[2]));
     un[2] = fmaf(r, F6[2], um[2] + (up[0] * s[1] - up[1] * s[0]));
-    const float gn = sqrtf(fmaf(un[0], un[0], fmaf(un[1], un[1], fmaf(un[2], un[2], 1.f))));
-    const float ign = rcpf(gn);
+    const float ign = rsqf(fmaf(un[0], un[0], fmaf(un[1], un[1], fmaf(un[2], un[2], 1.f))));
     float dx[3], e[3];
     int dc[3];
 #pragma unroll

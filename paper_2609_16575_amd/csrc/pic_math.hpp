@@ -14,6 +14,9 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+// 1/sqrt(x) in one hardware approximation (one transcendental instead of a
+// square root and a reciprocal)
+__device__ __forceinline__ float rsqf(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
 
 // global index of cell-axis coordinate x on axis a: periodic wrap (any x),
@@ -72,8 +75,7 @@ __device__ inline void gather_global(const GridP &g, const float *const E[3], co
 __device__ __forceinline__ float boris_f32(float &ux, float &uy, float &uz, const float E[3],
                                            const float B[3], float r, float &gam) {
     const float umx = fmaf(r, E[0], ux), umy = fmaf(r, E[1], uy), umz = fmaf(r, E[2], uz);
-    const float gm = sqrtf(fmaf(umx, umx, fmaf(umy, umy, fmaf(umz, umz, 1.f))));
-    const float ig = rcpf(gm);
+    const float ig = rsqf(fmaf(umx, umx, fmaf(umy, umy, fmaf(umz, umz, 1.f))));  // 1/gamma-
     const float tx = r * B[0] * ig, ty = r * B[1] * ig, tz = r * B[2] * ig;
     const float sf = 2.f * rcpf(fmaf(tx, tx, fmaf(ty, ty, fmaf(tz, tz, 1.f))));
     const float sx = sf * tx, sy = sf * ty, sz = sf * tz;
@@ -86,8 +88,10 @@ __device__ __forceinline__ float boris_f32(float &ux, float &uy, float &uz, cons
     ux = fmaf(r, E[0], plx);
     uy = fmaf(r, E[1], ply);
     uz = fmaf(r, E[2], plz);
-    gam = sqrtf(fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.f))));
-    return rcpf(gam);
+    const float g2 = fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.f)));
+    const float igp = rsqf(g2);
+    gam = g2 * igp;
+    return igp;
 }
 
 // Line integral of the bilinear CIC edge weights along a straight segment
