@@ -86,9 +86,15 @@ enum {
 /* Grid and time step (Sec. 2.3).  dt must satisfy
  *   dt <= 1 / sqrt(1/d0^2 + 1/d1^2 + 1/d2^2)              (c = 1)
  * FP32_CELLREL additionally limits n to <= 2047 x 2047 x 1023 cells (the
- * packed cell index) unless the handle holds no particles (max_capacity 0).  sort_every = S > 0 re-sorts particles by tile and cell
- * at the start of every S-th step (FP32 path); 0 sorts only on request and
- * once before the first step. */
+ * packed cell index) unless the handle holds no particles (max_capacity 0).
+ * sort_every = S > 0 re-sorts particles by tile and cell at the start of
+ * every S-th step (FP32 path); 0 sorts only on request and once before the
+ * first step; -1 sorts adaptively: when particles leave their tile's
+ * windows faster than 2e-5 of the particle slots per step, or after 64
+ * steps.  The count is read back two steps late: each step waits for the
+ * step two before it, so the GPU always has a step queued.  The adaptive
+ * mode keeps four pinned host words and four events per handle (freed by
+ * empic_destroy). */
 typedef struct {
     int32_t n[3];
     int32_t bc[3];      /* EMPIC_BC_* per axis */

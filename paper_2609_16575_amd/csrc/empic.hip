@@ -150,6 +150,15 @@ struct empic_sim {
     void *filt = nullptr;
     long long nstep = 0, rho_prev_step = -1;
     bool need_sort = true;
+    // adaptive sorting (sort_every = -1): after every step the cumulative
+    // out-of-window count is copied into a ring of pinned host slots; the
+    // step two steps later reads it (so the GPU keeps a step queued)
+    bool adaptive = false;
+    unsigned long long *fb_host = nullptr;  // ADAPT_RING slots
+    hipEvent_t fb_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    long long fb_tag[4] = {-1, -1, -1, -1};  // nstep after which each slot was copied
+    long long fb_prev_tag = -1, last_sort_step = 0;
+    unsigned long long fb_prev = 0;
     double jscale = 1099511627776.0;  // fixed-point scale of the fused kernel's current window
     bool poisoned = false;
     std::string err;
@@ -248,6 +257,58 @@ void do_sort(empic_sim *s, int32_t *const *perm = nullptr) {
     }
     ev_end(s, t);
     s->need_sort = false;
+    s->last_sort_step = s->nstep;
+}
+
+// Adaptive sorting.  Particles that have drifted out of their tile's LDS
+// windows since the last sort are pushed by the slower global-memory pass,
+// and their number grows quickly once drift reaches the window margin.  The
+// step reads the count of two steps earlier (waiting for that step only, so
+// one step stays queued on the GPU); once out-of-window particles arrive
+// faster than SORT_RATE of the particle slots per step after the last sort,
+// or SORT_MAX steps have passed, it starts with a sort.
+constexpr int ADAPT_RING = 4;
+constexpr int ADAPT_LAG = 2;
+constexpr double SORT_RATE = 2e-5;
+constexpr int SORT_MAX = 64;
+
+void release_adaptive(empic_sim *s) {
+    for (int r = 0; r < ADAPT_RING; ++r)
+        if (s->fb_ev[r]) {
+            (void)hipEventSynchronize(s->fb_ev[r]);
+            (void)hipEventDestroy(s->fb_ev[r]);
+            s->fb_ev[r] = nullptr;
+        }
+    if (s->fb_host) (void)hipHostFree(s->fb_host);
+    s->fb_host = nullptr;
+}
+
+void adaptive_poll(empic_sim *s) {
+    if (s->nstep - s->last_sort_step >= SORT_MAX) s->need_sort = true;
+    const long long want = s->nstep - ADAPT_LAG;
+    if (want < 1) return;
+    const int slot = (int)(want % ADAPT_RING);
+    if (s->fb_tag[slot] != want) return;  // not recorded (first steps, other entry points)
+    s->fb_tag[slot] = -1;
+    if (hipEventSynchronize(s->fb_ev[slot]) != hipSuccess) return;  // reported by the step's check
+    const unsigned long long c = ((volatile unsigned long long *)s->fb_host)[slot];
+    if (s->fb_prev_tag == want - 1 && want - 1 >= s->last_sort_step && c >= s->fb_prev) {
+        long long slots = 0;
+        for (int i = 0; i < s->nsp; ++i) slots += s->sp[i].host_count;
+        if ((double)(c - s->fb_prev) > SORT_RATE * (double)(slots > 0 ? slots : 1))
+            s->need_sort = true;
+    }
+    s->fb_prev = c;
+    s->fb_prev_tag = want;
+}
+
+void adaptive_record(empic_sim *s) {
+    const int slot = (int)(s->nstep % ADAPT_RING);
+    if (hipMemcpyAsync(s->fb_host + slot, s->fallback, sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipEventRecord(s->fb_ev[slot], s->stream) != hipSuccess)
+        return;  // the step's error check reports it
+    s->fb_tag[slot] = s->nstep;
 }
 
 // One PIC cycle.  FP32 path: particles are read from buffer set bit s of
@@ -425,7 +486,7 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
     }
     if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return EMPIC_E_ARG;
     if (g->dt > (1.0 + 1e-12) / std::sqrt(inv2)) return EMPIC_E_CFL;  // 3D CFL, c = 1
-    if (g->sort_every < 0) return EMPIC_E_ARG;
+    if (g->sort_every < -1) return EMPIC_E_ARG;
     if (V >= (1LL << 31)) return EMPIC_E_UNSUPPORTED;
     for (int a = 0; a < 3; ++a)  // launch grids put one axis in a grid dimension
         if (g->n[a] + 1 > 65535) return EMPIC_E_UNSUPPORTED;
@@ -474,7 +535,19 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
     // zero the fault word, counters and the Bbar array (a fill kernel; no memset nodes)
     launch_fill_i32((int32_t *)(s->ws + L.fault), 16, 0, s->stream);
     launch_fill_i32((int32_t *)(s->ws + L.Bbar), (long long)(3 * s->g.V * es / 4), 0, s->stream);
-    if (hipGetLastError() != hipSuccess) {
+    bool ok = true;
+    if (g->sort_every < 0 && g->precision == EMPIC_FP32_CELLREL) {
+        s->adaptive = true;
+        ok = hipHostMalloc((void **)&s->fb_host, ADAPT_RING * sizeof(unsigned long long),
+                           hipHostMallocDefault) == hipSuccess;
+        for (int r = 0; ok && r < ADAPT_RING; ++r) {
+            ok = hipEventCreateWithFlags(&s->fb_ev[r], hipEventDisableTiming) == hipSuccess;
+            if (ok) s->fb_host[r] = 0;
+        }
+    }
+    if (!ok || hipGetLastError() != hipSuccess) {
+        (void)hipGetLastError();
+        release_adaptive(s);
         delete s;
         return EMPIC_E_HIP;
     }
@@ -714,9 +787,11 @@ empic_status empic_step(empic_sim *s, int32_t nsteps) {
             one_step<double>(s);
         } else {
             if (s->window.enabled) window_step(s);
+            if (s->adaptive) adaptive_poll(s);
             const int S = s->desc.sort_every;
             if (s->nsp > 0 && (s->need_sort || (S > 0 && s->nstep % S == 0))) do_sort(s);
             one_step<float>(s);
+            if (s->adaptive && s->nsp > 0) adaptive_record(s);
         }
     }
     return check_launch(s, "step");
@@ -1139,6 +1214,7 @@ const char *empic_last_error(const empic_sim *s) { return s ? s->err.c_str() : "
 
 void empic_destroy(empic_sim *s) {
     if (!s) return;
+    release_adaptive(s);
     for (TimedEvent &t : s->events) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);

@@ -266,13 +266,14 @@ def test_particles_leave_through_absorbing_faces():
 
 def test_full_size_thermal_ep_sampled():
     """Workload 2 at its full size (128^3, 8 e + 8 p per cell, 33.5M particles),
-    in the configuration the benchmark times: continuity per step from the
-    GPU's FP64 diagnostics, and sampled particles pushed one by one by the
-    oracle with the GPU's fields, for both arithmetic paths."""
+    in the configuration the benchmark times (adaptive sorting): continuity
+    per step from the GPU's FP64 diagnostics, and sampled particles pushed
+    one by one by the oracle with the GPU's fields, for both arithmetic
+    paths."""
     w = W.thermal_two_species()
     rng = np.random.default_rng(0)
     for prec, tol in (("fp32", 2e-5), ("fp64", 1e-12)):
-        g = _sim(w, prec)
+        g = _sim(w, prec, sort_every=-1)
         g.step(2)
         g.diagnostics()
         E, B, _ = g.fields()
