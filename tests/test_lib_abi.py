@@ -69,7 +69,7 @@ def test_argument_checks(L):
     assert _create(L, _desc(n=(4, 0, 4)))[0] == 1
     assert _create(L, _desc(bc=(1, 0, 0), n=(1, 4, 4)))[0] == 1   # absorbing axis needs n >= 2
     assert _create(L, _desc(prec=2))[0] == 1
-    assert _create(L, _desc(sort_every=-1))[0] == 1
+    assert _create(L, _desc(sort_every=-2))[0] == 1   # -1 is the adaptive policy
     assert _create(L, _desc(), species=0)[0] == 1
     assert _create(L, _desc(), ws=100)[0] == 1                     # unaligned workspace
     assert _create(L, _desc(n=(2048, 8, 8)))[0] == 7               # packed cell index limit
