@@ -33,7 +33,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "particle-pushes/s (gather+push+deposit+Yee) FP32 vs FP64; adjoint step ms"
 COUNTERS = os.path.join(ROOT, "profiles", "push_fused_thermal_ep_128_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2609_16575_amd", "csrc", "push_f32.hip")
+# the fused kernel's source: its file and the headers it is built from
+KERNEL_SRC = [os.path.join(ROOT, "paper_2609_16575_amd", "csrc", f)
+              for f in ("push_f32.hip", "pic_math.hpp", "internal.hpp")]
 
 
 def _log(*a):
@@ -41,7 +43,10 @@ def _log(*a):
 
 
 def kernel_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def time_steps(sim, steps, warmup, torch):
