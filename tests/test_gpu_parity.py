@@ -177,6 +177,53 @@ def test_fp32_edge_offsets_and_seams():
         _common_fp32_state(g, o)
 
 
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 2)])
+def test_fp32_ragged_grid(bc):
+    """A grid that is a multiple of the 8 x 8 x 4 tile on no axis (13 x 11 x 7),
+    periodic, and absorbing / periodic / PEC: hot electrons with per-particle
+    weights, one step from a common state, then five more."""
+    n, d = (13, 11, 7), (1.0, 0.9, 1.1)
+    rng = np.random.default_rng(31)
+    pos = W._uniform_in_cells(rng, n, d, 6)
+    u = rng.normal(0.0, 0.2, pos.shape)
+    wpp = 0.05 + 0.1 * rng.random(len(pos))
+    w = W.Workload("ragged", n, d, W.courant_dt(d), bc,
+                   [W.SpeciesInit("e", -1.0, 1.0, 0.1, pos, u, wpp=wpp)], sort_every=2)
+    w.E0, w.B0 = W.random_fields(n, bc, scale=0.05, seed=6)
+    g, o = _sim(w, "fp32"), oracle_from(w, w.E0, w.B0)
+    _common_fp32_state(g, o)
+    g.step(1)
+    o.step(1)
+    compare_state(g, o, w, sp_tol=2e-5, f_tol=2e-5, label="ragged 1 step")
+    g.step(5)
+    o.step(5)
+    compare_state(g, o, w, sp_tol=2e-4, f_tol=2e-4, label="ragged 6 steps")
+
+
+def test_fp32_largest_packed_cell_indices():
+    """The largest grid the packed FP32 cell index holds (2047 x 3 x 1023
+    cells, periodic): particles in the last cells and across the seams of
+    the long axes, one step against the oracle."""
+    n = (2047, 3, 1023)
+    d = (1.0, 1.0, 1.0)
+    rng = np.random.default_rng(41)
+    corners = np.array([[2046.5, 1.5, 1022.5], [0.2, 0.5, 1022.9], [2046.95, 2.9, 0.05],
+                        [1023.5, 1.5, 511.5], [0.01, 0.01, 0.01]])
+    pos = np.mod(np.repeat(corners, 16, axis=0) + rng.uniform(-0.4, 0.4, (80, 3)),
+                 np.array(n, dtype=float))
+    u = rng.choice([-0.5, 0.5], size=pos.shape) + rng.normal(0, 0.05, pos.shape)
+    w = W.Workload("largest", n, d, W.courant_dt(d), (0, 0, 0),
+                   [W.SpeciesInit("e", -1.0, 1.0, 0.5, pos, u)], sort_every=1)
+    w.E0, w.B0 = W.random_fields(n, scale=0.02, seed=12)
+    g, o = _sim(w, "fp32"), oracle_from(w, w.E0, w.B0)
+    _common_fp32_state(g, o)
+    for _ in range(2):
+        g.step(1)
+        o.step(1)
+        compare_state(g, o, w, sp_tol=2e-5, f_tol=2e-5, label="largest")
+        _common_fp32_state(g, o)
+
+
 def test_fp32_out_of_window_fallback():
     """No re-sort and fast particles: many leave their tile's LDS window and go
     through the global-memory path; results still match the oracle."""
