@@ -150,11 +150,13 @@ struct empic_sim {
     void *filt = nullptr;
     long long nstep = 0, rho_prev_step = -1;
     bool need_sort = true;
-    // adaptive sorting (sort_every = -1): after every step the cumulative
-    // out-of-window count is copied into a ring of pinned host slots; the
-    // step two steps later reads it (so the GPU keeps a step queued)
+    // adaptive sorting (sort_every = -1): every step's out-of-window pass
+    // writes the cumulative out-of-window count into a ring of pinned host
+    // slots; the step two steps later reads it (so the GPU keeps a step
+    // queued)
     bool adaptive = false;
     unsigned long long *fb_host = nullptr;  // ADAPT_RING slots
+    unsigned long long *fb_dev = nullptr;   // the same slots as the device addresses them
     hipEvent_t fb_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     long long fb_tag[4] = {-1, -1, -1, -1};  // nstep after which each slot was copied
     long long fb_prev_tag = -1, last_sort_step = 0;
@@ -302,12 +304,16 @@ void adaptive_poll(empic_sim *s) {
     s->fb_prev_tag = want;
 }
 
+// slot that the step about to run publishes into (the state after it)
+unsigned long long *adaptive_slot(empic_sim *s) {
+    return s->fb_dev + (s->nstep + 1) % ADAPT_RING;
+}
+
+// after the step: mark its slot with an event (the write itself is done by
+// the step's out-of-window pass)
 void adaptive_record(empic_sim *s) {
     const int slot = (int)(s->nstep % ADAPT_RING);
-    if (hipMemcpyAsync(s->fb_host + slot, s->fallback, sizeof(unsigned long long),
-                       hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-        hipEventRecord(s->fb_ev[slot], s->stream) != hipSuccess)
-        return;  // the step's error check reports it
+    if (hipEventRecord(s->fb_ev[slot], s->stream) != hipSuccess) return;  // reported by the step
     s->fb_tag[slot] = s->nstep;
 }
 
@@ -315,7 +321,8 @@ void adaptive_record(empic_sim *s) {
 // rd_mask and written to bit s of wr_mask of table `tbl` (the species' own
 // sets by default).
 template <typename T>
-void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, int wr_mask = -1) {
+void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, int wr_mask = -1,
+              unsigned long long *publish = nullptr) {
     T *E[3], *B[3], *J[3], *Bb[3];
     field_ptrs<T>(s, E, B, J, Bb);
     const bool absorbing = s->g.bc[0] == EMPIC_BC_ABSORBING || s->g.bc[1] == EMPIC_BC_ABSORBING ||
@@ -345,7 +352,7 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
                               (float *const *)J, tbl, s->nsp, rmask, wmask, s->fault, s->fallback,
                               s->fb_list, s->fb_count, (long long)s->max_capacity * s->max_species,
                               s->jscale, pass == 1, s->stream, pass == 0 ? tp.a : nullptr,
-                              pass == 0 ? tp.b : nullptr);
+                              pass == 0 ? tp.b : nullptr, pass == 1 ? publish : nullptr);
         if (s->timing) s->events.push_back(tp);
     } else {
         ev_begin(s, t, 0);
@@ -538,8 +545,10 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
     bool ok = true;
     if (g->sort_every < 0 && g->precision == EMPIC_FP32_CELLREL) {
         s->adaptive = true;
+        // coherent: the device's writes reach host memory without a flush
         ok = hipHostMalloc((void **)&s->fb_host, ADAPT_RING * sizeof(unsigned long long),
-                           hipHostMallocDefault) == hipSuccess;
+                           hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
+        ok = ok && hipHostGetDevicePointer((void **)&s->fb_dev, s->fb_host, 0) == hipSuccess;
         for (int r = 0; ok && r < ADAPT_RING; ++r) {
             ok = hipEventCreateWithFlags(&s->fb_ev[r], hipEventDisableTiming) == hipSuccess;
             if (ok) s->fb_host[r] = 0;
@@ -790,8 +799,9 @@ empic_status empic_step(empic_sim *s, int32_t nsteps) {
             if (s->adaptive) adaptive_poll(s);
             const int S = s->desc.sort_every;
             if (s->nsp > 0 && (s->need_sort || (S > 0 && s->nstep % S == 0))) do_sort(s);
-            one_step<float>(s);
-            if (s->adaptive && s->nsp > 0) adaptive_record(s);
+            const bool publish = s->adaptive && s->nsp > 0;
+            one_step<float>(s, nullptr, -1, -1, publish ? adaptive_slot(s) : nullptr);
+            if (publish) adaptive_record(s);
         }
     }
     return check_launch(s, "step");

@@ -172,13 +172,15 @@ void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *p
                          hipStream_t s);
 
 // FP32 cell-relative path.  fallback_pass = false launches the fused tile
-// kernel, true the follow-up pass over particles that left their tile window.
+// kernel, true the follow-up pass over particles that left their tile window;
+// that pass also writes the cumulative out-of-window count to `publish`
+// (device-accessible pinned host memory) when it is not null.
 void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
                        float *const Bbar[3], float *const J[3], const DevSpecies *tbl, int nsp,
                        unsigned cur_mask, unsigned wr_mask, uint32_t *fault, unsigned long long *fallback,
                        int2 *fb_list, unsigned *fb_count, long long fb_cap, double jscale,
                        bool fallback_pass, hipStream_t s, hipEvent_t ev_start = nullptr,
-                       hipEvent_t ev_stop = nullptr);
+                       hipEvent_t ev_stop = nullptr, unsigned long long *publish = nullptr);
 void launch_dry_push_f32(const GridP &g, float *const E[3], float *const Bbar[3],
                          const SpeciesP &sp, double *partial_slot, uint32_t *fault,
                          hipStream_t s);

@@ -49,6 +49,7 @@ struct FusedArgs {
     int2 *fb_list;                 // (species, slot) of this step's out-of-window particles
     unsigned *fb_count;            // [0] entries in fb_list, [1] block ticket of k_push_fallback
     long long fb_cap;
+    unsigned long long *publish;   // host-visible copy of *fallback (k_push_fallback), or null
 };
 
 // global atomic deposit of one segment's 12 values at cell (ci,cj,ck)
@@ -394,6 +395,11 @@ __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
         if (ticket == gridDim.x - 1) {
             atomicExch(A.fb_count, 0u);
             atomicExch(A.fb_count + 1, 0u);
+            if (A.publish) {
+                // every tile workgroup of this step has finished: the count is final
+                *(volatile unsigned long long *)A.publish = *(volatile unsigned long long *)A.fallback;
+                __threadfence_system();
+            }
         }
     }
 }
@@ -763,7 +769,7 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
                        unsigned cur_mask, unsigned wr_mask, uint32_t *fault, unsigned long long *fallback,
                        int2 *fb_list, unsigned *fb_count, long long fb_cap, double jscale,
                        bool fallback_pass, hipStream_t s, hipEvent_t ev_start,
-                       hipEvent_t ev_stop) {
+                       hipEvent_t ev_stop, unsigned long long *publish) {
     FusedArgs A;
     A.g = g;
     A.ti = ti;
@@ -784,6 +790,7 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
     A.fb_list = fb_list;
     A.fb_count = fb_count;
     A.fb_cap = fb_cap;
+    A.publish = publish;
     const int nb = 8 * ((ti.ntiles + 7) / 8);
     if (fallback_pass)
         hipLaunchKernelGGL(k_push_fallback, dim3(64), dim3(256), 0, s, A);

@@ -147,3 +147,42 @@ def test_lwfa2d_reduced_tracks_oracle():
     assert len(shifts) >= 3, shifts
     d = g.diagnostics()
     assert d["fault_word"] & ~LB.FAULT_FALLBACK == 0, d["fault_word"]
+
+
+def test_window_and_injection_argument_checks():
+    """Invalid settings are refused with EMPIC_E_ARG and leave the handle usable."""
+    import ctypes as C
+    w = _window_slab()
+    w.window = None
+    g = _sim(w)
+    L, h = g.L, g.h
+
+    def win(axis, cells, v, t0=0.0):
+        d = LB.WindowDesc(1, axis, cells, 0, v, t0)
+        return L.empic_set_window(h, C.byref(d))
+
+    assert win(0, 8, 1.0) == 0
+    w_per = w.species[0].w
+    assert win(3, 8, 1.0) == 1            # no such axis
+    assert win(0, 0, 1.0) == 1            # no shift
+    assert win(0, 64, 1.0) == 1           # shift of the whole box
+    assert win(0, 8, 0.0) == 1            # not moving
+    assert win(0, 8, float("nan")) == 1
+    per = (C.c_int32 * 3)
+    assert L.empic_set_injection(h, 0, per(2, 1, 1), w_per) == 0
+    assert L.empic_set_injection(h, 0, per(65, 1, 1), w_per) == 1
+    assert L.empic_set_injection(h, 0, per(2, 0, 1), w_per) == 1
+    assert L.empic_set_injection(h, 0, per(2, 1, 1), -1.0) == 1
+    assert L.empic_set_injection(h, 1, per(2, 1, 1), w_per) == 1   # no such species
+    assert L.empic_set_injection(h, 0, per(0, 0, 0), 0.0) == 0     # off
+    g.step(2)
+    d = g.diagnostics()
+    assert d["fault_word"] & ~LB.FAULT_FALLBACK == 0
+
+
+def test_window_needs_an_absorbing_axis():
+    import ctypes as C
+    w = W.langmuir_thermal(n=(16, 8, 8), steps=1)  # periodic everywhere
+    g = _sim(w)
+    d = LB.WindowDesc(1, 0, 4, 0, 1.0, 0.0)
+    assert g.L.empic_set_window(g.h, C.byref(d)) == 1
