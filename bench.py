@@ -149,6 +149,30 @@ def adjoint_leg(torch, n=128, steps=50, K=10):
             "loss": rec["loss"], "grad_u_norm": rec["gU_norm"], "grad_finite": rec["finite"]}
 
 
+def field_only_leg(torch, n=256, steps=50):
+    """The Yee update alone (Faraday + centring of B, Ampere-Maxwell) on a
+    periodic vacuum grid of n^3 cells: field cell-updates/s and the HBM
+    rate of the two curl kernels (60 + 48 algorithmic bytes per cell in
+    FP32: Faraday reads E, B and writes B, B-bar and the zeroed J; Ampere
+    reads E, B, J and writes E)."""
+    from paper_2609_16575_amd import workloads as W
+    from paper_2609_16575_amd.sim import Sim
+    w = W.Workload("vacuum", (n,) * 3, (1.0,) * 3, W.courant_dt((1.0,) * 3), (0, 0, 0), [])
+    w.E0, w.B0 = W.random_fields(w.n, scale=1.0, seed=3)
+    sim = Sim(w, precision="fp32")
+    wall, kt = time_steps(sim, steps, 5, torch)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    cells = w.n_cells
+    field_ms = kt["field_ms"] / steps
+    gbs = 108.0 * cells / (field_ms * 1e-3) / 1e9
+    return {"workload": "vacuum, periodic %d^3, FP32" % n, "cell_updates_per_s": cells * steps / wall,
+            "ms_per_step": 1e3 * wall / steps, "curl_kernels_ms_per_step": field_ms,
+            "achieved_GBps": gbs, "frac_of_hbm": gbs / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_cell": 108}
+
+
 def copy_calibration(torch, nbytes=1 << 30):
     """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
     x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -216,7 +240,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64", "adjoint"], default=None)
+    ap.add_argument("--only", choices=["fp32", "fp64", "adjoint", "fields"], default=None)
     ap.add_argument("--workload", choices=["thermal", "lwfa", "weibel256", "lwfa2d"],
                     default="thermal", help="thermal (the benchmark) or another workload's FP32 step")
     args = ap.parse_args()
@@ -288,6 +312,9 @@ def main():
         sim.close()
         del sim
         torch.cuda.empty_cache()
+
+    if args.only in (None, "fields"):
+        out["fields_only"] = field_only_leg(torch)
 
     out["adjoint"] = None
     if not args.no_adjoint and args.only in (None, "adjoint"):

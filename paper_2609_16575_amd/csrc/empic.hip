@@ -336,24 +336,27 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
     ev_end(s, t);
     // 2. gather, Boris, move, ZigZag for every species
     if constexpr (sizeof(T) == 4) {
-        unsigned mask = 0;
-        for (int i = 0; i < s->nsp; ++i) mask |= (unsigned)s->sp[i].cur << i;
-        if (!tbl) tbl = s->table;
-        const unsigned rmask = rd_mask < 0 ? mask : (unsigned)rd_mask;
-        const unsigned wmask = wr_mask < 0 ? mask : (unsigned)wr_mask;
-        // the fused kernel is timed by events attached to its own dispatch
-        TimedEvent tp{nullptr, nullptr, 0};
-        if (s->timing) {
-            (void)hipEventCreate(&tp.a);
-            (void)hipEventCreate(&tp.b);
+        if (s->nsp > 0) {  // a handle without species has nothing to push
+            unsigned mask = 0;
+            for (int i = 0; i < s->nsp; ++i) mask |= (unsigned)s->sp[i].cur << i;
+            if (!tbl) tbl = s->table;
+            const unsigned rmask = rd_mask < 0 ? mask : (unsigned)rd_mask;
+            const unsigned wmask = wr_mask < 0 ? mask : (unsigned)wr_mask;
+            // the fused kernel is timed by events attached to its own dispatch
+            TimedEvent tp{nullptr, nullptr, 0};
+            if (s->timing) {
+                (void)hipEventCreate(&tp.a);
+                (void)hipEventCreate(&tp.b);
+            }
+            for (int pass = 0; pass < 2; ++pass)
+                launch_push_fused(s->g, s->ti, (float *const *)E, (float *const *)Bb,
+                                  (float *const *)J, tbl, s->nsp, rmask, wmask, s->fault,
+                                  s->fallback, s->fb_list, s->fb_count,
+                                  (long long)s->max_capacity * s->max_species, s->jscale,
+                                  pass == 1, s->stream, pass == 0 ? tp.a : nullptr,
+                                  pass == 0 ? tp.b : nullptr, pass == 1 ? publish : nullptr);
+            if (s->timing) s->events.push_back(tp);
         }
-        for (int pass = 0; pass < 2; ++pass)
-            launch_push_fused(s->g, s->ti, (float *const *)E, (float *const *)Bb,
-                              (float *const *)J, tbl, s->nsp, rmask, wmask, s->fault, s->fallback,
-                              s->fb_list, s->fb_count, (long long)s->max_capacity * s->max_species,
-                              s->jscale, pass == 1, s->stream, pass == 0 ? tp.a : nullptr,
-                              pass == 0 ? tp.b : nullptr, pass == 1 ? publish : nullptr);
-        if (s->timing) s->events.push_back(tp);
     } else {
         ev_begin(s, t, 0);
         for (int i = 0; i < s->nsp; ++i)
