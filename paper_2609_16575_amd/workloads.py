@@ -1,4 +1,6 @@
-"""Seeded synthetic plasmas for the five workloads of this project.
+"""Seeded synthetic plasmas and set-ups of the workloads of this project
+(the five benchmark configurations, the waveguide and PEC cases, and the
+two-dimensional wakefield run of Sec. 4).
 
 This module only draws random numbers and lays out initial conditions; it
 holds none of the PIC step's arithmetic, so both the FP64 oracle and the HIP
