@@ -261,8 +261,10 @@ empic_status empic_set_window(empic_sim *s, const empic_window_desc *w);
  * particles per axis at offsets (m + 1/2)/per_cell[a], u = 0, weight w (a
  * species without per-particle weights injects its own w); ids continue
  * from the loaded count.  per_cell = {0,0,0} turns it off.  A shift that
- * would exceed the species' capacity injects nothing and raises
- * EMPIC_FAULT_CAPACITY. */
+ * would exceed the species' capacity injects nothing (its ids are skipped)
+ * and raises EMPIC_FAULT_CAPACITY.  Ids are int32: empic_step refuses a shift whose
+ * injection would take them past 2^31 - 1 (EMPIC_E_CAPACITY before that
+ * step; the handle stays usable). */
 empic_status empic_set_injection(empic_sim *s, int32_t sp, const int32_t per_cell[3], double w);
 
 /* Current filter (READING of the compensated smoothing module, Sec. 2.2):

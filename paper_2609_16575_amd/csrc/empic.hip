@@ -386,11 +386,22 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
 // move `cells` cells back along the window axis, particles behind it are
 // removed, cold plasma is injected into the new cells, and the next sort
 // regroups everything.
-void window_step(empic_sim *s) {
+// Returns false, changing nothing, when the injection would take a species'
+// int32 particle ids past 2^31 - 1.
+bool window_step(empic_sim *s) {
     const empic_window_desc &W = s->window;
     const int a = W.axis;
     const double t = s->nstep * s->g.dt;
-    if ((t - W.t_start) * W.velocity < (double)(s->window_shifts + 1) * W.cells * s->g.d[a]) return;
+    if ((t - W.t_start) * W.velocity < (double)(s->window_shifts + 1) * W.cells * s->g.d[a])
+        return true;
+    for (int i = 0; i < s->nsp; ++i) {
+        const SpeciesState &S = s->sp[i];
+        if (!S.inject) continue;
+        long long m = (long long)S.inj_per[0] * S.inj_per[1] * S.inj_per[2] * W.cells;
+        for (int b = 0; b < 3; ++b)
+            if (b != a) m *= s->g.n[b];
+        if (S.next_id + m > 2147483647LL) return false;
+    }
     s->window_shifts += 1;
     float *E[3], *B[3], *tmp[3];
     for (int c = 0; c < 3; ++c) {
@@ -417,6 +428,7 @@ void window_step(empic_sim *s) {
     }
     s->need_sort = true;
     s->rho_prev_step = -1;
+    return true;
 }
 
 empic_status check_launch(empic_sim *s, const char *what) {
@@ -798,7 +810,9 @@ empic_status empic_step(empic_sim *s, int32_t nsteps) {
         if (fp64(s)) {
             one_step<double>(s);
         } else {
-            if (s->window.enabled) window_step(s);
+            if (s->window.enabled && !window_step(s))
+                return fail(s, EMPIC_E_CAPACITY,
+                            "the injected plasma would take particle ids past 2^31 - 1");
             if (s->adaptive) adaptive_poll(s);
             const int S = s->desc.sort_every;
             if (s->nsp > 0 && (s->need_sort || (S > 0 && s->nstep % S == 0))) do_sort(s);

@@ -186,3 +186,28 @@ def test_window_needs_an_absorbing_axis():
     g = _sim(w)
     d = LB.WindowDesc(1, 0, 4, 0, 1.0, 0.0)
     assert g.L.empic_set_window(g.h, C.byref(d)) == 1
+
+
+def test_injection_refused_before_ids_overflow():
+    """Skipped injections still use up ids; once the next injection would
+    take them past 2^31 - 1 the step is refused with EMPIC_E_CAPACITY and
+    the handle stays usable."""
+    import ctypes as C
+    w = _window_slab(t_start=0.0)
+    g = _sim(w)
+    per = (C.c_int32 * 3)(64, 64, 64)  # 2^18 per cell: 2^29 per shift of 8 x 16 x 16 cells
+    LB.check(g.h, g.L.empic_set_injection(g.h, 0, per, float(w.species[0].w)))
+    refused = None
+    for n in range(200):
+        st = g.L.empic_step(g.h, 1)
+        if st != 0:
+            refused = (n, st)
+            break
+    assert refused is not None and refused[1] == 5, refused  # EMPIC_E_CAPACITY
+    shifts = [s for s in _shift_steps(w, 200) if s <= refused[0]]
+    assert len(shifts) == 4, (refused, shifts)  # ids 2^29 per shift: the fourth would pass 2^31 - 1
+    LB.check(g.h, g.L.empic_set_injection(g.h, 0, (C.c_int32 * 3)(0, 0, 0), 0.0))
+    g.step(3)
+    with pytest.raises(LB.EmpicError) as e:  # the skipped injections raised the fault
+        g.diagnostics()
+    assert e.value.status == 5
