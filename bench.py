@@ -205,7 +205,7 @@ def other_workload(args, torch):
         w.laser.t0 = 0.0
         w.window.t_start = 0.0
         desc = ("two-dimensional wakefield 1400x2x300, ppc 32, a0=3, window moving from the start "
-                "(%d particles), sort every 10" % w.n_particles)
+                "(%d particles), 16x2x8 tiles, adaptive sort" % w.n_particles)
     sim = Sim(w, precision="fp32", sort_every=sort_every)
     wall, kt = time_steps(sim, args.steps, args.warmup, torch)
     push_ms = kt["push_ms"] / max(kt["push_n"], 1)

@@ -383,8 +383,12 @@ empic_status empic_dot_f64(empic_sim *s, const float *a, const float *b, int64_t
 
 /* Cells per tile of the FP32 path's sort order and fused kernel (x, y, z):
  * particles are stored tile by tile (tiles x-fastest), cell by cell inside a
- * tile (x-fastest).  Host-only; needs no handle. */
+ * tile (x-fastest).  empic_tile_shape gives the shape of three-dimensional
+ * grids (8 x 8 x 4); empic_grid_tile_shape the shape a grid gets, 16 x 2 x 8
+ * when it is at most three cells thick along y (the two-dimensional runs of
+ * Sec. 4).  Host-only; no handle needed. */
 void empic_tile_shape(int32_t out[3]);
+void empic_grid_tile_shape(const empic_grid_desc *g, int32_t out[3]);
 
 /* Per-handle message for the last failed call; valid until the next call. */
 const char *empic_last_error(const empic_sim *s);

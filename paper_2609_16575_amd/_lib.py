@@ -118,6 +118,7 @@ SIGNATURES = {
     "empic_sort_recorded": (C.c_int, [_P, C.c_void_p * MAX_SPECIES]),
     "empic_sort_vjp": (C.c_int, [_P, C.c_void_p * MAX_SPECIES, C.POINTER(Adjoint)]),
     "empic_tile_shape": (None, [C.POINTER(C.c_int32)]),
+    "empic_grid_tile_shape": (None, [C.POINTER(GridDesc), C.POINTER(C.c_int32)]),
     "empic_last_error": (C.c_char_p, [_P]),
     "empic_destroy": (None, [_P]),
 }
@@ -141,9 +142,14 @@ def lib():
     return L
 
 
-def tile_shape():
+def tile_shape(grid=None):
+    """Tile shape of the FP32 path: of three-dimensional grids, or the one
+    the grid descriptor `grid` gets."""
     out = (C.c_int32 * 3)()
-    lib().empic_tile_shape(out)
+    if grid is None:
+        lib().empic_tile_shape(out)
+    else:
+        lib().empic_grid_tile_shape(C.byref(grid), out)
     return tuple(out)
 
 

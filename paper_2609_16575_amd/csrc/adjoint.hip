@@ -54,14 +54,15 @@ __device__ __forceinline__ int pwrap(int x, int n) {
 }
 
 // ---- field and lam_E' access: the tile's LDS windows or global memory --------
+template <class TL>
 struct LdsAcc {
     const float *sF;  // 6 x FW3: E0..2, Bbar0..2
     const float *sL;  // 3 x JW3: lam_E'
     __device__ float F(int q, int i, int j, int k) const {
-        return sF[q * FW3 + i + FWX * (j + FWY * k)];
+        return sF[q * TL::FW3 + i + TL::FWX * (j + TL::FWY * k)];
     }
     __device__ float L(int c, int i, int j, int k) const {
-        return sL[c * JW3 + i + JWX * (j + JWY * k)];
+        return sL[c * TL::JW3 + i + TL::JWX * (j + TL::JWY * k)];
     }
 };
 
@@ -344,11 +345,14 @@ __device__ void scatter_global(const GlobAcc &G, float *const lEg[3], float *con
 }
 
 // window-row tables of a tile: global x index, y*ext0, z*ext0*ext1 (periodic)
-__device__ __forceinline__ void window_rows(const GridP &g, const int wo[3], int sG[3][16]) {
+template <class TL>
+__device__ __forceinline__ void window_rows(const GridP &g, const int wo[3],
+                                            int sG[3][TL::ROWS]) {
+    constexpr int ROWS = TL::ROWS;
     const int tid = threadIdx.x;
-    if (tid < 3 * 16) {
-        const int a = tid / 16, r = tid % 16;
-        const int wl = a == 0 ? JWX : (a == 1 ? JWY : JWZ);
+    if (tid < 3 * ROWS) {
+        const int a = tid / ROWS, r = tid % ROWS;
+        const int wl = a == 0 ? TL::JWX : (a == 1 ? TL::JWY : TL::JWZ);
         if (r < wl) {
             const int mul = a == 0 ? 1 : (a == 1 ? g.ext[0] : g.ext[0] * g.ext[1]);
             sG[a][r] = pwrap(wo[a] + r, g.n[a]) * mul;
@@ -356,7 +360,9 @@ __device__ __forceinline__ void window_rows(const GridP &g, const int wo[3], int
     }
 }
 
+template <class TL>
 __device__ __forceinline__ int tile_of_block(const TileInfo &ti, int wo[3]) {
+    constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
     const int nb8 = gridDim.x >> 3;
     const int tile = (blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);  // XCD-contiguous tiles
     const int tx = tile % ti.nt[0];
@@ -373,20 +379,23 @@ __device__ __forceinline__ int tile_of_block(const TileInfo &ti, int wo[3]) {
 // arrays A.l6, zero for particles handled elsewhere) and the tile's exponent:
 // all its |lam_Ep|, |lam_Bp| < 2^tile_exp.
 // three waves per SIMD measure faster than two without spills
+template <class TL>
 __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, AdjSpecies S) {
+    constexpr int FWX = TL::FWX, FWY = TL::FWY, FW3 = TL::FW3;
+    constexpr int JWX = TL::JWX, JWY = TL::JWY, JW3 = TL::JW3;
     __shared__ float sF[6 * FW3];
     __shared__ float sL[3 * JW3];
-    __shared__ int sG[3][16];
+    __shared__ int sG[3][TL::ROWS];
     __shared__ int sE;
 
     const GridP &g = A.g;
     int wo[3];
-    const int tile = tile_of_block(A.ti, wo);
+    const int tile = tile_of_block<TL>(A.ti, wo);
     if (tile >= A.ti.ntiles) return;
     const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
     if (beg >= end) return;
     const int tid = threadIdx.x;
-    window_rows(g, wo, sG);
+    window_rows<TL>(g, wo, sG);
     if (tid == 0) sE = NO_EXP;
     __syncthreads();
     for (int e = tid; e < 6 * FW3; e += ADJ_THREADS) {
@@ -408,11 +417,11 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
     }
     __syncthreads();
 
-    const LdsAcc lacc{sF, sL};
+    const LdsAcc<TL> lacc{sF, sL};
     const GlobAcc gacc{g.n[0], g.n[1], g.n[2], g.ext[0], g.ext[1],
                        {A.E[0], A.E[1], A.E[2]}, {A.Bb[0], A.Bb[1], A.Bb[2]},
                        {A.lJ[0], A.lJ[1], A.lJ[2]}};
-    constexpr int LHI_X = TX + 2 * MARGIN, LHI_Y = TY + 2 * MARGIN, LHI_Z = TZ + 2 * MARGIN;
+    constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
     int emax = NO_EXP;
     for (int base = (beg & ~(APPT - 1)) + tid * APPT; base < end; base += ADJ_THREADS * APPT) {
         const vuA c4 = *(const vuA *)(S.cell + base);
@@ -511,13 +520,15 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
 // rounded to an int32 (error <= 2^-32 of the tile's largest |lam|); one
 // entry takes at most one contribution per particle, so the sum cannot
 // overflow.  Lanes of a wave take particles 16 apart, in different cells.
+template <class TL>
 __global__ __launch_bounds__(SCAT_THREADS) void k_adj_scatter(AdjArgs A, AdjSpecies S) {
+    constexpr int FWX = TL::FWX, FWY = TL::FWY, FW3 = TL::FW3;
     __shared__ unsigned long long sA[6 * FW3];
-    __shared__ int sG[3][16];
+    __shared__ int sG[3][TL::ROWS];
 
     const GridP &g = A.g;
     int wo[3];
-    const int tile = tile_of_block(A.ti, wo);
+    const int tile = tile_of_block<TL>(A.ti, wo);
     if (tile >= A.ti.ntiles) return;
     const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
     if (beg >= end) return;
@@ -525,10 +536,10 @@ __global__ __launch_bounds__(SCAT_THREADS) void k_adj_scatter(AdjArgs A, AdjSpec
     if (et == NO_EXP) return;
     const int ee = max(et, -96);  // keeps the scale a finite float
     const int tid = threadIdx.x;
-    window_rows(g, wo, sG);
+    window_rows<TL>(g, wo, sG);
     for (int e = tid; e < 6 * FW3; e += SCAT_THREADS) sA[e] = 0ull;
     __syncthreads();
-    constexpr int LHI_X = TX + 2 * MARGIN, LHI_Y = TY + 2 * MARGIN, LHI_Z = TZ + 2 * MARGIN;
+    constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
     const float scale = ldexpf(1.f, EB - ee);  // at most 2^127
     const int q0 = (tid & 63) * (SPPT * (SCAT_THREADS / 64)) + (tid >> 6) * SPPT;
     for (int base = (beg & ~(SPPT - 1)) + q0; base < end; base += SCAT_THREADS * SPPT) {
@@ -741,10 +752,20 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
         A.fb_cap = fb_cap < sp[i].capacity ? fb_cap : sp[i].capacity;
         for (int q = 0; q < 6; ++q) A.l6[q] = l6[i][q];
         launch_fill_i32((int32_t *)fb_count, 1, 0, s);
-        hipLaunchKernelGGL(k_adj_particles, dim3(nblocks), dim3(ADJ_THREADS), 0, s, A, S);
+        if (ti.slab)
+            hipLaunchKernelGGL(k_adj_particles<TileSlab>, dim3(nblocks), dim3(ADJ_THREADS), 0, s,
+                               A, S);
+        else
+            hipLaunchKernelGGL(k_adj_particles<TileCube>, dim3(nblocks), dim3(ADJ_THREADS), 0, s,
+                               A, S);
         hipLaunchKernelGGL(k_adj_fallback, dim3(64), dim3(256), 0, s, A, S);
         launch_fill_i32((int32_t *)fb_count, 1, 0, s);  // the step kernels expect it empty
-        hipLaunchKernelGGL(k_adj_scatter, dim3(nblocks), dim3(SCAT_THREADS), 0, s, A, S);
+        if (ti.slab)
+            hipLaunchKernelGGL(k_adj_scatter<TileSlab>, dim3(nblocks), dim3(SCAT_THREADS), 0, s,
+                               A, S);
+        else
+            hipLaunchKernelGGL(k_adj_scatter<TileCube>, dim3(nblocks), dim3(SCAT_THREADS), 0, s,
+                               A, S);
     }
     const dim3 grid((g.n[0] + 63) / 64, (g.n[1] + 3) / 4, g.n[2]);
     hipLaunchKernelGGL(k_adj_bprime, grid, dim3(64, 4), 0, s, g, lE[0], lE[1], lE[2], lB[0], lB[1],

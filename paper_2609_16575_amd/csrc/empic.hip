@@ -28,14 +28,28 @@ struct Layout {
     long long mur_stride;
 };
 
+// The tile shape of a grid: 16 x 2 x 8 when it is at most three cells thick
+// along y (the two-dimensional runs), else 8 x 8 x 4.
+void tile_shape_of(const empic_grid_desc *d, int t[3], int &slab) {
+    slab = d->n[1] <= 3 ? 1 : 0;
+    t[0] = slab ? TileSlab::TX : TileCube::TX;
+    t[1] = slab ? TileSlab::TY : TileCube::TY;
+    t[2] = slab ? TileSlab::TZ : TileCube::TZ;
+}
+
 void grid_info(const empic_grid_desc *d, GridP &g, TileInfo &ti) {
+    int t[3];
+    tile_shape_of(d, t, ti.slab);
     for (int a = 0; a < 3; ++a) {
         g.n[a] = d->n[a];
         g.bc[a] = d->bc[a];
         g.ext[a] = d->n[a] + (d->bc[a] != EMPIC_BC_PERIODIC ? 1 : 0);  // walled: n+1 planes
         g.d[a] = d->d[a];
         g.inv_d[a] = 1.0 / d->d[a];
-        ti.nt[a] = (d->n[a] + (a == 0 ? TX : a == 1 ? TY : TZ) - 1) / (a == 0 ? TX : a == 1 ? TY : TZ);
+        ti.nt[a] = (d->n[a] + t[a] - 1) / t[a];
+        int lg = 0;
+        while ((1 << lg) < t[a]) ++lg;
+        ti.lg[a] = lg;
     }
     g.dt = d->dt;
     g.V = (long long)g.ext[0] * g.ext[1] * g.ext[2];
@@ -1232,9 +1246,16 @@ empic_status empic_dot_f64(empic_sim *s, const float *a, const float *b, int64_t
 
 void empic_tile_shape(int32_t out[3]) {
     if (!out) return;
-    out[0] = TX;
-    out[1] = TY;
-    out[2] = TZ;
+    out[0] = TileCube::TX;
+    out[1] = TileCube::TY;
+    out[2] = TileCube::TZ;
+}
+
+void empic_grid_tile_shape(const empic_grid_desc *g, int32_t out[3]) {
+    if (!g || !out) return;
+    int t[3], slab;
+    tile_shape_of(g, t, slab);
+    for (int a = 0; a < 3; ++a) out[a] = t[a];
 }
 
 const char *empic_last_error(const empic_sim *s) { return s ? s->err.c_str() : "null handle"; }

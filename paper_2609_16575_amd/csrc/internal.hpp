@@ -22,23 +22,37 @@ struct GridP {
     long long V;  // ext0 * ext1 * ext2
 };
 
-// Tile of cells owned by one workgroup of the fused FP32 particle kernel.
-// 8 x 8 x 4 keeps the LDS field window (27.6 KB) plus the int64 current
-// window (36.5 KB) under 80 KB, so two workgroups share a CU.
-constexpr int TX = 8, TY = 8, TZ = 4;
-constexpr int TC = TX * TY * TZ;
 // Drift margin: particles up to MARGIN cells outside their tile (moved since
 // the last sort) are still served from the tile's LDS windows.
 constexpr int MARGIN = 1;
-// LDS field window (gather stencil: cells -1..+1 around a particle cell).
-constexpr int FWX = TX + 2 * MARGIN + 2, FWY = TY + 2 * MARGIN + 2, FWZ = TZ + 2 * MARGIN + 2;
-// LDS current window (second ZigZag segment may sit one cell further, edges +1).
-constexpr int JWX = TX + 2 * MARGIN + 3, JWY = TY + 2 * MARGIN + 3, JWZ = TZ + 2 * MARGIN + 3;
-constexpr int FW3 = FWX * FWY * FWZ;
-constexpr int JW3 = JWX * JWY * JWZ;
 constexpr int PUSH_THREADS = 512;
 constexpr int PPT = 4;  // consecutive particles per thread (one 16-byte access per array)
-static_assert(JWX <= 16 && JWY <= 16 && JWZ <= 16, "window index tables hold 16 rows");
+constexpr int TC = 256;  // cells per tile (every shape)
+
+// Tile of cells owned by one workgroup of the fused FP32 particle kernel, and
+// its LDS windows: the field window covers the gather stencil (cells -1..+1
+// around a particle cell), the current window one cell more (the second
+// ZigZag segment) and the far edges.
+template <int X, int Y, int Z>
+struct TileT {
+    static constexpr int TX = X, TY = Y, TZ = Z;
+    static constexpr int FWX = X + 2 * MARGIN + 2, FWY = Y + 2 * MARGIN + 2, FWZ = Z + 2 * MARGIN + 2;
+    static constexpr int JWX = X + 2 * MARGIN + 3, JWY = Y + 2 * MARGIN + 3, JWZ = Z + 2 * MARGIN + 3;
+    static constexpr int FW3 = FWX * FWY * FWZ, JW3 = JWX * JWY * JWZ;
+    static constexpr int LHI_X = X + 2 * MARGIN, LHI_Y = Y + 2 * MARGIN, LHI_Z = Z + 2 * MARGIN;
+    static constexpr int ROWS = 24;  // rows of the window index tables
+    static_assert(X * Y * Z == TC, "every tile shape holds TC cells");
+    static_assert(JWX <= ROWS && JWY <= ROWS && JWZ <= ROWS, "window index tables");
+    static_assert((X & (X - 1)) == 0 && (Y & (Y - 1)) == 0 && (Z & (Z - 1)) == 0,
+                  "power-of-two tile sides (sort keys use shifts)");
+};
+// Three-dimensional grids: 8 x 8 x 4, field window 27.6 KB + int64 current
+// window 36.5 KB, two workgroups per CU.
+using TileCube = TileT<8, 8, 4>;
+// Grids at most three cells thick along y (the two-dimensional runs):
+// 16 x 2 x 8 keeps 256 cells per tile where the cube would hold 8 x 2 x 4;
+// 34.6 KB + 45.9 KB, still two workgroups in a CU's 160 KB of LDS.
+using TileSlab = TileT<16, 2, 8>;
 
 // Packed cell index of the FP32 path: i | j << 11 | k << 22; all ones = removed.
 constexpr uint32_t DEAD = 0xFFFFFFFFu;
@@ -51,15 +65,17 @@ __host__ __device__ inline int cell_k(uint32_t c) { return (int)(c >> 22); }
 
 struct TileInfo {
     int nt[3];      // tiles per axis
+    int lg[3];      // log2 of the tile sides
     int ntiles;
+    int slab;       // 1: TileSlab, 0: TileCube
     long long NK;   // ntiles * TC sort keys
 };
 
 __host__ __device__ inline long long sort_key(const TileInfo &t, int i, int j, int k) {
-    const int tx = i / TX, ty = j / TY, tz = k / TZ;
-    const int lx = i - tx * TX, ly = j - ty * TY, lz = k - tz * TZ;
+    const int tx = i >> t.lg[0], ty = j >> t.lg[1], tz = k >> t.lg[2];
+    const int lx = i - (tx << t.lg[0]), ly = j - (ty << t.lg[1]), lz = k - (tz << t.lg[2]);
     const long long tile = tx + (long long)t.nt[0] * (ty + (long long)t.nt[1] * tz);
-    return tile * TC + (lx + TX * (ly + TY * lz));
+    return tile * TC + (lx + ((ly + (lz << t.lg[1])) << t.lg[0]));
 }
 
 // Per-species launch parameters of the particle kernels.

@@ -177,8 +177,10 @@ __device__ __forceinline__ bool new_cell(const GridP &g, int a, int c, int dc, i
 }
 
 // ---- LDS window versions ----
+template <class TL>
 __device__ __forceinline__ float tri_lds(const float *F, int i, int j, int k, float fx, float fy,
                                          float fz) {
+    constexpr int FWX = TL::FWX, FWY = TL::FWY;
     const float *p = F + i + FWX * (j + FWY * k);
     const float c00 = lerpf(p[0], p[1], fx);
     const float c10 = lerpf(p[FWX], p[FWX + 1], fx);
@@ -188,7 +190,9 @@ __device__ __forceinline__ float tri_lds(const float *F, int i, int j, int k, fl
 }
 
 // J window offsets of the 12 edges of a cell, in segment_weights order
+template <class TL>
 __device__ __forceinline__ int edge_off(int q) {
+    constexpr int JWX = TL::JWX, JWY = TL::JWY, JW3 = TL::JW3;
     // J_x (oy,oz); J_y (oz,ox); J_z (ox,oy)
     const int c = q >> 2, b = q & 3, o1 = b & 1, o2 = b >> 1;
     if (c == 0) return JW3 * 0 + o1 * JWX + o2 * JWX * JWY;

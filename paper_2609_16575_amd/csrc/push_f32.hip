@@ -122,21 +122,27 @@ __device__ void particle_global(const FusedArgs &A, const DevSpecies &D, uint32_
 // The LDS current window accumulates int64 fixed point: integer LDS atomics
 // are an order of magnitude faster than float ones on this LDS, and the tile's
 // sums become exact and independent of the order of the adds.
+template <class TL>
 __device__ __forceinline__ void lds_add12(unsigned long long *sJ, int base, const float v[12],
                                           double scale) {
 #pragma unroll
     for (int q = 0; q < 12; ++q)
-        atomicAdd(sJ + base + edge_off(q), (unsigned long long)to_fixed(v[q], scale));
+        atomicAdd(sJ + base + edge_off<TL>(q), (unsigned long long)to_fixed(v[q], scale));
 }
 
 typedef float __attribute__((address_space(1))) gfloat;
 typedef uint32_t __attribute__((address_space(1))) guint;
 
+template <class TL>
 __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
+    constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
+    constexpr int FWX = TL::FWX, FWY = TL::FWY, FW3 = TL::FW3;
+    constexpr int JWX = TL::JWX, JWY = TL::JWY, JWZ = TL::JWZ, JW3 = TL::JW3;
+    constexpr int ROWS = TL::ROWS;
     __shared__ float sF[6 * FW3];
     __shared__ unsigned long long sJ[3 * JW3];
-    __shared__ int sG[3][16];
-    __shared__ int sPad[3][16];
+    __shared__ int sG[3][ROWS];
+    __shared__ int sPad[3][ROWS];
 
     const GridP &g = A.g;
     const int nb8 = gridDim.x >> 3;
@@ -154,8 +160,8 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     const int tid = threadIdx.x;
 
     // global index tables of the window rows: x index, y*ext0, z*ext0*ext1
-    if (tid < 3 * 16) {
-        const int a = tid / 16, l = tid % 16;
+    if (tid < 3 * ROWS) {
+        const int a = tid / ROWS, l = tid % ROWS;
         const int wl = a == 0 ? JWX : (a == 1 ? JWY : JWZ);
         if (l < wl) {
             const int gi = gaxis(g, a, wo[a] + l);
@@ -195,7 +201,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
 
     uint32_t fbits = 0;
     unsigned nfb = 0;
-    constexpr int LHI_X = TX + 2 * MARGIN, LHI_Y = TY + 2 * MARGIN, LHI_Z = TZ + 2 * MARGIN;
+    constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
 
     for (int s = 0; s < A.nsp; ++s) {
         const DevSpecies &D = A.tbl[s];
@@ -265,12 +271,12 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
                 half_axis(oy, ly, hy, fy);
                 half_axis(oz, lz, hz, fz);
                 float Ep[3], Bp[3];
-                Ep[0] = tri_lds(sF + 0 * FW3, hx, ly, lz, fx, oy, oz);
-                Ep[1] = tri_lds(sF + 1 * FW3, lx, hy, lz, ox, fy, oz);
-                Ep[2] = tri_lds(sF + 2 * FW3, lx, ly, hz, ox, oy, fz);
-                Bp[0] = tri_lds(sF + 3 * FW3, lx, hy, hz, ox, fy, fz);
-                Bp[1] = tri_lds(sF + 4 * FW3, hx, ly, hz, fx, oy, fz);
-                Bp[2] = tri_lds(sF + 5 * FW3, hx, hy, lz, fx, fy, oz);
+                Ep[0] = tri_lds<TL>(sF + 0 * FW3, hx, ly, lz, fx, oy, oz);
+                Ep[1] = tri_lds<TL>(sF + 1 * FW3, lx, hy, lz, ox, fy, oz);
+                Ep[2] = tri_lds<TL>(sF + 2 * FW3, lx, ly, hz, ox, oy, fz);
+                Bp[0] = tri_lds<TL>(sF + 3 * FW3, lx, hy, hz, ox, fy, fz);
+                Bp[1] = tri_lds<TL>(sF + 4 * FW3, hx, ly, hz, fx, oy, fz);
+                Bp[2] = tri_lds<TL>(sF + 5 * FW3, hx, hy, lz, fx, fy, oz);
                 float ux = ux4[k], uy = uy4[k], uz = uz4[k], gam;
                 const float ig = boris_f32(ux, uy, uz, Ep, Bp, r, gam);
                 if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
@@ -291,14 +297,14 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
                     const float W[3] = {fmaf(0.5f, dx[0], o[0]), fmaf(0.5f, dx[1], o[1]),
                                         fmaf(0.5f, dx[2], o[2])};
                     segment_weights(W, dx, amp, v);
-                    lds_add12(sJ, jb, v, A.jscale);
+                    lds_add12<TL>(sJ, jb, v, A.jscale);
                 } else {
                     float WA[3], DA[3], WB[3], DB[3];
                     zigzag_split(o, dx, e, dc, WA, DA, WB, DB);
                     segment_weights(WA, DA, amp, v);
-                    lds_add12(sJ, jb, v, A.jscale);
+                    lds_add12<TL>(sJ, jb, v, A.jscale);
                     segment_weights(WB, DB, amp, v);
-                    lds_add12(sJ, jb + dc[0] + JWX * (dc[1] + JWY * dc[2]), v, A.jscale);
+                    lds_add12<TL>(sJ, jb + dc[0] + JWX * (dc[1] + JWY * dc[2]), v, A.jscale);
                 }
                 int ni, nj, nk;
                 const int ok = (int)new_cell(g, 0, ci, dc[0], ni) & (int)new_cell(g, 1, cj, dc[1], nj) &
@@ -764,6 +770,18 @@ void launch_write_species(DevSpecies *dst, const DevSpecies &v, hipStream_t s) {
     hipLaunchKernelGGL(k_write_species, dim3(1), dim3(1), 0, s, dst, v);
 }
 
+namespace {
+template <class TL>
+void launch_fused(const FusedArgs &A, int nb, hipStream_t s, hipEvent_t ev_start,
+                  hipEvent_t ev_stop) {
+    if (ev_start)  // timestamps taken by the dispatch itself
+        hipExtLaunchKernelGGL(k_push_fused<TL>, dim3(nb), dim3(PUSH_THREADS), 0, s, ev_start,
+                              ev_stop, 0, A);
+    else
+        hipLaunchKernelGGL(k_push_fused<TL>, dim3(nb), dim3(PUSH_THREADS), 0, s, A);
+}
+}  // namespace
+
 void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
                        float *const Bbar[3], float *const J[3], const DevSpecies *tbl, int nsp,
                        unsigned cur_mask, unsigned wr_mask, uint32_t *fault, unsigned long long *fallback,
@@ -794,11 +812,10 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
     const int nb = 8 * ((ti.ntiles + 7) / 8);
     if (fallback_pass)
         hipLaunchKernelGGL(k_push_fallback, dim3(64), dim3(256), 0, s, A);
-    else if (ev_start)  // timestamps taken by the dispatch itself
-        hipExtLaunchKernelGGL(k_push_fused, dim3(nb), dim3(PUSH_THREADS), 0, s, ev_start, ev_stop,
-                              0, A);
+    else if (ti.slab)
+        launch_fused<TileSlab>(A, nb, s, ev_start, ev_stop);
     else
-        hipLaunchKernelGGL(k_push_fused, dim3(nb), dim3(PUSH_THREADS), 0, s, A);
+        launch_fused<TileCube>(A, nb, s, ev_start, ev_stop);
 }
 
 void launch_dry_push_f32(const GridP &g, float *const E[3], float *const Bbar[3],

@@ -353,7 +353,7 @@ class LaserUnits:
 
 def lwfa_2d(per=(4, 2, 4), cells=(1400, 2, 300), n0_cm3=3.0e18, lambda0_um=0.8,
             fwhm_fs=28.0, w0_um=12.0, a0=3.0, window_lp=(3.0, 1.0, 3.0), travel_lp=6.0,
-            window_start=0.75, shift_cells=8, sort_every=10, steps=None):
+            window_start=0.75, shift_cells=8, sort_every=-1, steps=None):
     """The two-dimensional laser-wakefield run of Sec. 4 (its parameter table).
 
     Our x is the paper's propagation axis z, our z its transverse x, y is the
@@ -369,7 +369,8 @@ def lwfa_2d(per=(4, 2, 4), cells=(1400, 2, 300), n0_cm3=3.0e18, lambda0_um=0.8,
     at x node 1: E_inc = a0 exp(-(z - zc)^2/w0^2) exp(-2 ln2 (t-t0)^2/tau^2)
     sin(t - t0), tau = the intensity FWHM, t0 = 2.5 tau.  `steps` defaults to
     the pulse peak travelling `travel_lp` plasma wavelengths past the sheet.
-    Deterministic (no random draws).
+    Sorting is adaptive (every window shift sorts as well).  Deterministic
+    (no random draws).
     """
     U = LaserUnits(lambda0_um * 1e-6)
     n_pl = n0_cm3 / U.n_crit_cm3

@@ -89,13 +89,14 @@ def test_sort_vjp_moves_adjoints_back():
     assert np.array_equal(pre, expect)
 
 
-@pytest.mark.parametrize("drift_steps", [0, 25])
-def test_one_step_vjp_matches_oracle(drift_steps):
+@pytest.mark.parametrize("drift_steps,n", [(0, (16, 16, 8)), (25, (16, 16, 8)), (0, (40, 2, 16)),
+                                           (25, (40, 2, 16))])
+def test_one_step_vjp_matches_oracle(drift_steps, n):
     """One-step VJP against the oracle's; with drift_steps unsorted steps
     first, some particles are outside their tile window and take the
-    global-memory path."""
+    global-memory path.  The 40 x 2 x 16 grid gets the 16 x 2 x 8 tiles."""
     import torch
-    n, d = (16, 16, 8), (1.0, 0.9, 1.1)
+    d = (1.0, 0.9, 1.1)
     rng = np.random.default_rng(5)
     L = np.asarray(n) * np.asarray(d)
     sp = []

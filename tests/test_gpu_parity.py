@@ -243,8 +243,10 @@ def test_fp32_out_of_window_fallback():
     assert d["fault_word"] & 16
 
 
-def test_sort_is_a_permutation():
-    w = W.thermal_two_species(n=(16, 16, 16), ppc=4)
+@pytest.mark.parametrize("n", [(16, 16, 16), (40, 2, 20)])
+def test_sort_is_a_permutation(n):
+    """Also on a grid two cells thick along y, which gets the 16 x 2 x 8 tiles."""
+    w = W.thermal_two_species(n=n, ppc=4)
     g = _sim(w, "fp32")
     g.step(3)
     before = [g.particles_by_id(i) for i in range(2)]
@@ -255,7 +257,8 @@ def test_sort_is_a_permutation():
         assert np.array_equal(P0, P1) and np.array_equal(U0, U1)
     # storage order is by tile, then by cell inside the tile
     from paper_2609_16575_amd import _lib
-    T = np.array(_lib.tile_shape())
+    T = np.array(_lib.tile_shape(g.desc))
+    assert tuple(T) == ((16, 2, 8) if n[1] <= 3 else (8, 8, 4))
     nt = -(-np.array(w.n) // T)
     P, _, _ = g.particles(0)
     c = np.floor(P).astype(int)
