@@ -136,7 +136,7 @@ def _quiet_lattice(n, d, per_axis):
 
 
 def langmuir_thermal(n=(16, 16, 16), ppc=8, vth=0.01, amp=1e-3, mode=1, steps=200, seed=1001):
-    """Workload 1: periodic thermal plasma with a Langmuir perturbation.
+    """Periodic thermal plasma with a Langmuir perturbation.
 
     16^3 cells of size 1, 8 electrons per cell uniformly random in the cell,
     u ~ N(0, vth^2) per component plus u_x += amp sin(2 pi mode x / L_x),
@@ -154,7 +154,7 @@ def langmuir_thermal(n=(16, 16, 16), ppc=8, vth=0.01, amp=1e-3, mode=1, steps=20
 
 def thermal_two_species(n=(128, 128, 128), ppc=8, vth=0.05, steps=100, seed=1002,
                         sort_every=10):
-    """Workload 2: periodic thermal electron-proton plasma (the benchmark).
+    """Periodic thermal electron-proton plasma (the benchmark).
 
     128^3 cells of size 1, 8 electrons and 8 protons per cell; protons sit on
     the electron positions (exact initial neutrality, E^0 = 0 satisfies
@@ -175,7 +175,7 @@ def thermal_two_species(n=(128, 128, 128), ppc=8, vth=0.05, steps=100, seed=1002
 def lwfa_slab(n=(1024, 128, 128), d=(0.05, 0.2, 0.2), ppc=2, x_start=128, ramp=40,
               n_plasma=0.01, a0=2.0, w0=8.0, tau=10.0, steps=2000, seed=1003,
               sort_every=10):
-    """Workload 3: laser-wakefield-like box with absorbing faces (laser units).
+    """Laser-wakefield-like box with absorbing faces (laser units).
 
     c = omega0 = 1, densities in units of n_c.  Cold electron slab filling
     x >= x_start cells with a linear up-ramp over `ramp` cells to n_plasma,
@@ -212,7 +212,7 @@ def lwfa_slab(n=(1024, 128, 128), d=(0.05, 0.2, 0.2), ppc=2, x_start=128, ramp=4
 
 
 def cold_langmuir_lattice(n=(32, 32, 32), per_axis=(4, 2, 2), eps=1e-2, mode=1, steps=500):
-    """Workload 4: cold quiet-start plasma for the differentiable run.
+    """Cold quiet-start plasma for the differentiable run.
 
     32^3 cells, 16 particles per cell on a (4, 2, 2) lattice at offsets
     (m + 1/2)/n_m, u_x = eps sin(2 pi mode x / L_x), background rho_bg = +1.
@@ -230,7 +230,7 @@ def cold_langmuir_lattice(n=(32, 32, 32), per_axis=(4, 2, 2), eps=1e-2, mode=1, 
 
 def weibel_bimaxwellian(n=(256, 256, 256), ppc=16, vth_x=0.25, vth_perp=0.05, steps=50,
                         seed=1005, sort_every=10):
-    """Workload 5: anisotropic (T_x/T_perp = 25) electrons over immobile ions.
+    """Anisotropic (T_x/T_perp = 25) electrons over immobile ions.
 
     u_x ~ N(0, 0.25^2), u_y, u_z ~ N(0, 0.05^2); 16 electrons per cell
     uniformly random in the cell; background rho_bg = +1.

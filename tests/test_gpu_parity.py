@@ -53,7 +53,7 @@ def test_fp64_one_step_thermal_with_fields():
 
 
 def test_fp64_langmuir_workload_50_steps():
-    """Workload 1 as specified (16^3, 8 ppc, v_th = 0.01c, E = B = 0)."""
+    """The Langmuir thermal plasma as specified (16^3, 8 ppc, v_th = 0.01c, E = B = 0)."""
     w = W.langmuir_thermal()
     g, o = _sim(w, "fp64"), oracle_from(w)
     g.step(1)
@@ -100,7 +100,7 @@ def test_fp32_two_species_one_step():
 
 
 def test_fp32_multistep_tracks_oracle_and_conserves_charge():
-    """20 steps of workload 1 (sort every 10): stays near the FP64 run and the
+    """20 steps of the Langmuir thermal plasma (sort every 10): stays near the FP64 run and the
     continuity residual of every step is at FP32 round-off."""
     w = W.langmuir_thermal(steps=20)
     g, o = _sim(w, "fp32"), oracle_from(w)
@@ -315,7 +315,7 @@ def test_particles_leave_through_absorbing_faces():
 
 
 def test_full_size_thermal_ep_sampled():
-    """Workload 2 at its full size (128^3, 8 e + 8 p per cell, 33.5M particles),
+    """The thermal e+p benchmark plasma at its full size (128^3, 8 e + 8 p per cell, 33.5M particles),
     in the configuration the benchmark times (adaptive sorting): continuity
     per step from the GPU's FP64 diagnostics, and sampled particles pushed
     one by one by the oracle with the GPU's fields, for both arithmetic

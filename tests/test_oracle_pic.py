@@ -74,7 +74,7 @@ def test_cold_plasma_oscillation_frequency_energy_continuity():
 
 
 def test_thermal_langmuir_workload_invariants():
-    """Workload 1 (16^3, 8 ppc random, v_th = 0.01c, Langmuir perturbation):
+    """The Langmuir thermal plasma (16^3, 8 ppc random, v_th = 0.01c, perturbed):
     continuity and Gauss drift at round-off over 40 steps, bounded energy."""
     w = W.langmuir_thermal(steps=40)
     sim = O.OracleSim(w.n, w.d, w.dt)
