@@ -133,82 +133,21 @@ __device__ __forceinline__ void lds_add12(unsigned long long *sJ, int base, cons
 typedef float __attribute__((address_space(1))) gfloat;
 typedef uint32_t __attribute__((address_space(1))) guint;
 
-template <class TL>
-__global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
-    constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
-    constexpr int FWX = TL::FWX, FWY = TL::FWY, FW3 = TL::FW3;
-    constexpr int JWX = TL::JWX, JWY = TL::JWY, JWZ = TL::JWZ, JW3 = TL::JW3;
-    constexpr int ROWS = TL::ROWS;
-    __shared__ float sF[6 * FW3];
-    __shared__ unsigned long long sJ[3 * JW3];
-    __shared__ int sG[3][ROWS];
-    __shared__ int sPad[3][ROWS];
-
-    const GridP &g = A.g;
-    const int nb8 = gridDim.x >> 3;
-    const int tile = (blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);  // XCD-contiguous tiles
-    if (tile >= A.ti.ntiles) return;
-    int total = 0;
-    for (int s = 0; s < A.nsp; ++s)
-        total += A.tbl[s].p[0].tile_off[tile + 1] - A.tbl[s].p[0].tile_off[tile];
-    if (total == 0) return;
-
-    const int tx = tile % A.ti.nt[0];
-    const int tyz = tile / A.ti.nt[0];
-    const int ty = tyz % A.ti.nt[1], tz = tyz / A.ti.nt[1];
-    const int wo[3] = {tx * TX - MARGIN - 1, ty * TY - MARGIN - 1, tz * TZ - MARGIN - 1};
-    const int tid = threadIdx.x;
-
-    // global index tables of the window rows: x index, y*ext0, z*ext0*ext1
-    if (tid < 3 * ROWS) {
-        const int a = tid / ROWS, l = tid % ROWS;
-        const int wl = a == 0 ? JWX : (a == 1 ? JWY : JWZ);
-        if (l < wl) {
-            const int gi = gaxis(g, a, wo[a] + l);
-            const int mul = a == 0 ? 1 : (a == 1 ? g.ext[0] : g.ext[0] * g.ext[1]);
-            sG[a][l] = gi < 0 ? -1 : gi * mul;
-            sPad[a][l] = (gi >= 0 && g.bc[a] != EMPIC_BC_PERIODIC && gi >= g.n[a]) ? 1 : 0;
-        }
-    }
-    __syncthreads();
-    {
-        // every thread's window loads are issued before any is waited on
-        constexpr int NST = (6 * FW3 + PUSH_THREADS - 1) / PUSH_THREADS;
-        float tmp[NST];
-#pragma unroll
-        for (int q = 0; q < NST; ++q) {
-            const int e = tid + q * PUSH_THREADS;
-            tmp[q] = 0.f;
-            if (e < 6 * FW3) {
-                const int comp = e / FW3;
-                const int r = e - comp * FW3;
-                const int lz = r / (FWX * FWY);
-                const int r2 = r - lz * (FWX * FWY);
-                const int ly = r2 / FWX, lx = r2 - ly * FWX;
-                const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
-                const float *src = comp < 3 ? A.E[comp] : A.Bb[comp - 3];
-                if (gx >= 0 && gy >= 0 && gz >= 0) tmp[q] = src[gx + gy + gz];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < NST; ++q) {
-            const int e = tid + q * PUSH_THREADS;
-            if (e < 6 * FW3) sF[e] = tmp[q];
-        }
-    }
-    for (int e = tid; e < 3 * JW3; e += PUSH_THREADS) sJ[e] = 0ull;
-    __syncthreads();
-
-    uint32_t fbits = 0;
-    unsigned nfb = 0;
+// One species of one tile: P consecutive particles per thread (one access
+// of P elements per array), gather from the LDS field window, Boris (Sec.
+// 2.4), move, ZigZag deposit (Sec. 2.5) into the LDS current window; the
+// new state goes to the write set.
+template <class TL, int P>
+__device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecies &D,
+                                             const SpeciesP &S, const SpeciesP &Wr, int beg,
+                                             int end, const int wo[3], const float *sF,
+                                             unsigned long long *sJ, int s, uint32_t &fbits,
+                                             unsigned &nfb) {
+    typedef float VF __attribute__((ext_vector_type(P)));
+    typedef uint32_t VU __attribute__((ext_vector_type(P)));
+    constexpr int FW3 = TL::FW3, JWX = TL::JWX, JWY = TL::JWY;
     constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
-
-    for (int s = 0; s < A.nsp; ++s) {
-        const DevSpecies &D = A.tbl[s];
-        const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
-        const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
-        const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
-        if (beg >= end) continue;
+    const GridP &g = A.g;
         const float r = D.r;
         const float qcx = D.qc[0], qcy = D.qc[1], qcz = D.qc[2];
         const gfloat *WP = S.per_particle_w ? (const gfloat *)S.w : nullptr;
@@ -218,27 +157,29 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
         guint *CQ = (guint *)Wr.cell;
         gfloat *OXQ = (gfloat *)Wr.pos[0], *OYQ = (gfloat *)Wr.pos[1], *OZQ = (gfloat *)Wr.pos[2];
         gfloat *UXQ = (gfloat *)Wr.u[0], *UYQ = (gfloat *)Wr.u[1], *UZQ = (gfloat *)Wr.u[2];
-        const int base0 = beg & ~(PPT - 1);
-        for (int base = base0 + tid * PPT; base < end; base += PUSH_THREADS * PPT) {
-            // one 16-byte (non-temporal) access per array: PPT = 4 consecutive particles
-            const vu4 c4 = __builtin_nontemporal_load((const vu4 *)(CP + base));
-            const vf4 ox4 = __builtin_nontemporal_load((const vf4 *)(OXP + base));
-            const vf4 oy4 = __builtin_nontemporal_load((const vf4 *)(OYP + base));
-            const vf4 oz4 = __builtin_nontemporal_load((const vf4 *)(OZP + base));
-            const vf4 ux4 = __builtin_nontemporal_load((const vf4 *)(UXP + base));
-            const vf4 uy4 = __builtin_nontemporal_load((const vf4 *)(UYP + base));
-            const vf4 uz4 = __builtin_nontemporal_load((const vf4 *)(UZP + base));
-            vf4 w4 = (vf4){1.f, 1.f, 1.f, 1.f};
-            if (WP) w4 = __builtin_nontemporal_load((const vf4 *)(WP + base));
+        const int base0 = P == 1 ? beg : (beg & ~(P - 1));
+        for (int base = base0 + (int)threadIdx.x * P; base < end; base += PUSH_THREADS * P) {
+            // one (non-temporal) access of P consecutive particles per array
+            const VU c4 = __builtin_nontemporal_load((const VU *)(CP + base));
+            const VF ox4 = __builtin_nontemporal_load((const VF *)(OXP + base));
+            const VF oy4 = __builtin_nontemporal_load((const VF *)(OYP + base));
+            const VF oz4 = __builtin_nontemporal_load((const VF *)(OZP + base));
+            const VF ux4 = __builtin_nontemporal_load((const VF *)(UXP + base));
+            const VF uy4 = __builtin_nontemporal_load((const VF *)(UYP + base));
+            const VF uz4 = __builtin_nontemporal_load((const VF *)(UZP + base));
+            VF w4;
+#pragma unroll
+            for (int k = 0; k < P; ++k) w4[k] = 1.f;
+            if (WP) w4 = __builtin_nontemporal_load((const VF *)(WP + base));
 
             // per particle: staggered CIC gather from LDS (Sec. 2.5), Boris push
             // (Sec. 2.4), move, ZigZag deposit (Sec. 2.5) into the fixed-point LDS
             // window.  A particle outside the tile window keeps its state here and is
             // pushed by k_push_fallback.
-            float nux[PPT], nuy[PPT], nuz[PPT], nox[PPT], noy[PPT], noz[PPT];
-            uint32_t ncell[PPT];
+            float nux[P], nuy[P], nuz[P], nox[P], noy[P], noz[P];
+            uint32_t ncell[P];
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
+            for (int k = 0; k < P; ++k) {
                 const int p = base + k;
                 const uint32_t c = c4[k];
                 const bool valid = p >= beg && p < end && c != DEAD;
@@ -317,20 +258,31 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
                 nuy[k] = uy;
                 nuz[k] = uz;
             }
-            if (base >= beg && base + PPT <= end) {
-                __builtin_nontemporal_store((vu4){ncell[0], ncell[1], ncell[2], ncell[3]},
-                                            (vu4 *)(CQ + base));
-                __builtin_nontemporal_store((vf4){nox[0], nox[1], nox[2], nox[3]}, (vf4 *)(OXQ + base));
-                __builtin_nontemporal_store((vf4){noy[0], noy[1], noy[2], noy[3]}, (vf4 *)(OYQ + base));
-                __builtin_nontemporal_store((vf4){noz[0], noz[1], noz[2], noz[3]}, (vf4 *)(OZQ + base));
-                __builtin_nontemporal_store((vf4){nux[0], nux[1], nux[2], nux[3]}, (vf4 *)(UXQ + base));
-                __builtin_nontemporal_store((vf4){nuy[0], nuy[1], nuy[2], nuy[3]}, (vf4 *)(UYQ + base));
-                __builtin_nontemporal_store((vf4){nuz[0], nuz[1], nuz[2], nuz[3]}, (vf4 *)(UZQ + base));
+            if (base >= beg && base + P <= end) {
+                VU vc;
+                VF vox, voy, voz, vux, vuy, vuz;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    vc[k] = ncell[k];
+                    vox[k] = nox[k];
+                    voy[k] = noy[k];
+                    voz[k] = noz[k];
+                    vux[k] = nux[k];
+                    vuy[k] = nuy[k];
+                    vuz[k] = nuz[k];
+                }
+                __builtin_nontemporal_store(vc, (VU *)(CQ + base));
+                __builtin_nontemporal_store(vox, (VF *)(OXQ + base));
+                __builtin_nontemporal_store(voy, (VF *)(OYQ + base));
+                __builtin_nontemporal_store(voz, (VF *)(OZQ + base));
+                __builtin_nontemporal_store(vux, (VF *)(UXQ + base));
+                __builtin_nontemporal_store(vuy, (VF *)(UYQ + base));
+                __builtin_nontemporal_store(vuz, (VF *)(UZQ + base));
             } else {
                 // every slot of this tile, removed ones too (a step into another
                 // buffer set carries the whole record)
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) {
+                for (int k = 0; k < P; ++k) {
                     const int p = base + k;
                     if (p < beg || p >= end) continue;
                     CQ[p] = ncell[k];
@@ -343,6 +295,90 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
                 }
             }
         }
+}
+
+template <class TL>
+__global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
+    constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
+    constexpr int FWX = TL::FWX, FWY = TL::FWY, FW3 = TL::FW3;
+    constexpr int JWX = TL::JWX, JWY = TL::JWY, JWZ = TL::JWZ, JW3 = TL::JW3;
+    constexpr int ROWS = TL::ROWS;
+    __shared__ float sF[6 * FW3];
+    __shared__ unsigned long long sJ[3 * JW3];
+    __shared__ int sG[3][ROWS];
+    __shared__ int sPad[3][ROWS];
+
+    const GridP &g = A.g;
+    const int nb8 = gridDim.x >> 3;
+    const int tile = (blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);  // XCD-contiguous tiles
+    if (tile >= A.ti.ntiles) return;
+    int total = 0;
+    for (int s = 0; s < A.nsp; ++s)
+        total += A.tbl[s].p[0].tile_off[tile + 1] - A.tbl[s].p[0].tile_off[tile];
+    if (total == 0) return;
+
+    const int tx = tile % A.ti.nt[0];
+    const int tyz = tile / A.ti.nt[0];
+    const int ty = tyz % A.ti.nt[1], tz = tyz / A.ti.nt[1];
+    const int wo[3] = {tx * TX - MARGIN - 1, ty * TY - MARGIN - 1, tz * TZ - MARGIN - 1};
+    const int tid = threadIdx.x;
+
+    // global index tables of the window rows: x index, y*ext0, z*ext0*ext1
+    if (tid < 3 * ROWS) {
+        const int a = tid / ROWS, l = tid % ROWS;
+        const int wl = a == 0 ? JWX : (a == 1 ? JWY : JWZ);
+        if (l < wl) {
+            const int gi = gaxis(g, a, wo[a] + l);
+            const int mul = a == 0 ? 1 : (a == 1 ? g.ext[0] : g.ext[0] * g.ext[1]);
+            sG[a][l] = gi < 0 ? -1 : gi * mul;
+            sPad[a][l] = (gi >= 0 && g.bc[a] != EMPIC_BC_PERIODIC && gi >= g.n[a]) ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    {
+        // every thread's window loads are issued before any is waited on
+        constexpr int NST = (6 * FW3 + PUSH_THREADS - 1) / PUSH_THREADS;
+        float tmp[NST];
+#pragma unroll
+        for (int q = 0; q < NST; ++q) {
+            const int e = tid + q * PUSH_THREADS;
+            tmp[q] = 0.f;
+            if (e < 6 * FW3) {
+                const int comp = e / FW3;
+                const int r = e - comp * FW3;
+                const int lz = r / (FWX * FWY);
+                const int r2 = r - lz * (FWX * FWY);
+                const int ly = r2 / FWX, lx = r2 - ly * FWX;
+                const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
+                const float *src = comp < 3 ? A.E[comp] : A.Bb[comp - 3];
+                if (gx >= 0 && gy >= 0 && gz >= 0) tmp[q] = src[gx + gy + gz];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NST; ++q) {
+            const int e = tid + q * PUSH_THREADS;
+            if (e < 6 * FW3) sF[e] = tmp[q];
+        }
+    }
+    for (int e = tid; e < 3 * JW3; e += PUSH_THREADS) sJ[e] = 0ull;
+    __syncthreads();
+
+    uint32_t fbits = 0;
+    unsigned nfb = 0;
+    constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
+
+    for (int s = 0; s < A.nsp; ++s) {
+        const DevSpecies &D = A.tbl[s];
+        const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
+        const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
+        const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
+        if (beg >= end) continue;
+        // a sparse tile (few particles of this species) takes one particle per
+        // thread, so that all its waves work; a dense one four per thread
+        if (end - beg <= 2 * PUSH_THREADS)
+            push_species<TL, 1>(A, D, S, Wr, beg, end, wo, sF, sJ, s, fbits, nfb);
+        else
+            push_species<TL, PPT>(A, D, S, Wr, beg, end, wo, sF, sJ, s, fbits, nfb);
     }
     if (fbits) atomicOr(A.fault, fbits | (nfb ? EMPIC_FAULT_FALLBACK : 0u));
     else if (nfb) atomicOr(A.fault, (uint32_t)EMPIC_FAULT_FALLBACK);
