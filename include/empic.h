@@ -280,7 +280,11 @@ empic_status empic_set_filter(empic_sim *s, int32_t passes, int32_t compensate);
 /* Advance the state by nsteps PIC cycles (Sec. 2.2): Faraday with temporal
  * centring of B -> gather, Boris, move, ZigZag deposit for every species ->
  * current filter -> Ampere-Maxwell -> laser source -> Mur faces -> PEC walls
- * -> port.  FP32 path: counting sort every sort_every steps.  Asynchronous. */
+ * -> port.  FP32 path: a moving-window shift when one is due, then the
+ * counting sort when sort_every (or the adaptive policy) asks for it, before
+ * the cycle.  Asynchronous, except that the adaptive policy waits for the step
+ * two steps earlier.  EMPIC_E_CAPACITY: an injection would overflow the ids
+ * (the steps before it were taken). */
 empic_status empic_step(empic_sim *s, int32_t nsteps);
 
 /* Sort (FP32 path) by tile and cell now, dropping removed particles. */
