@@ -845,10 +845,17 @@ empic_status empic_deposit_rho(empic_sim *s, int32_t sp, double *rho_out) {
     for (int i = 0; i < s->nsp; ++i) {
         if (sp >= 0 && i != sp) continue;
         const SpeciesP p = species_params(s, i, s->sp[i].cur);
-        if (fp64(s))
+        if (fp64(s)) {
             launch_rho_f64(s->g, p, s->sp[i].host_count, rho_out, s->stream);
-        else
-            launch_rho_f32(s->g, p, rho_out, s->stream);
+        } else {
+            // fixed-point scale of the tile windows: one contribution |q| w / dV <= 2^48
+            const double dV = s->g.d[0] * s->g.d[1] * s->g.d[2];
+            const double B = std::fabs(s->sp[i].desc.q) * s->sp[i].wmax / dV;
+            const double e =
+                B > 0.0 && std::isfinite(B) ? std::floor(std::log2(std::ldexp(1.0, 48) / B)) : 0.0;
+            const double scale = std::ldexp(1.0, (int)std::fmax(-1000.0, std::fmin(1000.0, e)));
+            launch_rho_f32(s->g, s->ti, s->sp[i].tiles_valid, scale, p, rho_out, s->stream);
+        }
     }
     return check_launch(s, "deposit_rho");
 }

@@ -201,7 +201,11 @@ void launch_dry_push_f32(const GridP &g, float *const E[3], float *const Bbar[3]
                          const SpeciesP &sp, double *partial_slot, uint32_t *fault,
                          hipStream_t s);
 void launch_kinetic_f32(const SpeciesP &sp, double *partial_slot, hipStream_t s);
-void launch_rho_f32(const GridP &g, const SpeciesP &sp, double *rho, hipStream_t s);
+// CIC rho of an FP32 species added to rho (FP64 nodes); tile-grouped
+// particles (tiles_valid) are accumulated per tile in fixed point at `scale`
+// (a power of two with one particle's contribution below 2^48).
+void launch_rho_f32(const GridP &g, const TileInfo &ti, bool tiles_valid, double scale,
+                    const SpeciesP &sp, double *rho, hipStream_t s);
 void launch_load_f32(const GridP &g, const SpeciesP &sp, long long count, const double *pos,
                      const double *u, const double *w, const int32_t *ids, uint32_t *fault,
                      hipStream_t s);

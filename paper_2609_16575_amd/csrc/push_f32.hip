@@ -519,6 +519,84 @@ __global__ void k_rho_f32(GridP g, SpeciesP sp, double *rho) {
     }
 }
 
+// CIC rho of particles still grouped by the tiles of the last sort: one
+// workgroup per tile accumulates its particles in an LDS window of nodes as
+// int64 fixed point (scale: one contribution <= 2^48), then adds the window
+// to the global FP64 array, one atomic per touched node instead of eight per
+// particle.  Particles that drifted out of the window add their eight
+// contributions directly.
+template <class TL>
+__global__ __launch_bounds__(256) void k_rho_tiles(GridP g, TileInfo ti, SpeciesP sp,
+                                                   double scale, double *rho) {
+    constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
+    constexpr int FWX = TL::FWX, FWY = TL::FWY, FWZ = TL::FWZ, FW3 = TL::FW3, ROWS = TL::ROWS;
+    constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
+    __shared__ unsigned long long acc[FW3];
+    __shared__ int sG[3][ROWS];
+    const int nb8 = gridDim.x >> 3;
+    const int tile = (blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);  // XCD-contiguous tiles
+    if (tile >= ti.ntiles) return;
+    const int beg = sp.tile_off[tile], end = sp.tile_off[tile + 1];
+    if (beg >= end) return;
+    const int tx = tile % ti.nt[0];
+    const int tyz = tile / ti.nt[0];
+    const int ty = tyz % ti.nt[1], tz = tyz / ti.nt[1];
+    const int wo[3] = {tx * TX - MARGIN - 1, ty * TY - MARGIN - 1, tz * TZ - MARGIN - 1};
+    const int tid = threadIdx.x;
+    if (tid < 3 * ROWS) {
+        const int a = tid / ROWS, l = tid % ROWS;
+        const int wl = a == 0 ? FWX : (a == 1 ? FWY : FWZ);
+        if (l < wl) {
+            const int gi = gaxis(g, a, wo[a] + l);
+            const int mul = a == 0 ? 1 : (a == 1 ? g.ext[0] : g.ext[0] * g.ext[1]);
+            sG[a][l] = gi < 0 ? -1 : gi * mul;
+        }
+    }
+    for (int e = tid; e < FW3; e += 256) acc[e] = 0ull;
+    __syncthreads();
+    const float *WP = (sp.per_particle_w && sp.w) ? (const float *)sp.w : nullptr;
+    const double dV = g.d[0] * g.d[1] * g.d[2];
+    for (int p = beg + tid; p < end; p += 256) {
+        const uint32_t c = sp.cell[p];
+        if (c == DEAD) continue;
+        const double amp = sp.q * (WP ? (double)WP[p] : sp.w_species) / dV;
+        const int ci[3] = {cell_i(c), cell_j(c), cell_k(c)};
+        const double f[3] = {((const float *)sp.pos[0])[p], ((const float *)sp.pos[1])[p],
+                             ((const float *)sp.pos[2])[p]};
+        const int lx = local_axis(g, 0, ci[0], wo[0]), ly = local_axis(g, 1, ci[1], wo[1]),
+                  lz = local_axis(g, 2, ci[2], wo[2]);
+        const bool inwin =
+            lx >= 1 && lx <= LHI_X && ly >= 1 && ly <= LHI_Y && lz >= 1 && lz <= LHI_Z;
+        for (int o = 0; o < 8; ++o) {
+            const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+            const double wt = (ox ? f[0] : 1.0 - f[0]) * (oy ? f[1] : 1.0 - f[1]) *
+                              (oz ? f[2] : 1.0 - f[2]);
+            if (inwin) {
+                const long long v = __double2ll_rn(amp * wt * scale);
+                atomicAdd(acc + (lx + ox) + FWX * ((ly + oy) + FWY * (lz + oz)),
+                          (unsigned long long)v);
+            } else {
+                const int gx = gaxis(g, 0, ci[0] + ox), gy = gaxis(g, 1, ci[1] + oy),
+                          gz = gaxis(g, 2, ci[2] + oz);
+                if (gx < 0 || gy < 0 || gz < 0) continue;
+                atomicAdd(rho + gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz), amp * wt);
+            }
+        }
+    }
+    __syncthreads();
+    const double inv = 1.0 / scale;
+    for (int e = tid; e < FW3; e += 256) {
+        const long long v = (long long)acc[e];
+        if (v == 0) continue;
+        const int lz = e / (FWX * FWY);
+        const int r = e - lz * (FWX * FWY);
+        const int ly = r / FWX, lx = r - ly * FWX;
+        const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
+        if (gx < 0 || gy < 0 || gz < 0) continue;
+        atomicAdd(rho + gx + gy + gz, (double)v * inv);
+    }
+}
+
 // FP64 global positions -> packed cell + FP32 offset (on the device)
 __global__ void k_load_f32(GridP g, SpeciesP sp, long long count, const double *pos,
                            const double *u, const double *w, const int32_t *ids, uint32_t *fault) {
@@ -866,9 +944,16 @@ void launch_kinetic_f32(const SpeciesP &sp, double *partial_slot, hipStream_t s)
     hipLaunchKernelGGL(k_kinetic_f32, dim3(RED_BLOCKS), dim3(256), 0, s, sp, partial_slot);
 }
 
-void launch_rho_f32(const GridP &g, const SpeciesP &sp, double *rho, hipStream_t s) {
+void launch_rho_f32(const GridP &g, const TileInfo &ti, bool tiles_valid, double scale,
+                    const SpeciesP &sp, double *rho, hipStream_t s) {
     if (sp.capacity <= 0) return;
-    hipLaunchKernelGGL(k_rho_f32, dim3(nblk(sp.capacity, 256)), dim3(256), 0, s, g, sp, rho);
+    const unsigned nb = 8 * ((ti.ntiles + 7) / 8);
+    if (tiles_valid && ti.slab)
+        hipLaunchKernelGGL(k_rho_tiles<TileSlab>, dim3(nb), dim3(256), 0, s, g, ti, sp, scale, rho);
+    else if (tiles_valid)
+        hipLaunchKernelGGL(k_rho_tiles<TileCube>, dim3(nb), dim3(256), 0, s, g, ti, sp, scale, rho);
+    else
+        hipLaunchKernelGGL(k_rho_f32, dim3(nblk(sp.capacity, 256)), dim3(256), 0, s, g, sp, rho);
 }
 
 void launch_load_f32(const GridP &g, const SpeciesP &sp, long long count, const double *pos,
