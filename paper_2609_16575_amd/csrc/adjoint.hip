@@ -203,8 +203,9 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
 #pragma unroll
     for (int a = 0; a < 3; ++a) um[a] = fmaf(r, F6[a], u[a]);
     const float igm = rsqf(fmaf(um[0], um[0], fmaf(um[1], um[1], fmaf(um[2], um[2], 1.f))));
+    const float rig = r * igm;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) t[a] = r * F6[3 + a] * igm;
+    for (int a = 0; a < 3; ++a) t[a] = rig * F6[3 + a];
     const float den = fmaf(t[0], t[0], fmaf(t[1], t[1], fmaf(t[2], t[2], 1.f)));
     const float iden = rcpf(den);
     const float sf = 2.f * iden;

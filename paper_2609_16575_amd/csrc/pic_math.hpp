@@ -76,7 +76,8 @@ __device__ __forceinline__ float boris_f32(float &ux, float &uy, float &uz, cons
                                            const float B[3], float r, float &gam) {
     const float umx = fmaf(r, E[0], ux), umy = fmaf(r, E[1], uy), umz = fmaf(r, E[2], uz);
     const float ig = rsqf(fmaf(umx, umx, fmaf(umy, umy, fmaf(umz, umz, 1.f))));  // 1/gamma-
-    const float tx = r * B[0] * ig, ty = r * B[1] * ig, tz = r * B[2] * ig;
+    const float rig = r * ig;
+    const float tx = rig * B[0], ty = rig * B[1], tz = rig * B[2];
     const float sf = 2.f * rcpf(fmaf(tx, tx, fmaf(ty, ty, fmaf(tz, tz, 1.f))));
     const float sx = sf * tx, sy = sf * ty, sz = sf * tz;
     const float upx = umx + (umy * tz - umz * ty);
@@ -99,18 +100,24 @@ __device__ __forceinline__ float boris_f32(float &ux, float &uy, float &uz, cons
 // cell) and its displacement D (cell units):
 // out[0..3] J_x edges (oy,oz) = (0,0),(1,0),(0,1),(1,1); out[4..7] J_y edges
 // (oz,ox); out[8..11] J_z edges (ox,oy).
+// Component c is amp_c D_c [w_b1 w_b2 +- D_b1 D_b2 / 12] with (w(0), w(1)) =
+// (1 - W, W); it is evaluated as four FMAs on amp_c D_c (1 - W_b1), amp_c D_c
+// W_b1 and the cross term amp_c D_0 D_1 D_2 / 12, whose triple product all
+// three components share (30 operations per segment).
 __device__ __forceinline__ void segment_weights(const float W[3], const float D[3],
                                                 const float amp_c[3], float out[12]) {
+    const float p3 = D[0] * D[1] * (D[2] * (1.f / 12.f));
+    const float om[3] = {1.f - W[0], 1.f - W[1], 1.f - W[2]};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int b1 = (c + 1) % 3, b2 = (c + 2) % 3;
-        const float amp = amp_c[c] * D[c];
-        const float cr = D[b1] * D[b2] * (1.f / 12.f);
-        const float w1 = W[b1], w2 = W[b2];
-        out[4 * c + 0] = amp * ((1.f - w1) * (1.f - w2) + cr);
-        out[4 * c + 1] = amp * (w1 * (1.f - w2) - cr);
-        out[4 * c + 2] = amp * ((1.f - w1) * w2 - cr);
-        out[4 * c + 3] = amp * (w1 * w2 + cr);
+        const float a = amp_c[c] * D[c];
+        const float a0 = a * om[b1], a1 = a * W[b1];
+        const float cr = amp_c[c] * p3;
+        out[4 * c + 0] = fmaf(a0, om[b2], cr);
+        out[4 * c + 1] = fmaf(a1, om[b2], -cr);
+        out[4 * c + 2] = fmaf(a0, W[b2], -cr);
+        out[4 * c + 3] = fmaf(a1, W[b2], cr);
     }
 }
 

@@ -157,6 +157,16 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
         guint *CQ = (guint *)Wr.cell;
         gfloat *OXQ = (gfloat *)Wr.pos[0], *OYQ = (gfloat *)Wr.pos[1], *OZQ = (gfloat *)Wr.pos[2];
         gfloat *UXQ = (gfloat *)Wr.u[0], *UYQ = (gfloat *)Wr.u[1], *UZQ = (gfloat *)Wr.u[2];
+        // per-component window bases, opaque to the compiler so that it keeps
+        // one register base per component and puts the eight corner offsets of
+        // a gather into the ds_read2 offset fields
+        const float *sFc[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            uint32_t o = c * FW3;
+            asm volatile("" : "+s"(o));
+            sFc[c] = sF + o;
+        }
         const int base0 = P == 1 ? beg : (beg & ~(P - 1));
         for (int base = base0 + (int)threadIdx.x * P; base < end; base += PUSH_THREADS * P) {
             // one (non-temporal) access of P consecutive particles per array
@@ -212,12 +222,12 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
                 half_axis(oy, ly, hy, fy);
                 half_axis(oz, lz, hz, fz);
                 float Ep[3], Bp[3];
-                Ep[0] = tri_lds<TL>(sF + 0 * FW3, hx, ly, lz, fx, oy, oz);
-                Ep[1] = tri_lds<TL>(sF + 1 * FW3, lx, hy, lz, ox, fy, oz);
-                Ep[2] = tri_lds<TL>(sF + 2 * FW3, lx, ly, hz, ox, oy, fz);
-                Bp[0] = tri_lds<TL>(sF + 3 * FW3, lx, hy, hz, ox, fy, fz);
-                Bp[1] = tri_lds<TL>(sF + 4 * FW3, hx, ly, hz, fx, oy, fz);
-                Bp[2] = tri_lds<TL>(sF + 5 * FW3, hx, hy, lz, fx, fy, oz);
+                Ep[0] = tri_lds<TL>(sFc[0], hx, ly, lz, fx, oy, oz);
+                Ep[1] = tri_lds<TL>(sFc[1], lx, hy, lz, ox, fy, oz);
+                Ep[2] = tri_lds<TL>(sFc[2], lx, ly, hz, ox, oy, fz);
+                Bp[0] = tri_lds<TL>(sFc[3], lx, hy, hz, ox, fy, fz);
+                Bp[1] = tri_lds<TL>(sFc[4], hx, ly, hz, fx, oy, fz);
+                Bp[2] = tri_lds<TL>(sFc[5], hx, hy, lz, fx, fy, oz);
                 float ux = ux4[k], uy = uy4[k], uz = uz4[k], gam;
                 const float ig = boris_f32(ux, uy, uz, Ep, Bp, r, gam);
                 if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
