@@ -346,29 +346,37 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     }
     __syncthreads();
     {
-        // every thread's window loads are issued before any is waited on
-        constexpr int NST = (6 * FW3 + PUSH_THREADS - 1) / PUSH_THREADS;
-        float tmp[NST];
+        // a thread owns the same window points of all six components: their
+        // global offset is worked out once, and every load is issued before
+        // any is waited on
+        constexpr int NR = (FW3 + PUSH_THREADS - 1) / PUSH_THREADS;
+        int off[NR];
 #pragma unroll
-        for (int q = 0; q < NST; ++q) {
-            const int e = tid + q * PUSH_THREADS;
-            tmp[q] = 0.f;
-            if (e < 6 * FW3) {
-                const int comp = e / FW3;
-                const int r = e - comp * FW3;
+        for (int q = 0; q < NR; ++q) {
+            const int r = tid + q * PUSH_THREADS;
+            off[q] = -1;
+            if (r < FW3) {
                 const int lz = r / (FWX * FWY);
                 const int r2 = r - lz * (FWX * FWY);
                 const int ly = r2 / FWX, lx = r2 - ly * FWX;
                 const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
-                const float *src = comp < 3 ? A.E[comp] : A.Bb[comp - 3];
-                if (gx >= 0 && gy >= 0 && gz >= 0) tmp[q] = src[gx + gy + gz];
+                if (gx >= 0 && gy >= 0 && gz >= 0) off[q] = gx + gy + gz;
             }
         }
+        float tmp[6][NR];
 #pragma unroll
-        for (int q = 0; q < NST; ++q) {
-            const int e = tid + q * PUSH_THREADS;
-            if (e < 6 * FW3) sF[e] = tmp[q];
+        for (int c = 0; c < 6; ++c) {
+            const float *src = c < 3 ? A.E[c] : A.Bb[c - 3];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) tmp[c][q] = off[q] >= 0 ? src[off[q]] : 0.f;
         }
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const int r = tid + q * PUSH_THREADS;
+                if (r < FW3) sF[c * FW3 + r] = tmp[c][q];
+            }
     }
     for (int e = tid; e < 3 * JW3; e += PUSH_THREADS) sJ[e] = 0ull;
     __syncthreads();
@@ -394,21 +402,21 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     else if (nfb) atomicOr(A.fault, (uint32_t)EMPIC_FAULT_FALLBACK);
     if (nfb) atomicAdd(A.fallback, (unsigned long long)nfb);
     __syncthreads();
-    // add the tile's current to global J (non-zero entries only)
-    for (int e = tid; e < 3 * JW3; e += PUSH_THREADS) {
-        const long long fx = (long long)sJ[e];
-        if (fx == 0) continue;
-        const float v = (float)((double)fx * A.jinv);
-        const int comp = e / JW3;
-        const int r = e - comp * JW3;
+    // add the tile's current to global J (non-zero entries only); a thread
+    // owns the same window points of the three components
+    for (int r = tid; r < JW3; r += PUSH_THREADS) {
         const int lz = r / (JWX * JWY);
         const int r2 = r - lz * (JWX * JWY);
         const int ly = r2 / JWX, lx = r2 - ly * JWX;
         const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
         if (gx < 0 || gy < 0 || gz < 0) continue;
-        const int lc = comp == 0 ? lx : (comp == 1 ? ly : lz);
-        if (sPad[comp][lc]) continue;
-        atomicAdd(A.J[comp] + gx + gy + gz, v);
+        const int lc[3] = {lx, ly, lz};
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) {
+            const long long fx = (long long)sJ[comp * JW3 + r];
+            if (fx == 0 || sPad[comp][lc[comp]]) continue;
+            atomicAdd(A.J[comp] + gx + gy + gz, (float)((double)fx * A.jinv));
+        }
     }
 }
 
