@@ -133,16 +133,49 @@ __device__ __forceinline__ void lds_add12(unsigned long long *sJ, int base, cons
 typedef float __attribute__((address_space(1))) gfloat;
 typedef uint32_t __attribute__((address_space(1))) guint;
 
+// P consecutive particles of one thread as loaded (one access of P elements
+// per array; weight 1 without per-particle weights)
+template <int P>
+struct Batch {
+    typedef float VF __attribute__((ext_vector_type(P)));
+    typedef uint32_t VU __attribute__((ext_vector_type(P)));
+    VU c;
+    VF ox, oy, oz, ux, uy, uz, w;
+};
+
+template <int P>
+__device__ __forceinline__ int batch_base0(int beg) {
+    return P == 1 ? beg : (beg & ~(P - 1));
+}
+
+template <int P>
+__device__ __forceinline__ void load_batch(const SpeciesP &S, int base, Batch<P> &b) {
+    typedef typename Batch<P>::VF VF;
+    typedef typename Batch<P>::VU VU;
+    b.c = __builtin_nontemporal_load((const VU *)((const guint *)S.cell + base));
+    b.ox = __builtin_nontemporal_load((const VF *)((const gfloat *)S.pos[0] + base));
+    b.oy = __builtin_nontemporal_load((const VF *)((const gfloat *)S.pos[1] + base));
+    b.oz = __builtin_nontemporal_load((const VF *)((const gfloat *)S.pos[2] + base));
+    b.ux = __builtin_nontemporal_load((const VF *)((const gfloat *)S.u[0] + base));
+    b.uy = __builtin_nontemporal_load((const VF *)((const gfloat *)S.u[1] + base));
+    b.uz = __builtin_nontemporal_load((const VF *)((const gfloat *)S.u[2] + base));
+#pragma unroll
+    for (int k = 0; k < P; ++k) b.w[k] = 1.f;
+    if (S.per_particle_w) b.w = __builtin_nontemporal_load((const VF *)((const gfloat *)S.w + base));
+}
+
 // One species of one tile: P consecutive particles per thread (one access
 // of P elements per array), gather from the LDS field window, Boris (Sec.
 // 2.4), move, ZigZag deposit (Sec. 2.5) into the LDS current window; the
-// new state goes to the write set.
+// new state goes to the write set.  With use_pre, `pre` holds this thread's
+// first batch (the caller issued its loads early).
 template <class TL, int P>
 __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecies &D,
                                              const SpeciesP &S, const SpeciesP &Wr, int beg,
                                              int end, const int wo[3], const float *sF,
                                              unsigned long long *sJ, int s, uint32_t &fbits,
-                                             unsigned &nfb) {
+                                             unsigned &nfb, const Batch<P> &pre,
+                                             bool use_pre) {
     typedef float VF __attribute__((ext_vector_type(P)));
     typedef uint32_t VU __attribute__((ext_vector_type(P)));
     constexpr int FW3 = TL::FW3, JWX = TL::JWX, JWY = TL::JWY;
@@ -150,10 +183,6 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
     const GridP &g = A.g;
         const float r = D.r;
         const float qcx = D.qc[0], qcy = D.qc[1], qcz = D.qc[2];
-        const gfloat *WP = S.per_particle_w ? (const gfloat *)S.w : nullptr;
-        guint *CP = (guint *)S.cell;
-        gfloat *OXP = (gfloat *)S.pos[0], *OYP = (gfloat *)S.pos[1], *OZP = (gfloat *)S.pos[2];
-        gfloat *UXP = (gfloat *)S.u[0], *UYP = (gfloat *)S.u[1], *UZP = (gfloat *)S.u[2];
         guint *CQ = (guint *)Wr.cell;
         gfloat *OXQ = (gfloat *)Wr.pos[0], *OYQ = (gfloat *)Wr.pos[1], *OZQ = (gfloat *)Wr.pos[2];
         gfloat *UXQ = (gfloat *)Wr.u[0], *UYQ = (gfloat *)Wr.u[1], *UZQ = (gfloat *)Wr.u[2];
@@ -167,20 +196,19 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
             asm volatile("" : "+s"(o));
             sFc[c] = sF + o;
         }
-        const int base0 = P == 1 ? beg : (beg & ~(P - 1));
-        for (int base = base0 + (int)threadIdx.x * P; base < end; base += PUSH_THREADS * P) {
-            // one (non-temporal) access of P consecutive particles per array
-            const VU c4 = __builtin_nontemporal_load((const VU *)(CP + base));
-            const VF ox4 = __builtin_nontemporal_load((const VF *)(OXP + base));
-            const VF oy4 = __builtin_nontemporal_load((const VF *)(OYP + base));
-            const VF oz4 = __builtin_nontemporal_load((const VF *)(OZP + base));
-            const VF ux4 = __builtin_nontemporal_load((const VF *)(UXP + base));
-            const VF uy4 = __builtin_nontemporal_load((const VF *)(UYP + base));
-            const VF uz4 = __builtin_nontemporal_load((const VF *)(UZP + base));
-            VF w4;
-#pragma unroll
-            for (int k = 0; k < P; ++k) w4[k] = 1.f;
-            if (WP) w4 = __builtin_nontemporal_load((const VF *)(WP + base));
+        const int base0 = batch_base0<P>(beg) + (int)threadIdx.x * P;
+        // one (non-temporal) access of P consecutive particles per array; with
+        // one particle per thread the batch of the next pass is loaded at the
+        // end of this one (the first may come from the caller)
+        Batch<P> b;
+        if constexpr (P == 1) {
+            if (use_pre) b = pre;
+            else if (base0 < end) load_batch<P>(S, base0, b);
+        }
+        for (int base = base0; base < end; base += PUSH_THREADS * P) {
+            if constexpr (P != 1) load_batch<P>(S, base, b);
+            const VU c4 = b.c;
+            const VF ox4 = b.ox, oy4 = b.oy, oz4 = b.oz, ux4 = b.ux, uy4 = b.uy, uz4 = b.uz, w4 = b.w;
 
             // per particle: staggered CIC gather from LDS (Sec. 2.5), Boris push
             // (Sec. 2.4), move, ZigZag deposit (Sec. 2.5) into the fixed-point LDS
@@ -304,6 +332,8 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
                     UZQ[p] = nuz[k];
                 }
             }
+            if constexpr (P == 1)
+                if (base + PUSH_THREADS * P < end) load_batch<P>(S, base + PUSH_THREADS * P, b);
         }
 }
 
@@ -326,6 +356,14 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     for (int s = 0; s < A.nsp; ++s)
         total += A.tbl[s].p[0].tile_off[tile + 1] - A.tbl[s].p[0].tile_off[tile];
     if (total == 0) return;
+
+    // a sparse tile of species 0 (one particle per thread) loads its particles
+    // together with the field window: one memory latency for both
+    const SpeciesP &S0 = A.tbl[0].p[A.cur_mask & 1u];
+    const int beg0 = S0.tile_off[tile], end0 = S0.tile_off[tile + 1];
+    const bool sparse0 = end0 > beg0 && end0 - beg0 <= 2 * PUSH_THREADS;
+    Batch<1> pre1;
+    if (sparse0 && beg0 + (int)threadIdx.x < end0) load_batch<1>(S0, beg0 + (int)threadIdx.x, pre1);
 
     const int tx = tile % A.ti.nt[0];
     const int tyz = tile / A.ti.nt[0];
@@ -385,18 +423,22 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     unsigned nfb = 0;
     constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
 
-    for (int s = 0; s < A.nsp; ++s) {
+    // a sparse tile (few particles of a species) takes one particle per
+    // thread, so that all its waves work; a dense one four per thread
+    if (sparse0)
+        push_species<TL, 1>(A, A.tbl[0], S0, A.tbl[0].p[A.wr_mask & 1u], beg0, end0, wo, sF, sJ,
+                            0, fbits, nfb, pre1, true);
+    for (int s = sparse0 ? 1 : 0; s < A.nsp; ++s) {
         const DevSpecies &D = A.tbl[s];
         const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
         const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
         const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
         if (beg >= end) continue;
-        // a sparse tile (few particles of this species) takes one particle per
-        // thread, so that all its waves work; a dense one four per thread
         if (end - beg <= 2 * PUSH_THREADS)
-            push_species<TL, 1>(A, D, S, Wr, beg, end, wo, sF, sJ, s, fbits, nfb);
+            push_species<TL, 1>(A, D, S, Wr, beg, end, wo, sF, sJ, s, fbits, nfb, pre1, false);
         else
-            push_species<TL, PPT>(A, D, S, Wr, beg, end, wo, sF, sJ, s, fbits, nfb);
+            push_species<TL, PPT>(A, D, S, Wr, beg, end, wo, sF, sJ, s, fbits, nfb, Batch<PPT>(),
+                                  false);
     }
     if (fbits) atomicOr(A.fault, fbits | (nfb ? EMPIC_FAULT_FALLBACK : 0u));
     else if (nfb) atomicOr(A.fault, (uint32_t)EMPIC_FAULT_FALLBACK);
