@@ -399,22 +399,54 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
     window_rows<TL>(g, wo, sG);
     if (tid == 0) sE = NO_EXP;
     __syncthreads();
-    for (int e = tid; e < 6 * FW3; e += ADJ_THREADS) {
-        const int comp = e / FW3;
-        const int r = e - comp * FW3;
-        const int lz = r / (FWX * FWY);
-        const int r2 = r - lz * (FWX * FWY);
-        const int ly = r2 / FWX, lx = r2 - ly * FWX;
-        const float *src = comp < 3 ? A.E[comp] : A.Bb[comp - 3];
-        sF[e] = src[sG[0][lx] + sG[1][ly] + sG[2][lz]];
+    // a thread owns the same window points of every component: the global
+    // offset of a point is worked out once, and all loads of a window are
+    // issued before any is waited on
+    {
+        constexpr int NR = (FW3 + ADJ_THREADS - 1) / ADJ_THREADS;
+        int off[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const int r = min(tid + q * ADJ_THREADS, FW3 - 1);
+            const int lz = r / (FWX * FWY);
+            const int r2 = r - lz * (FWX * FWY);
+            const int ly = r2 / FWX, lx = r2 - ly * FWX;
+            off[q] = sG[0][lx] + sG[1][ly] + sG[2][lz];
+        }
+        float tmp[6][NR];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const float *src = c < 3 ? A.E[c] : A.Bb[c - 3];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) tmp[c][q] = src[off[q]];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (tid + q * ADJ_THREADS < FW3) sF[c * FW3 + tid + q * ADJ_THREADS] = tmp[c][q];
     }
-    for (int e = tid; e < 3 * JW3; e += ADJ_THREADS) {
-        const int comp = e / JW3;
-        const int r = e - comp * JW3;
-        const int lz = r / (JWX * JWY);
-        const int r2 = r - lz * (JWX * JWY);
-        const int ly = r2 / JWX, lx = r2 - ly * JWX;
-        sL[e] = A.lJ[comp][sG[0][lx] + sG[1][ly] + sG[2][lz]];
+    {
+        constexpr int NR = (JW3 + ADJ_THREADS - 1) / ADJ_THREADS;
+        int off[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const int r = min(tid + q * ADJ_THREADS, JW3 - 1);
+            const int lz = r / (JWX * JWY);
+            const int r2 = r - lz * (JWX * JWY);
+            const int ly = r2 / JWX, lx = r2 - ly * JWX;
+            off[q] = sG[0][lx] + sG[1][ly] + sG[2][lz];
+        }
+        float tmp[3][NR];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) tmp[c][q] = A.lJ[c][off[q]];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (tid + q * ADJ_THREADS < JW3) sL[c * JW3 + tid + q * ADJ_THREADS] = tmp[c][q];
     }
     __syncthreads();
 
@@ -580,16 +612,18 @@ __global__ __launch_bounds__(SCAT_THREADS) void k_adj_scatter(AdjArgs A, AdjSpec
     __syncthreads();
     // add the window to the global gather adjoints (non-zero entries only)
     const double inv = ldexp(1.0, ee - EB);
-    for (int e = tid; e < 6 * FW3; e += SCAT_THREADS) {
-        const long long fx = (long long)sA[e];
-        if (fx == 0) continue;
-        const int comp = e / FW3;
-        const int r = e - comp * FW3;
+    for (int r = tid; r < FW3; r += SCAT_THREADS) {
         const int lz = r / (FWX * FWY);
         const int r2 = r - lz * (FWX * FWY);
         const int ly = r2 / FWX, lx = r2 - ly * FWX;
-        float *dst = comp < 3 ? A.lEg[comp] : A.lBb[comp - 3];
-        atomicAdd(dst + sG[0][lx] + sG[1][ly] + sG[2][lz], (float)((double)fx * inv));
+        const int o = sG[0][lx] + sG[1][ly] + sG[2][lz];
+#pragma unroll
+        for (int comp = 0; comp < 6; ++comp) {
+            const long long fx = (long long)sA[comp * FW3 + r];
+            if (fx == 0) continue;
+            float *dst = comp < 3 ? A.lEg[comp] : A.lBb[comp - 3];
+            atomicAdd(dst + o, (float)((double)fx * inv));
+        }
     }
 }
 
