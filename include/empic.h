@@ -304,9 +304,12 @@ empic_status empic_particle_count(empic_sim *s, int32_t sp, int64_t *n);
 empic_status empic_sync(empic_sim *s);
 
 /* Kernel timing with HIP events on the handle's stream: enable = 1 starts
- * recording every launch of the particle kernel ("push") and of the field
- * kernels ("field"); empic_kernel_times returns the summed milliseconds and
- * the launch counts since enabling, and synchronises. */
+ * recording every launch of the particle kernel ("push"), of the field
+ * kernels ("field") and of the sort ("sort"); enable = 2 records the
+ * particle kernel only, through events attached to its own dispatch (no
+ * extra marker between kernels); 0 stops.  Other values: EMPIC_E_ARG.
+ * empic_kernel_times returns the summed milliseconds and the launch counts
+ * since enabling, and synchronises. */
 empic_status empic_enable_timing(empic_sim *s, int32_t enable);
 empic_status empic_kernel_times(empic_sim *s, double *push_ms, int64_t *push_launches,
                                 double *field_ms, int64_t *field_launches,

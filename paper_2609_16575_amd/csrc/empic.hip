@@ -178,7 +178,7 @@ struct empic_sim {
     double jscale = 1099511627776.0;  // fixed-point scale of the fused kernel's current window
     bool poisoned = false;
     std::string err;
-    bool timing = false;
+    int timing = 0;  // 0 off, 1 every timed kernel group, 2 the particle kernel only
     std::vector<TimedEvent> events;
     double t_ms[3] = {0, 0, 0};
     long long t_n[3] = {0, 0, 0};
@@ -238,13 +238,13 @@ SpeciesP species_params(const empic_sim *s, int i, int which) {
 void ev_begin(empic_sim *s, TimedEvent &t, int kind) {
     t.kind = kind;
     t.a = t.b = nullptr;
-    if (!s->timing) return;
+    if (!(s->timing == 1 || (s->timing == 2 && kind == 0))) return;  // mode 2: particle kernels only
     (void)hipEventCreate(&t.a);
     (void)hipEventCreate(&t.b);
     (void)hipEventRecord(t.a, s->stream);
 }
 void ev_end(empic_sim *s, TimedEvent &t) {
-    if (!s->timing || !t.a) return;
+    if (!t.a) return;
     (void)hipEventRecord(t.b, s->stream);
     s->events.push_back(t);
 }
@@ -959,7 +959,8 @@ empic_status empic_sync(empic_sim *s) {
 
 empic_status empic_enable_timing(empic_sim *s, int32_t enable) {
     EMPIC_GUARD(s);
-    s->timing = enable != 0;
+    if (enable < 0 || enable > 2) return fail(s, EMPIC_E_ARG, "timing mode is 0, 1 or 2");
+    s->timing = enable;
     return EMPIC_OK;
 }
 

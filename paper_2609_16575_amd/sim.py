@@ -359,8 +359,11 @@ class Sim:
         LB.check(self.h, self.L.empic_current_buffer(self.h, sp, C.byref(w)))
         return self.bufs[sp][w.value]
 
-    def enable_timing(self, on=True):
-        LB.check(self.h, self.L.empic_enable_timing(self.h, 1 if on else 0))
+    def enable_timing(self, on=True, push_only=False):
+        """HIP-event timing of the kernels (push_only: the particle kernel
+        alone, with no event markers between the other kernels)."""
+        mode = (2 if push_only else 1) if on else 0
+        LB.check(self.h, self.L.empic_enable_timing(self.h, mode))
 
     def kernel_times(self):
         v = [C.c_double(), C.c_int64(), C.c_double(), C.c_int64(), C.c_double(), C.c_int64()]
