@@ -856,6 +856,104 @@ __global__ void k_sort_scatter(TileInfo ti, SpeciesP cur, SpeciesP alt, const in
     if (perm) perm[dst] = (int32_t)p;
 }
 
+// Scatter pass after k_sort_count_tiles: one workgroup per old tile.  The
+// particles that stay in their tile (most of them between sorts) reach
+// their new slots through LDS, so that both the reads of the old range and
+// the writes of the new range are coalesced: each thread loads every array
+// of its old slots at once, then one array at a time goes to LDS in the old
+// order and out in the new order.  Particles that moved to another tile are
+// written straight to their slots (the slots of the new range that they
+// fill are skipped by their new tile's workgroup), and so is every particle
+// of a tile whose old or new range exceeds the LDS staging.
+constexpr int SCAT_NS = 9;                    // old slots per thread
+constexpr int SCAT_CAP = SORT_T * SCAT_NS;    // 4608 slots of LDS staging
+__global__ __launch_bounds__(SORT_T) void k_sort_scatter_tiles(TileInfo ti, SpeciesP cur,
+                                                               SpeciesP alt, const int32_t *offs,
+                                                               const int32_t *rank,
+                                                               int32_t *perm) {
+    __shared__ uint32_t buf[SCAT_CAP];
+    __shared__ int src_of[SCAT_CAP];  // new slot -> old slot of a stayer, -1: filled elsewhere
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const int beg = cur.tile_off[t], end = cur.tile_off[t + 1];
+    const int n_old = end - beg;
+    if (n_old <= 0) return;
+    const long long t0 = (long long)t * TC;
+    const int nb = offs[t0], n_new = offs[t0 + TC] - nb;
+    const bool has_w = cur.w && alt.w;
+    const uint32_t *S[9] = {cur.cell, (const uint32_t *)cur.pos[0], (const uint32_t *)cur.pos[1],
+                            (const uint32_t *)cur.pos[2], (const uint32_t *)cur.u[0],
+                            (const uint32_t *)cur.u[1], (const uint32_t *)cur.u[2],
+                            (const uint32_t *)cur.id, (const uint32_t *)cur.w};
+    uint32_t *D[9] = {alt.cell, (uint32_t *)alt.pos[0], (uint32_t *)alt.pos[1],
+                      (uint32_t *)alt.pos[2], (uint32_t *)alt.u[0], (uint32_t *)alt.u[1],
+                      (uint32_t *)alt.u[2], (uint32_t *)alt.id, (uint32_t *)alt.w};
+    if (n_old > SCAT_CAP || n_new > SCAT_CAP) {
+        for (int p = beg + tid; p < end; p += SORT_T) {
+            const int rk = rank[p];
+            if (rk < 0) continue;
+            const uint32_t c = cur.cell[p];
+            const long long d = offs[sort_key(ti, cell_i(c), cell_j(c), cell_k(c))] + rk;
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+                if (a < 8 || has_w) D[a][d] = S[a][p];
+            if (perm) perm[d] = p;
+        }
+        return;
+    }
+    for (int j = tid; j < n_new; j += SORT_T) src_of[j] = -1;
+    uint32_t v[9][SCAT_NS];
+    int rk[SCAT_NS];
+#pragma unroll
+    for (int k = 0; k < SCAT_NS; ++k) {
+        const int i = tid + k * SORT_T;
+        rk[k] = -1;
+        if (i < n_old) {
+            rk[k] = rank[beg + i];
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+                if (a < 8 || has_w) v[a][k] = S[a][beg + i];
+        }
+    }
+    __syncthreads();  // src_of cleared
+#pragma unroll
+    for (int k = 0; k < SCAT_NS; ++k) {
+        const int i = tid + k * SORT_T;
+        if (i >= n_old || rk[k] < 0) continue;
+        const uint32_t c = v[0][k];
+        const long long d = offs[sort_key(ti, cell_i(c), cell_j(c), cell_k(c))] + rk[k];
+        if (d >= nb && d < (long long)nb + n_new) {
+            src_of[d - nb] = i;
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a)
+                if (a < 8 || has_w) D[a][d] = v[a][k];
+            if (perm) perm[d] = beg + i;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        if (a < 8 || has_w) {  // uniform across the workgroup
+#pragma unroll
+            for (int k = 0; k < SCAT_NS; ++k) {
+                const int i = tid + k * SORT_T;
+                if (i < n_old) buf[i] = v[a][k];
+            }
+            __syncthreads();
+            for (int j = tid; j < n_new; j += SORT_T) {
+                const int o = src_of[j];
+                if (o >= 0) D[a][nb + j] = buf[o];
+            }
+            __syncthreads();
+        }
+    }
+    if (perm)
+        for (int j = tid; j < n_new; j += SORT_T) {
+            const int o = src_of[j];
+            if (o >= 0) perm[nb + j] = beg + o;
+        }
+}
+
 __global__ void k_tile_offsets(const int32_t *offs, long long NK, int ntiles, int32_t *tile_off,
                                int32_t *count) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1048,9 +1146,14 @@ void launch_sort(const GridP &g, const TileInfo &ti, const SpeciesP &cur, const 
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_T), 0, s, counts, NK, scan_blocks);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_T), 0, s, scan_blocks, nb, counts, NK);
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(SCAN_T), 0, s, counts, NK, scan_blocks);
-    if (cur.capacity > 0)
-        hipLaunchKernelGGL(k_sort_scatter, dim3(nblk(cur.capacity, 256)), dim3(256), 0, s, ti,
-                           cur, alt, counts, rank, perm);
+    if (cur.capacity > 0) {
+        if (tiles_valid)
+            hipLaunchKernelGGL(k_sort_scatter_tiles, dim3(ti.ntiles), dim3(SORT_T), 0, s, ti, cur,
+                               alt, counts, rank, perm);
+        else
+            hipLaunchKernelGGL(k_sort_scatter, dim3(nblk(cur.capacity, 256)), dim3(256), 0, s,
+                               ti, cur, alt, counts, rank, perm);
+    }
     hipLaunchKernelGGL(k_tile_offsets, dim3(nblk(ti.ntiles + 1, 256)), dim3(256), 0, s, counts,
                        NK, ti.ntiles, tile_off, cur.count);
 }
