@@ -732,6 +732,8 @@ __global__ void k_sort_count(TileInfo ti, GridP g, SpeciesP sp, int32_t *counts,
 // take a global atomic directly.  rank: >= 0 final, -1 removed, <= -2 local
 // rank (-2 - r) awaiting its key's base.
 constexpr int SORT_T = 512;
+constexpr int SCAT_NS = 9;                    // particles per thread of a tile held in registers
+constexpr int SCAT_CAP = SORT_T * SCAT_NS;    // 4608: the largest tile handled that way
 __global__ __launch_bounds__(SORT_T) void k_sort_count_tiles(TileInfo ti, GridP g, SpeciesP sp,
                                                              int32_t *counts, int32_t *rank,
                                                              uint32_t *fault) {
@@ -743,6 +745,40 @@ __global__ __launch_bounds__(SORT_T) void k_sort_count_tiles(TileInfo ti, GridP 
     for (int l = threadIdx.x; l < TC; l += SORT_T) hist[l] = 0;
     __syncthreads();
     const long long t0 = (long long)t * TC;
+    if (end - beg <= SORT_T * SCAT_NS) {
+        // the tile's particles fit SCAT_NS per thread: cells loaded at once,
+        // local ranks kept in registers for the final pass
+        int kl[SCAT_NS], lr[SCAT_NS];  // key within the tile (-1: none), local rank
+#pragma unroll
+        for (int k = 0; k < SCAT_NS; ++k) {
+            const int p = beg + (int)threadIdx.x + k * SORT_T;
+            kl[k] = -1;
+            lr[k] = 0;
+            if (p >= end) continue;
+            const uint32_t c = sp.cell[p];
+            const int i = cell_i(c), j = cell_j(c), kk = cell_k(c);
+            if (c == DEAD || i >= g.n[0] || j >= g.n[1] || kk >= g.n[2]) {
+                if (c != DEAD) atomicOr(fault, (uint32_t)EMPIC_FAULT_CELL);
+                rank[p] = -1;
+                continue;
+            }
+            const long long key = sort_key(ti, i, j, kk);
+            if (key >= t0 && key < t0 + TC) {
+                kl[k] = (int)(key - t0);
+                lr[k] = atomicAdd(hist + kl[k], 1);
+            } else {
+                rank[p] = atomicAdd(counts + key, 1);
+            }
+        }
+        __syncthreads();
+        for (int l = threadIdx.x; l < TC; l += SORT_T)
+            basek[l] = hist[l] ? atomicAdd(counts + t0 + l, hist[l]) : 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SCAT_NS; ++k)
+            if (kl[k] >= 0) rank[beg + (int)threadIdx.x + k * SORT_T] = basek[kl[k]] + lr[k];
+        return;
+    }
     for (int p = beg + threadIdx.x; p < end; p += SORT_T) {
         const uint32_t c = sp.cell[p];
         if (c == DEAD) {
@@ -865,8 +901,6 @@ __global__ void k_sort_scatter(TileInfo ti, SpeciesP cur, SpeciesP alt, const in
 // written straight to their slots (the slots of the new range that they
 // fill are skipped by their new tile's workgroup), and so is every particle
 // of a tile whose old or new range exceeds the LDS staging.
-constexpr int SCAT_NS = 9;                    // old slots per thread
-constexpr int SCAT_CAP = SORT_T * SCAT_NS;    // 4608 slots of LDS staging
 __global__ __launch_bounds__(SORT_T) void k_sort_scatter_tiles(TileInfo ti, SpeciesP cur,
                                                                SpeciesP alt, const int32_t *offs,
                                                                const int32_t *rank,
