@@ -707,22 +707,42 @@ __global__ void k_store_f32(GridP g, SpeciesP sp, double *pos, double *u, int32_
 // Counting sort by (tile, cell): rank within key from the histogram atomics,
 // exclusive scan of the key counts, scatter into the other buffer set.
 // ---------------------------------------------------------------------------
+// Every lane of a wave takes part (no early exit before the shuffles):
+// consecutive lanes with the same key (particles still in cell order, as
+// generated or as left by a previous sort) take their ranks from one atomic
+// of their run's first lane.
 __global__ void k_sort_count(TileInfo ti, GridP g, SpeciesP sp, int32_t *counts, int32_t *rank,
                              uint32_t *fault) {
     const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (p >= *sp.count) return;
-    const uint32_t c = sp.cell[p];
-    if (c == DEAD) {
-        rank[p] = -1;
-        return;
+    const bool in = p < *sp.count;
+    long long key = -1;
+    if (in) {
+        const uint32_t c = sp.cell[p];
+        const int i = cell_i(c), j = cell_j(c), k = cell_k(c);
+        if (c != DEAD) {
+            if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2])
+                atomicOr(fault, (uint32_t)EMPIC_FAULT_CELL);
+            else
+                key = sort_key(ti, i, j, k);
+        }
+        if (key < 0) rank[p] = -1;
     }
-    const int i = cell_i(c), j = cell_j(c), k = cell_k(c);
-    if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) {
-        atomicOr(fault, (uint32_t)EMPIC_FAULT_CELL);
-        rank[p] = -1;
-        return;
+    const int lane = (int)(threadIdx.x & 63);
+    const long long prev = __shfl_up(key, 1u, 64);
+    const bool head = key >= 0 && (lane == 0 || prev != key);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long stops = heads | ~__ballot(key >= 0);  // lanes that end a run
+    int base = 0;
+    if (head) {
+        const unsigned long long above = lane == 63 ? 0ull : stops & (~0ull << (lane + 1));
+        const int e = above ? __builtin_ctzll(above) : 64;
+        base = atomicAdd(counts + key, e - lane);
     }
-    rank[p] = atomicAdd(counts + sort_key(ti, i, j, k), 1);
+    // the first lane of this lane's run: the highest head at or below it
+    const unsigned long long upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+    const int h = upto ? 63 - __builtin_clzll(upto) : lane;
+    base = __shfl(base, h, 64);
+    if (key >= 0) rank[p] = base + (lane - h);
 }
 
 // Counting pass when the particles are still grouped by the tiles of the
