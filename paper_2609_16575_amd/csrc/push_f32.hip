@@ -5,16 +5,20 @@
 // per-particle weight).  Offsets relative to the cell keep the rounding of a
 // position at 2^-24 of a cell wherever the particle is in the grid.
 //
-// k_push_fused: one workgroup (512 threads) per 8x8x4 tile of cells
-// (particles counting-sorted by tile, then cell).  The workgroup
+// k_push_fused: one workgroup (512 threads) per 8x8x4 tile of cells (16x2x8
+// on grids at most three cells thick along y; particles counting-sorted by
+// tile, then cell).  The workgroup
 //   1. stages E^n and the centred B^n of the tile plus a halo into LDS
-//      (12 x 12 x 8 cells x 6 components),
+//      (12 x 12 x 8 cells x 6 components; a thread owns the same window
+//      points of every component and issues all its loads before waiting),
 //   2. zeroes an LDS current window (13 x 13 x 9 edges x 3),
 //   3. streams its particles: each thread owns PPT = 4 consecutive particles,
-//      one 16-byte access per array, and for each does the staggered CIC
-//      gather from LDS (Sec. 2.5), the relativistic Boris push (Sec. 2.4), the
-//      move and the ZigZag deposit (Sec. 2.5): 12 int64 LDS atomics per
-//      straight segment (24 for a particle crossing a cell face),
+//      one 16-byte access per array (one particle per thread in a tile with
+//      at most 1024 of a species; species 0's are then loaded together with
+//      the window), and for each does the staggered CIC gather from LDS (Sec.
+//      2.5), the relativistic Boris push (Sec. 2.4), the move and the ZigZag
+//      deposit (Sec. 2.5): 12 int64 LDS atomics per straight segment (24 for
+//      a particle crossing a cell face),
 //   4. adds the non-zero LDS current to global J with float atomics.
 // Particles that drifted more than MARGIN cells out of their tile since the
 // last sort are handled entirely through global memory (rare, counted).
@@ -421,7 +425,6 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
 
     uint32_t fbits = 0;
     unsigned nfb = 0;
-    constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
 
     // a sparse tile (few particles of a species) takes one particle per
     // thread, so that all its waves work; a dense one four per thread
