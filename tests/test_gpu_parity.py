@@ -243,10 +243,13 @@ def test_fp32_out_of_window_fallback():
     assert d["fault_word"] & 16
 
 
-@pytest.mark.parametrize("n", [(16, 16, 16), (40, 2, 20)])
-def test_sort_is_a_permutation(n):
-    """Also on a grid two cells thick along y, which gets the 16 x 2 x 8 tiles."""
-    w = W.thermal_two_species(n=n, ppc=4)
+@pytest.mark.parametrize("n,ppc", [((16, 16, 16), 4), ((40, 2, 20), 4), ((16, 16, 16), 20)])
+def test_sort_is_a_permutation(n, ppc):
+    """Also on a grid two cells thick along y, which gets the 16 x 2 x 8 tiles,
+    and with 20 per cell: 5120 particles of a species per tile, more than the
+    sort's per-tile register and LDS staging holds (4608), so that its
+    direct paths run."""
+    w = W.thermal_two_species(n=n, ppc=ppc)
     g = _sim(w, "fp32")
     g.step(3)
     before = [g.particles_by_id(i) for i in range(2)]
