@@ -165,7 +165,9 @@ typedef struct {
  * Gauss residual r = div E - rho - rho_bg at nodes (backward differences).
  * cont_max = max |rho^n - rho^{n-1} + dt div J^{n-1/2}| when the previous
  * call was made exactly one step earlier (cont_valid = 1), with rho_max the
- * largest |rho^n| of the particles for scale. */
+ * largest |rho^n| of the particles for scale; the nodes on the faces of a
+ * walled (absorbing or PEC) axis are left out of cont_max, since a particle
+ * leaving through the wall takes its charge out of the grid there. */
 typedef struct {
     int64_t step;
     double t;
@@ -357,7 +359,10 @@ empic_status empic_load_state(empic_sim *s, const empic_state *src);
  * tile offsets and slot count are carried over, ids and per-particle weights
  * copied unless dst shares src's arrays, and dst receives the new fields.
  * For re-computing the states between checkpoints without copying them.
- * src and dst must not share cell, offset or momentum arrays. */
+ * src and dst must not share cell, offset or momentum arrays.  A state
+ * carries no time: the handle's step count is left as it was, and a handle
+ * with a laser, port or moving window (whose fields depend on the step's
+ * time) gets EMPIC_E_UNSUPPORTED. */
 empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_state *dst);
 
 /* Vector-Jacobian product of one step taken from state st: lam holds the

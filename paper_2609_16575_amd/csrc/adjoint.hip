@@ -80,7 +80,7 @@ struct GlobAcc {
     __device__ float L(int c, int i, int j, int k) const { return lJ[c][idx(i, j, k)]; }
 };
 
-// trilinear value with the step kernel's operation order (tri_lds / tri_global)
+// trilinear value with the step kernel's operation order (tri_lds_at / tri_global)
 // and its gradient in the fractional coordinates
 template <class Acc>
 __device__ __forceinline__ void tri_vg(const Acc &a, int q, int i, int j, int k, float fx, float fy,

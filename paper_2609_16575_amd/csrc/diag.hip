@@ -65,8 +65,16 @@ __global__ void k_continuity(GridP g, const T *Jx, const T *Jy, const T *Jz, con
             for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.ext[0];
                  i += gridDim.x * blockDim.x) {
                 const long long p = i + (long long)g.ext[0] * (j + (long long)g.ext[1] * k);
-                // rho^{n+1} - rho^n + dt div J^{n+1/2}
-                const double r = rho_now[p] - rho_prev[p] + g.dt * div_node(g, Jx, Jy, Jz, i, j, k);
+                // rho^{n+1} - rho^n + dt div J^{n+1/2}, on every node but those
+                // of the faces of a walled axis: a particle that leaves through
+                // the wall takes its charge out of the grid there
+                const int idx[3] = {i, j, k};
+                bool face = false;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    face = face || (g.bc[a] != EMPIC_BC_PERIODIC && (idx[a] == 0 || idx[a] == g.n[a]));
+                const double r =
+                    face ? 0.0 : rho_now[p] - rho_prev[p] + g.dt * div_node(g, Jx, Jy, Jz, i, j, k);
                 mx = fmax(mx, fabs(r));
                 rm = fmax(rm, fabs(rho_now[p]));
             }

@@ -1174,6 +1174,11 @@ empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_
     if (!src || !dst || !s->bound) return fail(s, EMPIC_E_ARG, "null state or fields not bound");
     if (fp64(s)) return fail(s, EMPIC_E_UNSUPPORTED, "states are for the FP32 path");
     if (src == dst) return fail(s, EMPIC_E_ARG, "source and destination must differ");
+    // a state carries no time: a step whose sources or window depend on it
+    // cannot be taken from a state
+    if (s->laser.enabled || s->port.enabled || s->window.enabled)
+        return fail(s, EMPIC_E_UNSUPPORTED,
+                    "step_state: a laser, port or moving window depends on the step's time");
     const size_t fb = (size_t)s->g.V * 4;
     for (int a = 0; a < 3; ++a)
         if (!src->E[a] || !src->B[a] || !dst->E[a] || !dst->B[a])
@@ -1230,7 +1235,10 @@ empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_
         if (S.desc.per_particle_w && dst->w[i] != src->w[i])
             EMPIC_HIP(hipMemcpyAsync(dst->w[i], src->w[i], pb, hipMemcpyDeviceToDevice, s->stream));
     }
+    // the handle's own clock (diagnostics, sort schedule) does not move
+    const long long nstep = s->nstep;
     one_step<float>(s, s->xtable, 0, (int)((1u << s->nsp) - 1u));
+    s->nstep = nstep;
     for (int a = 0; a < 3; ++a) {
         EMPIC_HIP(hipMemcpyAsync(dst->E[a], s->E[a], fb, hipMemcpyDeviceToDevice, s->stream));
         EMPIC_HIP(hipMemcpyAsync(dst->B[a], s->B[a], fb, hipMemcpyDeviceToDevice, s->stream));

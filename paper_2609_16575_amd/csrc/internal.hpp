@@ -33,9 +33,14 @@ constexpr int TC = 256;  // cells per tile (every shape)
 // its LDS windows: the field window covers the gather stencil (cells -1..+1
 // around a particle cell), the current window one cell more (the second
 // ZigZag segment) and the far edges.
-template <int X, int Y, int Z>
+//
+// QCAP: entries of the LDS queue of second ZigZag segments (particles that
+// cross a cell face deposit their first segment at once and queue the
+// second, which the workgroup deposits after the tile's particles); 0: no
+// queue, the second segment is deposited at once.
+template <int X, int Y, int Z, int Q>
 struct TileT {
-    static constexpr int TX = X, TY = Y, TZ = Z;
+    static constexpr int TX = X, TY = Y, TZ = Z, QCAP = Q;
     static constexpr int FWX = X + 2 * MARGIN + 2, FWY = Y + 2 * MARGIN + 2, FWZ = Z + 2 * MARGIN + 2;
     static constexpr int JWX = X + 2 * MARGIN + 3, JWY = Y + 2 * MARGIN + 3, JWZ = Z + 2 * MARGIN + 3;
     static constexpr int FW3 = FWX * FWY * FWZ, JW3 = JWX * JWY * JWZ;
@@ -47,12 +52,14 @@ struct TileT {
                   "power-of-two tile sides (sort keys use shifts)");
 };
 // Three-dimensional grids: 8 x 8 x 4, field window 27.6 KB + int64 current
-// window 36.5 KB, two workgroups per CU.
-using TileCube = TileT<8, 8, 4>;
+// window 36.5 KB + a 16 KB crossing queue, two workgroups per CU (158.4 of
+// the 160 KB of LDS).
+using TileCube = TileT<8, 8, 4, 512>;
 // Grids at most three cells thick along y (the two-dimensional runs):
 // 16 x 2 x 8 keeps 256 cells per tile where the cube would hold 8 x 2 x 4;
-// 34.6 KB + 45.9 KB, still two workgroups in a CU's 160 KB of LDS.
-using TileSlab = TileT<16, 2, 8>;
+// 34.6 KB + 45.9 KB, still two workgroups in a CU's 160 KB of LDS, which
+// leaves no room for a crossing queue.
+using TileSlab = TileT<16, 2, 8, 0>;
 
 // Packed cell index of the FP32 path: i | j << 11 | k << 22; all ones = removed.
 constexpr uint32_t DEAD = 0xFFFFFFFFu;

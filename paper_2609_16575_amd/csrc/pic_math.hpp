@@ -184,11 +184,12 @@ __device__ __forceinline__ bool new_cell(const GridP &g, int a, int c, int dc, i
 }
 
 // ---- LDS window versions ----
+// trilinear value from the LDS field window at byte address pb (the corner
+// of lowest index)
 template <class TL>
-__device__ __forceinline__ float tri_lds(const float *F, int i, int j, int k, float fx, float fy,
-                                         float fz) {
+__device__ __forceinline__ float tri_lds_at(const char *pb, float fx, float fy, float fz) {
     constexpr int FWX = TL::FWX, FWY = TL::FWY;
-    const float *p = F + i + FWX * (j + FWY * k);
+    const float *p = (const float *)pb;
     const float c00 = lerpf(p[0], p[1], fx);
     const float c10 = lerpf(p[FWX], p[FWX + 1], fx);
     const float c01 = lerpf(p[FWX * FWY], p[FWX * FWY + 1], fx);
@@ -213,6 +214,13 @@ __device__ __forceinline__ int edge_off(int q) {
 __device__ __forceinline__ long long to_fixed(float x, double scale) {
     const double t = fma((double)x, scale, 6755399441055744.0);
     return __double_as_longlong(t) - 0x4338000000000000LL;
+}
+
+// int64 fixed point -> float: x inv with x converted exactly in two halves
+// (one rounding in the FMA, as a direct conversion), then rounded to FP32
+__device__ __forceinline__ float from_fixed(long long x, double inv) {
+    const double d = fma((double)(int)(x >> 32), 4294967296.0, (double)(uint32_t)x);
+    return (float)(d * inv);
 }
 
 __device__ __forceinline__ int local_axis(const GridP &g, int a, int c, int wo) {

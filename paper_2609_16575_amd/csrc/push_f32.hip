@@ -168,187 +168,284 @@ __device__ __forceinline__ void load_batch(const SpeciesP &S, int base, Batch<P>
     if (S.per_particle_w) b.w = __builtin_nontemporal_load((const VF *)((const gfloat *)S.w + base));
 }
 
+// Mid-point and displacement of the second ZigZag segment of a move from
+// offset o by dx with cell step dc, relative to the cell + dc: from the relay
+// point (the face crossed, or the mid-point of the move on an axis without a
+// crossing) to the end o + dx (Sec. 2.5)
+__device__ __forceinline__ void second_segment(const float o[3], const float dx[3],
+                                               const int dc[3], float WB[3], float DB[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float e = o[a] + dx[a];  // the end point as the move computed it
+        const float xr = dc[a] > 0 ? 1.f : 0.f;
+        DB[a] = dc[a] != 0 ? e - xr : 0.5f * dx[a];
+        WB[a] = dc[a] != 0 ? fmaf(0.5f, xr + e, -(float)dc[a]) : fmaf(0.75f, dx[a], o[a]);
+    }
+}
+
+// Queue of second ZigZag segments (TL::QCAP entries of 32 bytes): per entry
+// the particle's offset o and move dx (cell units), a code word (the
+// current-window index of its cell in bits 0-10, the cell step + 1 per axis
+// in bits 11-16, the species from bit 17) and the weight.
+struct SegQueue {
+    float4 *q;       // 2 float4 per entry
+    unsigned *n;     // entries claimed (may exceed the capacity)
+};
+
+// Per-tile constants of the particle loop.
+struct TileCtx {
+    int wo[3];          // global cell of window point 0 per axis
+    uint32_t wo_pack;   // the same, packed (interior tiles only)
+};
+
 // One species of one tile: P consecutive particles per thread (one access
 // of P elements per array), gather from the LDS field window, Boris (Sec.
 // 2.4), move, ZigZag deposit (Sec. 2.5) into the LDS current window; the
 // new state goes to the write set.  With use_pre, `pre` holds this thread's
 // first batch (the caller issued its loads early).
-template <class TL, int P>
+//
+// INTERIOR: the tile's current window lies inside the grid on every axis,
+// so that window-relative and new cell indices need no periodic wrap and no
+// removal test: both are sums on the packed cell index.
+//
+// The deposit of a particle that crosses a cell face is split as usual
+// (relay point per axis); its first segment is deposited with every other
+// particle's move, and its move goes to the workgroup's queue, whose second
+// segments are deposited once the tile's particles are done, so that the
+// rare crossings do not make every lane of a wave wait for a second
+// segment.  A full queue makes the particle deposit its second segment at
+// once.
+template <class TL, int P, bool INTERIOR>
 __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecies &D,
                                              const SpeciesP &S, const SpeciesP &Wr, int beg,
-                                             int end, const int wo[3], const float *sF,
-                                             unsigned long long *sJ, int s, uint32_t &fbits,
-                                             unsigned &nfb, const Batch<P> &pre,
+                                             int end, const TileCtx &T, const float *sF,
+                                             unsigned long long *sJ, const SegQueue &Q, int s,
+                                             uint32_t &fbits, unsigned &nfb, const Batch<P> &pre,
                                              bool use_pre) {
     typedef float VF __attribute__((ext_vector_type(P)));
     typedef uint32_t VU __attribute__((ext_vector_type(P)));
-    constexpr int FW3 = TL::FW3, JWX = TL::JWX, JWY = TL::JWY;
+    constexpr int FW3 = TL::FW3, FWX = TL::FWX, FWY = TL::FWY, JWX = TL::JWX, JWY = TL::JWY;
     constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
     const GridP &g = A.g;
-        const float r = D.r;
-        const float qcx = D.qc[0], qcy = D.qc[1], qcz = D.qc[2];
-        guint *CQ = (guint *)Wr.cell;
-        gfloat *OXQ = (gfloat *)Wr.pos[0], *OYQ = (gfloat *)Wr.pos[1], *OZQ = (gfloat *)Wr.pos[2];
-        gfloat *UXQ = (gfloat *)Wr.u[0], *UYQ = (gfloat *)Wr.u[1], *UZQ = (gfloat *)Wr.u[2];
-        // per-component window bases, opaque to the compiler so that it keeps
-        // one register base per component and puts the eight corner offsets of
-        // a gather into the ds_read2 offset fields
-        const float *sFc[6];
+    const float r = D.r;
+    const float qcx = D.qc[0], qcy = D.qc[1], qcz = D.qc[2];
+    const float dtd0 = A.dtd[0], dtd1 = A.dtd[1], dtd2 = A.dtd[2];
+    guint *CQ = (guint *)Wr.cell;
+    gfloat *OXQ = (gfloat *)Wr.pos[0], *OYQ = (gfloat *)Wr.pos[1], *OZQ = (gfloat *)Wr.pos[2];
+    gfloat *UXQ = (gfloat *)Wr.u[0], *UYQ = (gfloat *)Wr.u[1], *UZQ = (gfloat *)Wr.u[2];
+    // per-component window bases, opaque to the compiler so that it keeps one
+    // register base per component and puts the eight corner offsets of a
+    // gather into the ds_read2 offset fields
+    const char *sFc[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            uint32_t o = c * FW3;
-            asm volatile("" : "+s"(o));
-            sFc[c] = sF + o;
-        }
-        const int base0 = batch_base0<P>(beg) + (int)threadIdx.x * P;
-        // one (non-temporal) access of P consecutive particles per array; with
-        // one particle per thread the batch of the next pass is loaded at the
-        // end of this one (the first may come from the caller)
-        Batch<P> b;
-        if constexpr (P == 1) {
-            if (use_pre) b = pre;
-            else if (base0 < end) load_batch<P>(S, base0, b);
-        }
-        for (int base = base0; base < end; base += PUSH_THREADS * P) {
-            if constexpr (P != 1) load_batch<P>(S, base, b);
-            const VU c4 = b.c;
-            const VF ox4 = b.ox, oy4 = b.oy, oz4 = b.oz, ux4 = b.ux, uy4 = b.uy, uz4 = b.uz, w4 = b.w;
-
-            // per particle: staggered CIC gather from LDS (Sec. 2.5), Boris push
-            // (Sec. 2.4), move, ZigZag deposit (Sec. 2.5) into the fixed-point LDS
-            // window.  A particle outside the tile window keeps its state here and is
-            // pushed by k_push_fallback.
-            float nux[P], nuy[P], nuz[P], nox[P], noy[P], noz[P];
-            uint32_t ncell[P];
+    for (int c = 0; c < 6; ++c) {
+        uint32_t o = c * FW3 * 4;
+        asm volatile("" : "+s"(o));
+        sFc[c] = (const char *)sF + o;
+    }
+    const int lane = (int)(threadIdx.x & 63);
+    const int base0 = batch_base0<P>(beg) + (int)threadIdx.x * P;
+    // one (non-temporal) access of P consecutive particles per array; with
+    // one particle per thread the batch of the next pass is loaded at the
+    // end of this one (the first may come from the caller)
+    Batch<P> b;
+    if constexpr (P == 1) {
+        if (use_pre) b = pre;
+        else if (base0 < end) load_batch<P>(S, base0, b);
+    }
+    for (int base = base0; base < end; base += PUSH_THREADS * P) {
+        if constexpr (P != 1) load_batch<P>(S, base, b);
+        // a pushed particle's new state replaces its loaded one in the batch
+        // registers; one not pushed here keeps its record
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                const int p = base + k;
-                const uint32_t c = c4[k];
-                const bool valid = p >= beg && p < end && c != DEAD;
-                const int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
-                const float ox = ox4[k], oy = oy4[k], oz = oz4[k];
-                ncell[k] = c;
-                nox[k] = ox;
-                noy[k] = oy;
-                noz[k] = oz;
-                nux[k] = ux4[k];
-                nuy[k] = uy4[k];
-                nuz[k] = uz4[k];
-                if (!valid) continue;
-                if (!(ox >= 0.f && ox < 1.f && oy >= 0.f && oy < 1.f && oz >= 0.f && oz < 1.f))
-                    fbits |= EMPIC_FAULT_OFFSET;
-                const int lx = local_axis(g, 0, ci, wo[0]);
-                const int ly = local_axis(g, 1, cj, wo[1]);
-                const int lz = local_axis(g, 2, ck, wo[2]);
-                if (!(lx >= 1 && lx <= LHI_X && ly >= 1 && ly <= LHI_Y && lz >= 1 && lz <= LHI_Z)) {
-                    // drifted out of the tile window since the last sort
-                    ++nfb;
-                    const unsigned slot = atomicAdd(A.fb_count, 1u);
-                    if (slot < (unsigned long long)A.fb_cap) A.fb_list[slot] = make_int2(s, p);
-                    else fbits |= EMPIC_FAULT_CELL;
-                    continue;
+        for (int k = 0; k < P; ++k) {
+            const int p = base + k;
+            const uint32_t c = b.c[k];
+            if (!(p >= beg && p < end && c != DEAD)) continue;
+            // window-relative cell
+            int lx, ly, lz;
+            if constexpr (INTERIOR) {
+                const uint32_t cl = c - T.wo_pack;  // exact for every particle inside the window
+                lx = (int)(cl & 0x7FFu);
+                ly = (int)((cl >> 11) & 0x7FFu);
+                lz = (int)(cl >> 22);
+            } else {
+                lx = local_axis(g, 0, cell_i(c), T.wo[0]);
+                ly = local_axis(g, 1, cell_j(c), T.wo[1]);
+                lz = local_axis(g, 2, cell_k(c), T.wo[2]);
+            }
+            if (!((unsigned)(lx - 1) < (unsigned)LHI_X && (unsigned)(ly - 1) < (unsigned)LHI_Y &&
+                  (unsigned)(lz - 1) < (unsigned)LHI_Z)) {
+                // drifted out of the tile window since the last sort: pushed
+                // by k_push_fallback
+                ++nfb;
+                const unsigned slot = atomicAdd(A.fb_count, 1u);
+                if (slot < (unsigned long long)A.fb_cap) A.fb_list[slot] = make_int2(s, p);
+                else fbits |= EMPIC_FAULT_CELL;
+                continue;
+            }
+            const float ox = b.ox[k], oy = b.oy[k], oz = b.oz[k];
+            // a NaN offset is caught below as a non-finite momentum
+            if (!(fminf(fminf(ox, oy), oz) >= 0.f && fmaxf(fmaxf(ox, oy), oz) < 1.f))
+                fbits |= EMPIC_FAULT_OFFSET;
+            int hx, hy, hz;
+            float fx, fy, fz;
+            half_axis(ox, lx, hx, fx);
+            half_axis(oy, ly, hy, fy);
+            half_axis(oz, lz, hz, fz);
+            // byte offsets of the node (l) and half (h) positions per axis
+            const uint32_t xl = (uint32_t)lx * 4u, xh = (uint32_t)hx * 4u;
+            const uint32_t yl = __umul24((uint32_t)ly, FWX * 4), yh = __umul24((uint32_t)hy, FWX * 4);
+            const uint32_t zl = __umul24((uint32_t)lz, FWX * FWY * 4),
+                           zh = __umul24((uint32_t)hz, FWX * FWY * 4);
+            float Ep[3], Bp[3];
+            Ep[0] = tri_lds_at<TL>(sFc[0] + (xh + yl + zl), fx, oy, oz);
+            Ep[1] = tri_lds_at<TL>(sFc[1] + (xl + yh + zl), ox, fy, oz);
+            Ep[2] = tri_lds_at<TL>(sFc[2] + (xl + yl + zh), ox, oy, fz);
+            Bp[0] = tri_lds_at<TL>(sFc[3] + (xl + yh + zh), ox, fy, fz);
+            Bp[1] = tri_lds_at<TL>(sFc[4] + (xh + yl + zh), fx, oy, fz);
+            Bp[2] = tri_lds_at<TL>(sFc[5] + (xh + yh + zl), fx, fy, oz);
+            float ux = b.ux[k], uy = b.uy[k], uz = b.uz[k], gam;
+            const float ig = boris_f32(ux, uy, uz, Ep, Bp, r, gam);
+            if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
+            const float o[3] = {ox, oy, oz};
+            const float dx[3] = {ux * ig * dtd0, uy * ig * dtd1, uz * ig * dtd2};
+            if (!(fmaxf(fmaxf(fabsf(dx[0]), fabsf(dx[1])), fabsf(dx[2])) < 1.f))
+                fbits |= EMPIC_FAULT_FAST;
+            float e[3], no[3];
+            int dc[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) move_axis_sel(o[a], dx[a], e[a], dc[a], no[a]);
+            const float wq = b.w[k];
+            const float amp[3] = {qcx * wq, qcy * wq, qcz * wq};
+            const int jb = lx + JWX * (ly + JWY * lz);
+            const bool cross = (dc[0] | dc[1] | dc[2]) != 0;
+            // first segment: the whole move inside the cell, or from the start
+            // to the relay point (Sec. 2.5, ZigZag)
+            const float half = cross ? 0.5f : 1.f;
+            float WA[3], DA[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float xr = dc[a] > 0 ? 1.f : 0.f;
+                DA[a] = dc[a] != 0 ? xr - o[a] : half * dx[a];
+                WA[a] = fmaf(0.5f, DA[a], o[a]);
+            }
+            float v[12];
+            segment_weights(WA, DA, amp, v);
+            lds_add12<TL>(sJ, jb, v, A.jscale);
+            // second segment of the crossing particles: from the relay point
+            // to the end, in the cell + dc; queued as the move itself (the
+            // segment is worked out when the queue is deposited)
+            const unsigned long long m = __ballot(cross);
+            if (m) {
+                bool now = cross;
+                if constexpr (TL::QCAP > 0) {
+                    unsigned qb = 0;
+                    if (lane == __builtin_ctzll(__ballot(1)))
+                        qb = atomicAdd(Q.n, (unsigned)__popcll(m));
+                    const unsigned slot =
+                        __builtin_amdgcn_readfirstlane(qb) +
+                        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (cross && slot < (unsigned)TL::QCAP) {
+                        const uint32_t code = (uint32_t)jb | ((uint32_t)(dc[0] + 1) << 11) |
+                                              ((uint32_t)(dc[1] + 1) << 13) |
+                                              ((uint32_t)(dc[2] + 1) << 15) | ((uint32_t)s << 17);
+                        Q.q[2 * slot] = make_float4(o[0], o[1], o[2], __uint_as_float(code));
+                        Q.q[2 * slot + 1] = make_float4(dx[0], dx[1], dx[2], wq);
+                        now = false;
+                    }
                 }
-                int hx, hy, hz;
-                float fx, fy, fz;
-                half_axis(ox, lx, hx, fx);
-                half_axis(oy, ly, hy, fy);
-                half_axis(oz, lz, hz, fz);
-                float Ep[3], Bp[3];
-                Ep[0] = tri_lds<TL>(sFc[0], hx, ly, lz, fx, oy, oz);
-                Ep[1] = tri_lds<TL>(sFc[1], lx, hy, lz, ox, fy, oz);
-                Ep[2] = tri_lds<TL>(sFc[2], lx, ly, hz, ox, oy, fz);
-                Bp[0] = tri_lds<TL>(sFc[3], lx, hy, hz, ox, fy, fz);
-                Bp[1] = tri_lds<TL>(sFc[4], hx, ly, hz, fx, oy, fz);
-                Bp[2] = tri_lds<TL>(sFc[5], hx, hy, lz, fx, fy, oz);
-                float ux = ux4[k], uy = uy4[k], uz = uz4[k], gam;
-                const float ig = boris_f32(ux, uy, uz, Ep, Bp, r, gam);
-                if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
-                const float o[3] = {ox, oy, oz};
-                const float dx[3] = {ux * ig * A.dtd[0], uy * ig * A.dtd[1], uz * ig * A.dtd[2]};
-                if (!(fabsf(dx[0]) < 1.f && fabsf(dx[1]) < 1.f && fabsf(dx[2]) < 1.f))
-                    fbits |= EMPIC_FAULT_FAST;
-                float e[3], no[3];
-                int dc[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) move_axis_sel(o[a], dx[a], e[a], dc[a], no[a]);
-                const float wq = w4[k];
-                const float amp[3] = {qcx * wq, qcy * wq, qcz * wq};
-                const int jb = lx + JWX * (ly + JWY * lz);
-                float v[12];
-                if ((dc[0] | dc[1] | dc[2]) == 0) {
-                    // one straight segment in this cell
-                    const float W[3] = {fmaf(0.5f, dx[0], o[0]), fmaf(0.5f, dx[1], o[1]),
-                                        fmaf(0.5f, dx[2], o[2])};
-                    segment_weights(W, dx, amp, v);
-                    lds_add12<TL>(sJ, jb, v, A.jscale);
-                } else {
-                    float WA[3], DA[3], WB[3], DB[3];
-                    zigzag_split(o, dx, e, dc, WA, DA, WB, DB);
-                    segment_weights(WA, DA, amp, v);
-                    lds_add12<TL>(sJ, jb, v, A.jscale);
+                if (now) {
+                    float WB[3], DB[3];
+                    second_segment(o, dx, dc, WB, DB);
                     segment_weights(WB, DB, amp, v);
                     lds_add12<TL>(sJ, jb + dc[0] + JWX * (dc[1] + JWY * dc[2]), v, A.jscale);
                 }
-                int ni, nj, nk;
-                const int ok = (int)new_cell(g, 0, ci, dc[0], ni) & (int)new_cell(g, 1, cj, dc[1], nj) &
-                               (int)new_cell(g, 2, ck, dc[2], nk);
-                ncell[k] = ok ? pack_cell(ni, nj, nk) : DEAD;
-                nox[k] = no[0];
-                noy[k] = no[1];
-                noz[k] = no[2];
-                nux[k] = ux;
-                nuy[k] = uy;
-                nuz[k] = uz;
             }
-            if (base >= beg && base + P <= end) {
-                VU vc;
-                VF vox, voy, voz, vux, vuy, vuz;
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    vc[k] = ncell[k];
-                    vox[k] = nox[k];
-                    voy[k] = noy[k];
-                    voz[k] = noz[k];
-                    vux[k] = nux[k];
-                    vuy[k] = nuy[k];
-                    vuz[k] = nuz[k];
-                }
-                __builtin_nontemporal_store(vc, (VU *)(CQ + base));
-                __builtin_nontemporal_store(vox, (VF *)(OXQ + base));
-                __builtin_nontemporal_store(voy, (VF *)(OYQ + base));
-                __builtin_nontemporal_store(voz, (VF *)(OZQ + base));
-                __builtin_nontemporal_store(vux, (VF *)(UXQ + base));
-                __builtin_nontemporal_store(vuy, (VF *)(UYQ + base));
-                __builtin_nontemporal_store(vuz, (VF *)(UZQ + base));
+            if constexpr (INTERIOR) {
+                // inside the grid on every axis: a step of the packed index
+                b.c[k] = c + (uint32_t)(dc[0] + (dc[1] << 11) + (dc[2] << 22));
             } else {
-                // every slot of this tile, removed ones too (a step into another
-                // buffer set carries the whole record)
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    const int p = base + k;
-                    if (p < beg || p >= end) continue;
-                    CQ[p] = ncell[k];
-                    OXQ[p] = nox[k];
-                    OYQ[p] = noy[k];
-                    OZQ[p] = noz[k];
-                    UXQ[p] = nux[k];
-                    UYQ[p] = nuy[k];
-                    UZQ[p] = nuz[k];
-                }
+                int ni, nj, nk;
+                const int in = (int)new_cell(g, 0, cell_i(c), dc[0], ni) &
+                               (int)new_cell(g, 1, cell_j(c), dc[1], nj) &
+                               (int)new_cell(g, 2, cell_k(c), dc[2], nk);
+                b.c[k] = in ? pack_cell(ni, nj, nk) : DEAD;
             }
-            if constexpr (P == 1)
-                if (base + PUSH_THREADS * P < end) load_batch<P>(S, base + PUSH_THREADS * P, b);
+            b.ox[k] = no[0];
+            b.oy[k] = no[1];
+            b.oz[k] = no[2];
+            b.ux[k] = ux;
+            b.uy[k] = uy;
+            b.uz[k] = uz;
         }
+        if (base >= beg && base + P <= end) {
+            __builtin_nontemporal_store(b.c, (VU *)(CQ + base));
+            __builtin_nontemporal_store(b.ox, (VF *)(OXQ + base));
+            __builtin_nontemporal_store(b.oy, (VF *)(OYQ + base));
+            __builtin_nontemporal_store(b.oz, (VF *)(OZQ + base));
+            __builtin_nontemporal_store(b.ux, (VF *)(UXQ + base));
+            __builtin_nontemporal_store(b.uy, (VF *)(UYQ + base));
+            __builtin_nontemporal_store(b.uz, (VF *)(UZQ + base));
+        } else {
+            // every slot of this tile, removed ones too (a step into another
+            // buffer set carries the whole record)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const int p = base + k;
+                if (p < beg || p >= end) continue;
+                CQ[p] = b.c[k];
+                OXQ[p] = b.ox[k];
+                OYQ[p] = b.oy[k];
+                OZQ[p] = b.oz[k];
+                UXQ[p] = b.ux[k];
+                UYQ[p] = b.uy[k];
+                UZQ[p] = b.uz[k];
+            }
+        }
+        if constexpr (P == 1)
+            if (base + PUSH_THREADS * P < end) load_batch<P>(S, base + PUSH_THREADS * P, b);
+    }
+}
+
+// Every species of one tile (sparse ones one particle per thread, so that all
+// the workgroup's waves work; dense ones four per thread).
+template <class TL, bool INTERIOR>
+__device__ __forceinline__ void push_tile(const FusedArgs &A, const TileCtx &T, int tile,
+                                          bool sparse0, int beg0, int end0, const Batch<1> &pre1,
+                                          const float *sF, unsigned long long *sJ,
+                                          const SegQueue &Q, uint32_t &fbits, unsigned &nfb) {
+    if (sparse0)
+        push_species<TL, 1, INTERIOR>(A, A.tbl[0], A.tbl[0].p[A.cur_mask & 1u],
+                                      A.tbl[0].p[A.wr_mask & 1u], beg0, end0, T, sF, sJ, Q, 0,
+                                      fbits, nfb, pre1, true);
+    for (int s = sparse0 ? 1 : 0; s < A.nsp; ++s) {
+        const DevSpecies &D = A.tbl[s];
+        const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
+        const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
+        const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
+        if (beg >= end) continue;
+        if (end - beg <= 2 * PUSH_THREADS)
+            push_species<TL, 1, INTERIOR>(A, D, S, Wr, beg, end, T, sF, sJ, Q, s, fbits, nfb,
+                                          pre1, false);
+        else
+            push_species<TL, PPT, INTERIOR>(A, D, S, Wr, beg, end, T, sF, sJ, Q, s, fbits, nfb,
+                                            Batch<PPT>(), false);
+    }
 }
 
 template <class TL>
 __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
-    constexpr int FWX = TL::FWX, FWY = TL::FWY, FW3 = TL::FW3;
+    constexpr int FWX = TL::FWX, FWY = TL::FWY, FWZ = TL::FWZ, FW3 = TL::FW3;
     constexpr int JWX = TL::JWX, JWY = TL::JWY, JWZ = TL::JWZ, JW3 = TL::JW3;
     constexpr int ROWS = TL::ROWS;
+    constexpr int QN = TL::QCAP > 0 ? 2 * TL::QCAP : 1;
     __shared__ float sF[6 * FW3];
-    __shared__ unsigned long long sJ[3 * JW3];
+    __shared__ __align__(16) unsigned long long sJ[3 * JW3 + 1];
+    __shared__ float4 sQ[QN];
+    __shared__ unsigned sQn;
     __shared__ int sG[3][ROWS];
     __shared__ int sPad[3][ROWS];
 
@@ -372,15 +469,25 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     const int tx = tile % A.ti.nt[0];
     const int tyz = tile / A.ti.nt[0];
     const int ty = tyz % A.ti.nt[1], tz = tyz / A.ti.nt[1];
-    const int wo[3] = {tx * TX - MARGIN - 1, ty * TY - MARGIN - 1, tz * TZ - MARGIN - 1};
+    TileCtx T;
+    T.wo[0] = tx * TX - MARGIN - 1;
+    T.wo[1] = ty * TY - MARGIN - 1;
+    T.wo[2] = tz * TZ - MARGIN - 1;
+    const int JW[3] = {JWX, JWY, JWZ};
+    bool interior = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) interior = interior && T.wo[a] >= 0 && T.wo[a] + JW[a] <= g.n[a];
+    T.wo_pack = interior ? pack_cell(T.wo[0], T.wo[1], T.wo[2]) : 0u;
     const int tid = threadIdx.x;
 
     // global index tables of the window rows: x index, y*ext0, z*ext0*ext1
+    if (tid == 0) sQn = 0u;
     if (tid < 3 * ROWS) {
         const int a = tid / ROWS, l = tid % ROWS;
         const int wl = a == 0 ? JWX : (a == 1 ? JWY : JWZ);
         if (l < wl) {
-            const int gi = gaxis(g, a, wo[a] + l);
+            const int woa = a == 0 ? T.wo[0] : (a == 1 ? T.wo[1] : T.wo[2]);
+            const int gi = gaxis(g, a, woa + l);
             const int mul = a == 0 ? 1 : (a == 1 ? g.ext[0] : g.ext[0] * g.ext[1]);
             sG[a][l] = gi < 0 ? -1 : gi * mul;
             sPad[a][l] = (gi >= 0 && g.bc[a] != EMPIC_BC_PERIODIC && gi >= g.n[a]) ? 1 : 0;
@@ -388,79 +495,101 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     }
     __syncthreads();
     {
-        // a thread owns the same window points of all six components: their
-        // global offset is worked out once, and every load is issued before
-        // any is waited on
-        constexpr int NR = (FW3 + PUSH_THREADS - 1) / PUSH_THREADS;
-        int off[NR];
+        // a thread owns one (x, y) column of the window at every ZG-th z and
+        // the same points of all six components: their global offsets are
+        // worked out once, and every load is issued before any is waited on
+        constexpr int NCOL = FWX * FWY, ZG = PUSH_THREADS / NCOL, NZ = (FWZ + ZG - 1) / ZG;
+        const int col = tid % NCOL, zg = tid / NCOL;
+        if (zg < ZG) {
+            const int ly = col / FWX, lx = col - ly * FWX;
+            const int gxy = (sG[0][lx] >= 0 && sG[1][ly] >= 0) ? sG[0][lx] + sG[1][ly] : -1;
+            int off[NZ];
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const int r = tid + q * PUSH_THREADS;
-            off[q] = -1;
-            if (r < FW3) {
-                const int lz = r / (FWX * FWY);
-                const int r2 = r - lz * (FWX * FWY);
-                const int ly = r2 / FWX, lx = r2 - ly * FWX;
-                const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
-                if (gx >= 0 && gy >= 0 && gz >= 0) off[q] = gx + gy + gz;
+            for (int q = 0; q < NZ; ++q) {
+                const int lz = zg + q * ZG;
+                off[q] = (lz < FWZ && gxy >= 0 && sG[2][lz] >= 0) ? gxy + sG[2][lz] : -1;
             }
-        }
-        float tmp[6][NR];
+            float tmp[6][NZ];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            const float *src = c < 3 ? A.E[c] : A.Bb[c - 3];
+            for (int c = 0; c < 6; ++c) {
+                const float *src = c < 3 ? A.E[c] : A.Bb[c - 3];
 #pragma unroll
-            for (int q = 0; q < NR; ++q) tmp[c][q] = off[q] >= 0 ? src[off[q]] : 0.f;
-        }
-#pragma unroll
-        for (int c = 0; c < 6; ++c)
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                const int r = tid + q * PUSH_THREADS;
-                if (r < FW3) sF[c * FW3 + r] = tmp[c][q];
+                for (int q = 0; q < NZ; ++q) tmp[c][q] = off[q] >= 0 ? src[off[q]] : 0.f;
             }
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+#pragma unroll
+                for (int q = 0; q < NZ; ++q) {
+                    const int lz = zg + q * ZG;
+                    if (lz < FWZ) sF[c * FW3 + col + lz * NCOL] = tmp[c][q];
+                }
+        }
     }
-    for (int e = tid; e < 3 * JW3; e += PUSH_THREADS) sJ[e] = 0ull;
+    {
+        // 16-byte stores (the window has an even number of words with its pad)
+        uint4 *z4 = (uint4 *)sJ;
+        for (int e = tid; e < (3 * JW3 + 1) / 2; e += PUSH_THREADS) z4[e] = make_uint4(0u, 0u, 0u, 0u);
+    }
     __syncthreads();
 
     uint32_t fbits = 0;
     unsigned nfb = 0;
-
-    // a sparse tile (few particles of a species) takes one particle per
-    // thread, so that all its waves work; a dense one four per thread
-    if (sparse0)
-        push_species<TL, 1>(A, A.tbl[0], S0, A.tbl[0].p[A.wr_mask & 1u], beg0, end0, wo, sF, sJ,
-                            0, fbits, nfb, pre1, true);
-    for (int s = sparse0 ? 1 : 0; s < A.nsp; ++s) {
-        const DevSpecies &D = A.tbl[s];
-        const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
-        const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
-        const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
-        if (beg >= end) continue;
-        if (end - beg <= 2 * PUSH_THREADS)
-            push_species<TL, 1>(A, D, S, Wr, beg, end, wo, sF, sJ, s, fbits, nfb, pre1, false);
-        else
-            push_species<TL, PPT>(A, D, S, Wr, beg, end, wo, sF, sJ, s, fbits, nfb, Batch<PPT>(),
-                                  false);
-    }
+    const SegQueue Q = {sQ, &sQn};
+    if (interior)
+        push_tile<TL, true>(A, T, tile, sparse0, beg0, end0, pre1, sF, sJ, Q, fbits, nfb);
+    else
+        push_tile<TL, false>(A, T, tile, sparse0, beg0, end0, pre1, sF, sJ, Q, fbits, nfb);
     if (fbits) atomicOr(A.fault, fbits | (nfb ? EMPIC_FAULT_FALLBACK : 0u));
     else if (nfb) atomicOr(A.fault, (uint32_t)EMPIC_FAULT_FALLBACK);
     if (nfb) atomicAdd(A.fallback, (unsigned long long)nfb);
     __syncthreads();
+    if constexpr (TL::QCAP > 0) {
+        // the queued second segments
+        static_assert(TL::JW3 <= 2048, "window index in the 11 bits of a queue entry's code");
+        const int nq = (int)min(sQn, (unsigned)TL::QCAP);
+        for (int q = tid; q < nq; q += PUSH_THREADS) {
+            const float4 a = sQ[2 * q], bq = sQ[2 * q + 1];
+            const uint32_t code = __float_as_uint(a.w);
+            const int dc[3] = {(int)((code >> 11) & 3u) - 1, (int)((code >> 13) & 3u) - 1,
+                               (int)((code >> 15) & 3u) - 1};
+            const float *qc = A.tbl[code >> 17].qc;
+            const float amp[3] = {qc[0] * bq.w, qc[1] * bq.w, qc[2] * bq.w};
+            const float o[3] = {a.x, a.y, a.z}, dx[3] = {bq.x, bq.y, bq.z};
+            float WB[3], DB[3], v[12];
+            second_segment(o, dx, dc, WB, DB);
+            segment_weights(WB, DB, amp, v);
+            lds_add12<TL>(sJ, (int)(code & 0x7FFu) + dc[0] + JWX * (dc[1] + JWY * dc[2]), v,
+                          A.jscale);
+        }
+        __syncthreads();
+    }
     // add the tile's current to global J (non-zero entries only); a thread
-    // owns the same window points of the three components
-    for (int r = tid; r < JW3; r += PUSH_THREADS) {
-        const int lz = r / (JWX * JWY);
-        const int r2 = r - lz * (JWX * JWY);
-        const int ly = r2 / JWX, lx = r2 - ly * JWX;
-        const int gx = sG[0][lx], gy = sG[1][ly], gz = sG[2][lz];
-        if (gx < 0 || gy < 0 || gz < 0) continue;
-        const int lc[3] = {lx, ly, lz};
+    // owns one (x, y) column of the window at every ZG-th z, the same points
+    // of the three components
+    {
+        constexpr int NCOL = JWX * JWY, ZG = PUSH_THREADS / NCOL, NZ = (JWZ + ZG - 1) / ZG;
+        const int col = tid % NCOL, zg = tid / NCOL;
+        if (zg < ZG) {
+            const int ly = col / JWX, lx = col - ly * JWX;
+            const int gx = sG[0][lx], gy = sG[1][ly];
+            const bool skip0 = sPad[0][lx] != 0, skip1 = sPad[1][ly] != 0;
+            if (gx >= 0 && gy >= 0) {
 #pragma unroll
-        for (int comp = 0; comp < 3; ++comp) {
-            const long long fx = (long long)sJ[comp * JW3 + r];
-            if (fx == 0 || sPad[comp][lc[comp]]) continue;
-            atomicAdd(A.J[comp] + gx + gy + gz, (float)((double)fx * A.jinv));
+                for (int q = 0; q < NZ; ++q) {
+                    const int lz = zg + q * ZG;
+                    if (lz >= JWZ) break;
+                    const int gz = sG[2][lz];
+                    if (gz < 0) continue;
+                    const int r = col + lz * NCOL;
+                    const bool skip[3] = {skip0, skip1, sPad[2][lz] != 0};
+#pragma unroll
+                    for (int comp = 0; comp < 3; ++comp) {
+                        const long long fx = (long long)sJ[comp * JW3 + r];
+                        if (fx == 0 || skip[comp]) continue;
+                        atomicAdd(A.J[comp] + gx + gy + gz, from_fixed(fx, A.jinv));
+                    }
+                }
+            }
         }
     }
 }

@@ -222,6 +222,27 @@ class Sim:
         order = t.argsort(I)
         return tuple(x.cpu().numpy() for x in (pos[:n][m][order], u[:n][m][order], I[order]))
 
+    def particles_in_box(self, sp: int, lo, hi):
+        """(positions, momenta, ids) of the live particles of `sp` whose cell
+        coordinate x_a / d_a lies in [lo_a, hi_a) on every axis, sorted by id.
+        The selection runs on the device."""
+        t = self.torch
+        cap = self.caps[sp]
+        pos = t.empty((cap, 3), dtype=t.float64, device=self.dev)
+        u = t.empty((cap, 3), dtype=t.float64, device=self.dev)
+        idv = t.empty(cap, dtype=t.int32, device=self.dev)
+        cnt = C.c_int64()
+        LB.check(self.h, self.L.empic_store_particles_f64(self.h, sp, _ptr(pos), _ptr(u), _ptr(idv),
+                                                          C.byref(cnt)))
+        n = cnt.value
+        xi = pos[:n] / t.as_tensor(np.asarray(self.w.d, dtype=np.float64), device=self.dev)
+        m = idv[:n] >= 0
+        for a in range(3):
+            m &= (xi[:, a] >= float(lo[a])) & (xi[:, a] < float(hi[a]))
+        I = idv[:n][m]
+        order = t.argsort(I)
+        return tuple(x.cpu().numpy() for x in (pos[:n][m][order], u[:n][m][order], I[order]))
+
     def particles_by_id(self, sp: int):
         P, U, I = self.particles(sp)
         order = np.argsort(I, kind="stable")

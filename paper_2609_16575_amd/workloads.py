@@ -228,6 +228,24 @@ def cold_langmuir_lattice(n=(32, 32, 32), per_axis=(4, 2, 2), eps=1e-2, mode=1, 
                     (PERIODIC,) * 3, [sp], rho_bg=1.0, steps=steps, sort_every=0)
 
 
+def smooth_random_direction(pos, box, seed, scale=1e-2):
+    """A random direction in the space of all initial momenta of a species:
+    a smooth random momentum field (four Fourier modes per component with
+    integer wave numbers 0..2 along each axis and random phases) sampled at
+    each particle's position, normalised to unit RMS, plus white noise of the
+    same RMS, times `scale`.  A pure white-noise direction would be nearly
+    orthogonal to the modes a field loss responds to.  Seeded, draws only."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros_like(pos)
+    for c in range(3):
+        for _ in range(4):
+            k = rng.integers(0, 3, size=3) / np.asarray(box)
+            out[:, c] += rng.standard_normal() * np.cos(2 * np.pi * (pos @ k) + 2 * np.pi * rng.random())
+    out /= np.sqrt(np.mean(out ** 2))
+    out += rng.standard_normal(pos.shape)
+    return scale * out
+
+
 def weibel_bimaxwellian(n=(256, 256, 256), ppc=16, vth_x=0.25, vth_perp=0.05, steps=50,
                         seed=1005, sort_every=10):
     """Anisotropic (T_x/T_perp = 25) electrons over immobile ions.

@@ -59,3 +59,46 @@ def compare_state(gpu, orc, w, sp_tol, f_tol, label=""):
         tol = f_tol if k in ("E", "B", "J") else sp_tol
         assert v <= tol, (label, k, v, tol, errs)
     return errs
+
+
+def check_box_currents(g, w, boxes, tol, margin=2):
+    """One step of the GPU run `g`, with J compared element-wise with the
+    oracle's inside each box (lo, hi) of cells: the oracle takes the GPU's
+    fields and every particle within `margin` cells of the box (a particle
+    moves at most one cell, so these are all that deposit inside it) and
+    steps once.  Returns the largest relative difference (to max |J| over
+    the box)."""
+    E, B, _ = g.fields()
+    parts = []
+    for i in range(len(w.species)):
+        got = {}
+        for lo, hi in boxes:
+            lo_m = [lo[a] - margin for a in range(3)]
+            hi_m = [hi[a] + margin for a in range(3)]
+            P, U, I = g.particles_in_box(i, lo_m, hi_m)
+            for k in range(len(I)):
+                got[int(I[k])] = (P[k], U[k])
+        ids = np.array(sorted(got), dtype=np.int64)
+        P = np.array([got[k][0] for k in ids]).reshape(-1, 3)
+        U = np.array([got[k][1] for k in ids]).reshape(-1, 3)
+        parts.append((P, U, ids))
+    g.step(1)
+    _, _, Jg = g.fields()
+    o = O.OracleSim(w.n, w.d, w.dt, w.bc)
+    o.E[...] = E
+    o.B[...] = B
+    for i, (P, U, I) in enumerate(parts):
+        s = w.species[i]
+        wpp = None if s.wpp is None else s.wpp[I]
+        o.add_species(s.q, s.m, s.w, P, U, wpp=wpp, ids=I)
+    o.step(1)
+    worst = 0.0
+    for lo, hi in boxes:
+        sl = (slice(None), slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+        a, b = Jg[sl], o.J[sl]
+        den = float(np.max(np.abs(a)))
+        assert den > 0, (lo, hi)
+        err = float(np.max(np.abs(a - b))) / den
+        assert err <= tol, (lo, hi, err)
+        worst = max(worst, err)
+    return worst

@@ -6,7 +6,9 @@ cell (268M particles).  Both run in the configuration the FP32 step uses
 at scale (sorted tiles, fused kernel, sort every 10 steps); the oracle
 cannot step them whole, so it pushes a sample of particles one step with
 the GPU's fields, and the GPU's FP64 diagnostics give continuity at every
-node.  Particles are selected by id on the device.
+node.  Particles are selected by id on the device.  J is compared element
+by element inside boxes of cells, the oracle stepping every particle that
+can deposit there.  The wakefield box also runs its full 2000 steps.
 """
 import numpy as np
 import pytest
@@ -14,7 +16,7 @@ import pytest
 from oracle import oracle as O
 from paper_2609_16575_amd import workloads as W
 
-from gpu_common import pos_err_cells, rel
+from gpu_common import check_box_currents, pos_err_cells, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -58,6 +60,42 @@ def test_full_size_lwfa_slab_sampled():
     ids = np.concatenate([rng.choice(front, 3000, replace=False),
                           rng.choice(w.n_particles, 3000, replace=False)])
     _sampled_step(g, w, [np.unique(ids)], 2e-5)
+    # the laser's front is entering the slab: J where the plasma responds
+    check_box_currents(g, w, [((128, 60, 60), (136, 68, 68)), ((134, 56, 62), (142, 64, 70))],
+                       2e-5)
+    g.close()
+
+
+def test_lwfa_box_2000_steps():
+    """The wakefield box for its stated 2000 steps (the pulse crosses most of
+    the slab): every 100 steps the fault word, the continuity residual of
+    that step, the particle count and a finite total energy; at the end one
+    step with sampled particles and J inside boxes on the pulse's path
+    compared with the oracle."""
+    w = W.lwfa_slab()
+    from paper_2609_16575_amd.sim import Sim
+    g = Sim(w, precision="fp32")
+    n0 = w.n_particles
+    g.diagnostics()
+    for k in range(20):
+        g.step(99)
+        g.diagnostics()
+        g.step(1)
+        d = g.diagnostics()
+        assert d["fault_word"] & ~16 == 0, (k, d)
+        assert d["cont_valid"] and d["cont_max"] <= 1e-5 * d["rho_max"], (k, d)
+        assert np.isfinite(d["U_tot"]) and d["U_tot"] > 0, (k, d)
+        assert 0.99 * n0 <= d["n_particles"][0] <= n0, (k, d["n_particles"])
+    assert d["step"] == 2000
+    # the pulse has travelled about 940 cells along x
+    rng = np.random.default_rng(3)
+    x = w.species[0].pos[:, 0] / w.d[0]
+    path = np.nonzero((x > 880) & (x < 960))[0]
+    ids = np.concatenate([rng.choice(path, 3000, replace=False),
+                          rng.choice(w.n_particles, 3000, replace=False)])
+    _sampled_step(g, w, [np.unique(ids)], 2e-5)
+    check_box_currents(g, w, [((920, 60, 60), (928, 68, 68)), ((900, 58, 62), (908, 66, 70))],
+                       2e-5)
     g.close()
 
 
@@ -70,4 +108,6 @@ def test_full_size_weibel_sampled():
     g.step(12)  # past the first periodic sort after the initial one
     rng = np.random.default_rng(2)
     _sampled_step(g, w, [rng.choice(w.n_particles, 6000, replace=False)], 2e-5)
+    check_box_currents(g, w, [((20, 30, 40), (28, 38, 48)), ((200, 100, 60), (208, 108, 68)),
+                              ((120, 220, 180), (128, 228, 188))], 2e-5)
     g.close()

@@ -6,11 +6,15 @@ few seconds on the GPU).  The paper gives no data to compare with element
 by element, so the checks are the features it reports: a nonlinear wake
 with a depleted first bucket behind the pulse and a density spike at its
 back, a peak accelerating field of the order of the cold wave-breaking
-field (the paper quotes about 0.169 TV/m, i.e. 1.01 m c omega_p / e; the
-band below admits it and this code's own value), and results that barely
-change with the number of particles per cell.  Parity of the same set-up
-with the oracle is tested in a reduced box (test_gpu_window).
+field, and results that barely change with the number of particles per
+cell.  The peak field is held to this code's own value, 1.44 m c omega_p / e
+at ppc 8 and 1.49 at ppc 2, within 10 %, so that a change in the result
+shows; the paper quotes about 0.169 TV/m, i.e. 1.01 m c omega_p / e, for a
+set-up whose injection, envelope and read-out time it leaves open.  Parity
+of the same set-up with the oracle is tested in a reduced box
+(test_gpu_window).
 """
+PEAK_E0 = {2: 1.49, 8: 1.44}   # this code's peak accelerating field, m c omega_p / e
 import numpy as np
 import pytest
 
@@ -41,7 +45,7 @@ def test_lwfa2d_full_size_wake():
     w = W.lwfa_2d(per=(1, 2, 1))
     lam = w.lambda_p
     for ppc, (out, prof) in res.items():
-        assert 0.6 <= out["peak_accel_field_E0"] <= 2.0, (ppc, out)
+        assert abs(out["peak_accel_field_E0"] / PEAK_E0[ppc] - 1.0) <= 0.1, (ppc, out)
         # the pulse sits in the front third; behind it the first bucket is
         # depleted on axis and ends in a density spike
         x_n = np.arange(prof["ne"].shape[0]) * w.d[0]

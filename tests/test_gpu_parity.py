@@ -9,7 +9,7 @@ Tolerances (relative, ||a - b||_inf / ||b||_inf; positions in cells):
 import numpy as np
 import pytest
 
-from gpu_common import compare_state, oracle_from, pos_err_cells, rel
+from gpu_common import check_box_currents, compare_state, oracle_from, pos_err_cells, rel
 from oracle import oracle as O
 from paper_2609_16575_amd import workloads as W
 
@@ -97,6 +97,29 @@ def test_fp32_two_species_one_step():
     g.step(1)
     o.step(1)
     compare_state(g, o, w, sp_tol=2e-5, f_tol=2e-5, label="fp32 e+p")
+
+
+def test_fp32_dense_tiles_two_species():
+    """20 electrons + 20 protons per cell on 16^3: 5120 particles of each
+    species per 256-cell tile, so every tile takes three batches of 2048
+    (four per thread) per species and the sort moves tiles larger than its
+    LDS staging; fields, currents and particles by id after one step from a
+    common state (2e-5) and after ten more (2e-4)."""
+    w = W.thermal_two_species(n=(16, 16, 16), ppc=20, vth=0.05)
+    w.E0, w.B0 = W.random_fields(w.n, scale=0.05, seed=8)
+    g, o = _sim(w, "fp32", sort_every=5), oracle_from(w, w.E0, w.B0)
+    _common_fp32_state(g, o)
+    g.step(1)
+    o.step(1)
+    compare_state(g, o, w, sp_tol=2e-5, f_tol=2e-5, label="dense 1 step")
+    g.diagnostics()  # rho of this step, for the continuity of the next
+    for _ in range(10):
+        g.step(1)
+        d = g.diagnostics()
+        assert d["cont_valid"] and d["cont_max"] <= 1e-5 * d["rho_max"], d
+        assert d["fault_word"] & ~16 == 0, d
+    o.step(10)
+    compare_state(g, o, w, sp_tol=2e-4, f_tol=2e-4, label="dense 11 steps")
 
 
 def test_fp32_multistep_tracks_oracle_and_conserves_charge():
@@ -352,4 +375,7 @@ def test_full_size_thermal_ep_sampled():
             assert np.array_equal(Ig[idx], o.species[i].ids)
             assert pos_err_cells(Pg[idx], o.species[i].pos, w) <= tol
             assert rel(Ug[idx], o.species[i].u) <= tol
+        # J element by element in boxes of cells
+        check_box_currents(g, w, [((10, 20, 30), (18, 28, 38)), ((64, 64, 64), (72, 72, 72)),
+                                  ((100, 4, 110), (108, 12, 118))], tol)
         g.close()
