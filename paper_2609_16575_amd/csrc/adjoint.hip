@@ -120,8 +120,8 @@ __device__ __forceinline__ void stagger(int q, const int l[3], const float o[3],
 // (cell units) of sum_edges lam . J_segment, with D = e - s, W = (s + e)/2 - cell.
 template <class Acc>
 __device__ __forceinline__ void segment_vjp(const Acc &a, const int cell[3], const float W[3],
-                                            const float D[3], const float ampc[3], float ls[3],
-                                            float le[3]) {
+                                            const float D[3], const float ampc[3],
+                                            const float ampc_lo[3], float ls[3], float le[3]) {
     float lD[3] = {0.f, 0.f, 0.f}, lW[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -132,7 +132,8 @@ __device__ __forceinline__ void segment_vjp(const Acc &a, const int cell[3], con
             int p[3] = {cell[0], cell[1], cell[2]};
             p[b1] += o1;
             p[b2] += o2;
-            const float lam = a.L(c, p[0], p[1], p[2]) * ampc[c];
+            const float Lc = a.L(c, p[0], p[1], p[2]);
+            const float lam = fmaf(Lc, ampc_lo[c], Lc * ampc[c]);
             const float w1 = o1 ? W[b1] : 1.f - W[b1];
             const float w2 = o2 ? W[b2] : 1.f - W[b2];
             const float sg = (o1 == o2) ? 1.f : -1.f;
@@ -159,9 +160,9 @@ struct AdjArgs {
     const float *lJ[3];  // adjoint of E^{n+1}; lam_J = -dt * lam_E'
     float *lEg[3];       // accumulated adjoint of E^n through the gather
     float *lBb[3];       // accumulated adjoint of Bbar
-    float dtd[3];
+    float dtd[3], dtd_lo[3];  // dt / d_a and dt as FP32 pairs (split_f32)
     float inv_d[3];
-    float dt;
+    float dt, dt_lo;
     int *fb_list;        // slots of this species' particles outside their tile window
     unsigned *fb_count;  // entries in fb_list
     long long fb_cap;
@@ -177,8 +178,8 @@ struct AdjSpecies {
     float *lx[3];
     float *lu[3];
     const int32_t *tile_off;   // the state's tile offsets
-    float r;                   // q dt / (2 m)
-    float qc[3];               // q w d_a / (dt dV)  (w = 1 when per-particle)
+    float r, r_lo;             // q dt / (2 m) as an FP32 pair
+    float qc[3], qc_lo[3];     // q w d_a / (dt dV) as FP32 pairs (w = 1 when per-particle)
 };
 
 // One particle's adjoint up to the gather scatter: returns lam_Ep, lam_Bp in
@@ -198,32 +199,32 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
         tri_vg(acc, q, c[0], c[1], c[2], f[0], f[1], f[2], F6[q], G6[q]);
     }
     // ---- Boris with the step kernel's operations, keeping intermediates ----
-    const float r = S.r;
+    const float r = S.r, r_lo = S.r_lo;
     float um[3], t[3], s[3], up[3], un[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) um[a] = fmaf(r, F6[a], u[a]);
-    const float igm = rsqf(fmaf(um[0], um[0], fmaf(um[1], um[1], fmaf(um[2], um[2], 1.f))));
+    for (int a = 0; a < 3; ++a) um[a] = fmaf(r_lo, F6[a], fmaf(r, F6[a], u[a]));
+    const float igm = rsq_nr(fmaf(um[0], um[0], fmaf(um[1], um[1], fmaf(um[2], um[2], 1.f))));
     const float rig = r * igm;
 #pragma unroll
     for (int a = 0; a < 3; ++a) t[a] = rig * F6[3 + a];
     const float den = fmaf(t[0], t[0], fmaf(t[1], t[1], fmaf(t[2], t[2], 1.f)));
-    const float iden = rcpf(den);
+    const float iden = rcp_nr(den);
     const float sf = 2.f * iden;
 #pragma unroll
     for (int a = 0; a < 3; ++a) s[a] = sf * t[a];
     up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
     up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
     up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
-    un[0] = fmaf(r, F6[0], um[0] + (up[1] * s[2] - up[2] * s[1]));
-    un[1] = fmaf(r, F6[1], um[1] + (up[2] * s[0] - up[0] * s[2]));
-    un[2] = fmaf(r, F6[2], um[2] + (up[0] * s[1] - up[1] * s[0]));
-    const float ign = rsqf(fmaf(un[0], un[0], fmaf(un[1], un[1], fmaf(un[2], un[2], 1.f))));
+    un[0] = fmaf(r_lo, F6[0], fmaf(r, F6[0], um[0] + (up[1] * s[2] - up[2] * s[1])));
+    un[1] = fmaf(r_lo, F6[1], fmaf(r, F6[1], um[1] + (up[2] * s[0] - up[0] * s[2])));
+    un[2] = fmaf(r_lo, F6[2], fmaf(r, F6[2], um[2] + (up[0] * s[1] - up[1] * s[0])));
+    const float ign = rsq_nr(fmaf(un[0], un[0], fmaf(un[1], un[1], fmaf(un[2], un[2], 1.f))));
     float dx[3], e[3];
     int dc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float no;
-        dx[a] = un[a] * ign * A.dtd[a];
+        dx[a] = move_cells(un[a] * ign, A.dtd[a], A.dtd_lo[a]);
         move_axis_sel(o[a], dx[a], e[a], dc[a], no);
     }
     // ---- deposit adjoint: lam_J = -dt lam_E' on the touched edges ----
@@ -231,7 +232,14 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
     // the mid-point on every axis, and the line integral over the two halves
     // equals the step kernel's single straight segment, so one code path
     // serves every lane of a wave.
-    const float ampc[3] = {S.qc[0] * wq, S.qc[1] * wq, S.qc[2] * wq};
+    // q w d_c / (dt dV) per particle as an FP32 pair: hi = the rounded
+    // product, lo = its rounding error (FMA) plus the low part of the constant
+    float ampc[3], ampc_lo[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        ampc[c] = S.qc[c] * wq;
+        ampc_lo[c] = fmaf(S.qc_lo[c], wq, fmaf(S.qc[c], wq, -ampc[c]));
+    }
     float l1[3], l2[3];
     {
         float WA[3], DA[3], WB[3], DB[3];
@@ -239,8 +247,8 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
         float lsB[3] = {0.f, 0.f, 0.f}, leB[3] = {0.f, 0.f, 0.f};
         zigzag_split(o, dx, e, dc, WA, DA, WB, DB);
         const int lb[3] = {l[0] + dc[0], l[1] + dc[1], l[2] + dc[2]};
-        segment_vjp(acc, l, WA, DA, ampc, lsA, leA);
-        segment_vjp(acc, lb, WB, DB, ampc, lsB, leB);
+        segment_vjp(acc, l, WA, DA, ampc, ampc_lo, lsA, leA);
+        segment_vjp(acc, lb, WB, DB, ampc, ampc_lo, lsB, leB);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             // relay point: the mid-point (derivative 1/2 in both ends) or a face
@@ -253,9 +261,12 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
     float lxn[3], lv[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float m1 = -A.dt * l1[a], m2 = -A.dt * l2[a];  // lam_J = -dt lam_E'
+        // lam_J = -dt lam_E'; dt as its FP32 pair
+        const float m1 = -fmaf(A.dt_lo, l1[a], A.dt * l1[a]);
+        const float m2 = -fmaf(A.dt_lo, l2[a], A.dt * l2[a]);
         lxn[a] = lx[a] + (m1 + m2) * A.inv_d[a];
-        lv[a] = A.dt * (lx[a] + m2 * A.inv_d[a]);
+        const float xv = lx[a] + m2 * A.inv_d[a];
+        lv[a] = fmaf(A.dt_lo, xv, A.dt * xv);
     }
     const float uv = un[0] * lv[0] + un[1] * lv[1] + un[2] * lv[2];
     const float ign3 = ign * ign * ign;
@@ -266,7 +277,7 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
     float lE[3], lB[3], lum[3], lup[3], ls[3], lt[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        lE[a] = r * lupl[a];
+        lE[a] = fmaf(r_lo, lupl[a], r * lupl[a]);
         lum[a] = lupl[a];
     }
     lup[0] = s[1] * lupl[2] - s[2] * lupl[1];
@@ -294,7 +305,7 @@ __device__ __forceinline__ void particle_vjp(const Acc &acc, const AdjArgs &A, c
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         lum[a] += lgm * um[a] * igm;
-        lE[a] += r * lum[a];
+        lE[a] = fmaf(r_lo, lum[a], fmaf(r, lum[a], lE[a]));
     }
     // ---- gather adjoint: derivative in x (the scatter is the caller's) ----
 #pragma unroll
@@ -673,13 +684,13 @@ __global__ void k_adj_bprime(GridP g, const float *lEx, const float *lEy, const 
     float *lB[3] = {lBx, lBy, lBz};
     const float *lb[3] = {lbx, lby, lbz};
     float *tB[3] = {tx, ty, tz};
-    const float dt = (float)g.dt;
+    const float dt = (float)g.dt, dt_lo = (float)(g.dt - (double)dt);  // an FP32 pair
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
         const float curl = (lE[a2][nb(g, i, j, k, a1, 1)] - lE[a2][p]) * (float)g.inv_d[a1] -
                            (lE[a1][nb(g, i, j, k, a2, 1)] - lE[a1][p]) * (float)g.inv_d[a2];
-        const float t = lB[c][p] + dt * curl + 0.5f * lb[c][p];
+        const float t = lB[c][p] + dt * curl + dt_lo * curl + 0.5f * lb[c][p];
         tB[c][p] = t;
         lB[c][p] = t + 0.5f * lb[c][p];
     }
@@ -695,13 +706,13 @@ __global__ void k_adj_e(GridP g, float *lEx, float *lEy, float *lEz, const float
     float *lE[3] = {lEx, lEy, lEz};
     const float *ge[3] = {gx, gy, gz};
     const float *tB[3] = {tx, ty, tz};
-    const float dt = (float)g.dt;
+    const float dt = (float)g.dt, dt_lo = (float)(g.dt - (double)dt);  // an FP32 pair
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
         const float curl = (tB[a2][p] - tB[a2][nb(g, i, j, k, a1, -1)]) * (float)g.inv_d[a1] -
                            (tB[a1][p] - tB[a1][nb(g, i, j, k, a2, -1)]) * (float)g.inv_d[a2];
-        lE[c][p] = lE[c][p] + ge[c][p] - dt * curl;
+        lE[c][p] = lE[c][p] + ge[c][p] - dt * curl - dt_lo * curl;
     }
 }
 
@@ -759,10 +770,10 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
         A.lJ[a] = lJdep[a];
         A.lEg[a] = lEg[a];
         A.lBb[a] = lBb[a];
-        A.dtd[a] = (float)(g.dt / g.d[a]);
+        split_f32(g.dt / g.d[a], A.dtd[a], A.dtd_lo[a]);
         A.inv_d[a] = (float)(1.0 / g.d[a]);
     }
-    A.dt = (float)g.dt;
+    split_f32(g.dt, A.dt, A.dt_lo);
     A.fb_list = fb_list;
     A.fb_count = fb_count;
     A.tile_exp = tile_exp;
@@ -781,9 +792,9 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
         }
         S.w = (sp[i].per_particle_w && sp[i].w) ? (const float *)sp[i].w : nullptr;
         S.tile_off = tile_off[i];
-        S.r = (float)(sp[i].q * g.dt / (2.0 * sp[i].m));
+        split_f32(sp[i].q * g.dt / (2.0 * sp[i].m), S.r, S.r_lo);
         const double w = sp[i].per_particle_w ? 1.0 : sp[i].w_species;
-        for (int a = 0; a < 3; ++a) S.qc[a] = (float)(sp[i].q * w * g.d[a] / (g.dt * dV));
+        for (int a = 0; a < 3; ++a) split_f32(sp[i].q * w * g.d[a] / (g.dt * dV), S.qc[a], S.qc_lo[a]);
         A.fb_cap = fb_cap < sp[i].capacity ? fb_cap : sp[i].capacity;
         for (int q = 0; q < 6; ++q) A.l6[q] = l6[i][q];
         launch_fill_i32((int32_t *)fb_count, 1, 0, s);

@@ -650,10 +650,7 @@ empic_status empic_add_species(empic_sim *s, const empic_species_desc *desc, int
     DevSpecies D;
     D.p[0] = species_params(s, id, 0);
     D.p[1] = species_params(s, id, S.has_alt ? 1 : 0);
-    D.r = (float)(desc->q * s->g.dt / (2.0 * desc->m));
-    const double dV = s->g.d[0] * s->g.d[1] * s->g.d[2];
-    const double wsp = desc->per_particle_w ? 1.0 : desc->w;
-    for (int a = 0; a < 3; ++a) D.qc[a] = (float)(desc->q * wsp * s->g.d[a] / (s->g.dt * dV));
+    fill_species_consts(D, s->g, desc->q, desc->m, desc->per_particle_w ? 1.0 : desc->w);
     launch_write_species(s->table + id, D, s->stream);
     if (species_id_out) *species_id_out = id;
     s->need_sort = true;
@@ -1222,10 +1219,7 @@ empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_
             p.count = st[k]->tiles[i] ? st[k]->tiles[i] + s->ti.ntiles + 1 : nullptr;
             D.p[k] = p;
         }
-        D.r = (float)(S.desc.q * s->g.dt / (2.0 * S.desc.m));
-        const double dV = s->g.d[0] * s->g.d[1] * s->g.d[2];
-        const double wsp = S.desc.per_particle_w ? 1.0 : S.desc.w;
-        for (int a = 0; a < 3; ++a) D.qc[a] = (float)(S.desc.q * wsp * s->g.d[a] / (s->g.dt * dV));
+        fill_species_consts(D, s->g, S.desc.q, S.desc.m, S.desc.per_particle_w ? 1.0 : S.desc.w);
         launch_write_species(s->xtable + i, D, s->stream);
         if (S.capacity == 0) continue;
         const size_t pb = (size_t)S.capacity * 4;

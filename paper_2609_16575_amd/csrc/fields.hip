@@ -76,12 +76,14 @@ __global__ void k_faraday(GridP g, const T *__restrict__ Ex, const T *__restrict
         Jy[p] = T(0);
         Jz[p] = T(0);
     }
-    const T dt = (T)g.dt;
+    // dt as a pair of T (the low part is zero in FP64): no systematic error
+    // from its rounding in the FP32 updates
+    const T dt = (T)g.dt, dt_lo = (T)(g.dt - (double)dt);
     const T ix = (T)g.inv_d[0], iy = (T)g.inv_d[1], iz = (T)g.inv_d[2];
     // B^{n+1/2} = B^{n-1/2} - dt curl E^n (forward differences); Bbar = average
     if (valid_B(g, q, 0)) {
         const T curl = (Ez[p + up(g, q, 1)] - Ez[p]) * iy - (Ey[p + up(g, q, 2)] - Ey[p]) * iz;
-        const T old = Bx[p], nw = old - dt * curl;
+        const T old = Bx[p], nw = old - dt * curl - dt_lo * curl;
         if (write_B) Bx[p] = nw;
         Bbx[p] = T(0.5) * (old + nw);
     } else {
@@ -89,7 +91,7 @@ __global__ void k_faraday(GridP g, const T *__restrict__ Ex, const T *__restrict
     }
     if (valid_B(g, q, 1)) {
         const T curl = (Ex[p + up(g, q, 2)] - Ex[p]) * iz - (Ez[p + up(g, q, 0)] - Ez[p]) * ix;
-        const T old = By[p], nw = old - dt * curl;
+        const T old = By[p], nw = old - dt * curl - dt_lo * curl;
         if (write_B) By[p] = nw;
         Bby[p] = T(0.5) * (old + nw);
     } else {
@@ -97,7 +99,7 @@ __global__ void k_faraday(GridP g, const T *__restrict__ Ex, const T *__restrict
     }
     if (valid_B(g, q, 2)) {
         const T curl = (Ey[p + up(g, q, 0)] - Ey[p]) * ix - (Ex[p + up(g, q, 1)] - Ex[p]) * iy;
-        const T old = Bz[p], nw = old - dt * curl;
+        const T old = Bz[p], nw = old - dt * curl - dt_lo * curl;
         if (write_B) Bz[p] = nw;
         Bbz[p] = T(0.5) * (old + nw);
     } else {
@@ -113,20 +115,23 @@ __global__ void k_ampere(GridP g, T *__restrict__ Ex, T *__restrict__ Ey, T *__r
     Pt q;
     if (!make_point(g, q)) return;
     const long long p = q.p;
-    const T dt = (T)g.dt;
+    const T dt = (T)g.dt, dt_lo = (T)(g.dt - (double)dt);  // see k_faraday
     const T ix = (T)g.inv_d[0], iy = (T)g.inv_d[1], iz = (T)g.inv_d[2];
     // E^{n+1} = E^n + dt curl B^{n+1/2} - dt J^{n+1/2} (backward differences)
     if (ampere_E(g, q, 0)) {
         const T curl = (Bz[p] - Bz[p + dn(g, q, 1)]) * iy - (By[p] - By[p + dn(g, q, 2)]) * iz;
-        Ex[p] = Ex[p] + (dt * curl - dt * Jx[p]);
+        const T x = curl - Jx[p];
+        Ex[p] = Ex[p] + dt * x + dt_lo * x;
     }
     if (ampere_E(g, q, 1)) {
         const T curl = (Bx[p] - Bx[p + dn(g, q, 2)]) * iz - (Bz[p] - Bz[p + dn(g, q, 0)]) * ix;
-        Ey[p] = Ey[p] + (dt * curl - dt * Jy[p]);
+        const T x = curl - Jy[p];
+        Ey[p] = Ey[p] + dt * x + dt_lo * x;
     }
     if (ampere_E(g, q, 2)) {
         const T curl = (By[p] - By[p + dn(g, q, 0)]) * ix - (Bx[p] - Bx[p + dn(g, q, 1)]) * iy;
-        Ez[p] = Ez[p] + (dt * curl - dt * Jz[p]);
+        const T x = curl - Jz[p];
+        Ez[p] = Ez[p] + dt * x + dt_lo * x;
     }
 }
 

@@ -61,6 +61,18 @@ using TileCube = TileT<8, 8, 4, 512>;
 // leaves no room for a crossing queue.
 using TileSlab = TileT<16, 2, 8, 0>;
 
+// A constant c of the FP32 path as the pair (hi, lo) of FP32 numbers with
+// hi = c rounded and lo = c - hi rounded.  Products c x are formed as
+// fma(lo, x, hi x) (or added in two FMAs), so that the rounding of c itself
+// leaves no systematic relative error of up to 2^-24 in every step: such an
+// error would shift the frequencies of the discrete system (for instance the
+// plasma frequency through q dt / m, q w / (dt dV), dt / d and dt) and its
+// phase would grow with the number of steps.
+__host__ inline void split_f32(double c, float &hi, float &lo) {
+    hi = (float)c;
+    lo = (float)(c - (double)hi);
+}
+
 // Packed cell index of the FP32 path: i | j << 11 | k << 22; all ones = removed.
 constexpr uint32_t DEAD = 0xFFFFFFFFu;
 __host__ __device__ inline uint32_t pack_cell(int i, int j, int k) {
@@ -104,9 +116,11 @@ struct SpeciesP {
 // with a bit of `cur_mask` (kernel arguments are never indexed dynamically).
 struct DevSpecies {
     SpeciesP p[2];
-    float r;      // q dt / (2 m)
-    float qc[3];  // q w d_a / (dt dV)  (w = 1 when per-particle)
+    float r, r_lo;  // q dt / (2 m) as an FP32 pair (split_f32)
+    float qc[3];    // q w d_a / (dt dV)  (w = 1 when per-particle), rounded
+    double qcd[3];  // the same in FP64: the current window's fixed-point multipliers
 };
+void fill_species_consts(DevSpecies &D, const GridP &g, double q, double m, double w);
 void launch_write_species(DevSpecies *dst, const DevSpecies &v, hipStream_t s);
 
 constexpr int NQ = 16;       // reduction slots

@@ -18,6 +18,18 @@ __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x)
 // square root and a reciprocal)
 __device__ __forceinline__ float rsqf(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
+// 1/x and 1/sqrt(x) to about half an ulp: the hardware approximation and one
+// Newton step (the approximations alone can err by an ulp in the same
+// direction over a range of arguments, a systematic error of the velocity
+// that would accumulate over many steps)
+__device__ __forceinline__ float rcp_nr(float x) {
+    const float y = rcpf(x);
+    return fmaf(y, fmaf(-x, y, 1.f), y);
+}
+__device__ __forceinline__ float rsq_nr(float x) {
+    const float y = rsqf(x);
+    return fmaf(0.5f * y, fmaf(-x * y, y, 1.f), y);
+}
 
 // global index of cell-axis coordinate x on axis a: periodic wrap (any x),
 // -1 outside an absorbing axis' array
@@ -71,14 +83,18 @@ __device__ inline void gather_global(const GridP &g, const float *const E[3], co
     Bp[2] = tri_global(g, Bb[2], hx, hy, ck, fx, fy, oz);
 }
 
-// relativistic Boris push in FP32 (standard t/s rotation); returns 1/gamma of u+
+// relativistic Boris push in FP32 (standard t/s rotation); returns 1/gamma of u+.
+// r = q dt / (2 m) as the FP32 pair (r, r_lo): the electric half kicks add
+// both parts (no systematic error from the rounding of r); the rotation uses r.
 __device__ __forceinline__ float boris_f32(float &ux, float &uy, float &uz, const float E[3],
-                                           const float B[3], float r, float &gam) {
-    const float umx = fmaf(r, E[0], ux), umy = fmaf(r, E[1], uy), umz = fmaf(r, E[2], uz);
-    const float ig = rsqf(fmaf(umx, umx, fmaf(umy, umy, fmaf(umz, umz, 1.f))));  // 1/gamma-
+                                           const float B[3], float r, float r_lo, float &gam) {
+    const float umx = fmaf(r_lo, E[0], fmaf(r, E[0], ux));
+    const float umy = fmaf(r_lo, E[1], fmaf(r, E[1], uy));
+    const float umz = fmaf(r_lo, E[2], fmaf(r, E[2], uz));
+    const float ig = rsq_nr(fmaf(umx, umx, fmaf(umy, umy, fmaf(umz, umz, 1.f))));  // 1/gamma-
     const float rig = r * ig;
     const float tx = rig * B[0], ty = rig * B[1], tz = rig * B[2];
-    const float sf = 2.f * rcpf(fmaf(tx, tx, fmaf(ty, ty, fmaf(tz, tz, 1.f))));
+    const float sf = 2.f * rcp_nr(fmaf(tx, tx, fmaf(ty, ty, fmaf(tz, tz, 1.f))));
     const float sx = sf * tx, sy = sf * ty, sz = sf * tz;
     const float upx = umx + (umy * tz - umz * ty);
     const float upy = umy + (umz * tx - umx * tz);
@@ -86,11 +102,11 @@ __device__ __forceinline__ float boris_f32(float &ux, float &uy, float &uz, cons
     const float plx = umx + (upy * sz - upz * sy);
     const float ply = umy + (upz * sx - upx * sz);
     const float plz = umz + (upx * sy - upy * sx);
-    ux = fmaf(r, E[0], plx);
-    uy = fmaf(r, E[1], ply);
-    uz = fmaf(r, E[2], plz);
+    ux = fmaf(r_lo, E[0], fmaf(r, E[0], plx));
+    uy = fmaf(r_lo, E[1], fmaf(r, E[1], ply));
+    uz = fmaf(r_lo, E[2], fmaf(r, E[2], plz));
     const float g2 = fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.f)));
-    const float igp = rsqf(g2);
+    const float igp = rsq_nr(g2);
     gam = g2 * igp;
     return igp;
 }
@@ -206,6 +222,12 @@ __device__ __forceinline__ int edge_off(int q) {
     if (c == 0) return JW3 * 0 + o1 * JWX + o2 * JWX * JWY;
     if (c == 1) return JW3 * 1 + o1 * JWX * JWY + o2;
     return JW3 * 2 + o1 + o2 * JWX;
+}
+
+// Displacement in cells of a particle with velocity v along an axis with
+// dt / d = (dtd, dtd_lo) (an FP32 pair, see split_f32)
+__device__ __forceinline__ float move_cells(float v, float dtd, float dtd_lo) {
+    return fmaf(v, dtd_lo, v * dtd);
 }
 
 // Float -> int64 fixed point, round to nearest: the sum with 1.5 * 2^52 puts

@@ -46,7 +46,7 @@ struct FusedArgs {
     int nsp;
     unsigned cur_mask;      // bit s: buffer set species s is read from
     unsigned wr_mask;       // bit s: buffer set species s is written to (the same for a step in place)
-    float dtd[3];           // dt / d_a
+    float dtd[3], dtd_lo[3];  // dt / d_a as FP32 pairs (split_f32)
     double jscale, jinv;    // fixed-point scale of the LDS current window and its inverse
     uint32_t *fault;
     unsigned long long *fallback;  // cumulative count of out-of-window particles
@@ -87,7 +87,7 @@ __device__ void particle_global(const FusedArgs &A, const DevSpecies &D, uint32_
     float Ep[3], Bp[3];
     gather_global(g, A.E, A.Bb, ci, cj, ck, ox, oy, oz, Ep, Bp);
     float gam;
-    const float ig = boris_f32(ux, uy, uz, Ep, Bp, D.r, gam);
+    const float ig = boris_f32(ux, uy, uz, Ep, Bp, D.r, D.r_lo, gam);
     if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
     const float o[3] = {ox, oy, oz};
     const float uu[3] = {ux, uy, uz};
@@ -95,7 +95,7 @@ __device__ void particle_global(const FusedArgs &A, const DevSpecies &D, uint32_
     int dc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        dx[a] = uu[a] * ig * A.dtd[a];
+        dx[a] = move_cells(uu[a] * ig, A.dtd[a], A.dtd_lo[a]);
         if (!(fabsf(dx[a]) < 1.f)) fbits |= EMPIC_FAULT_FAST;
         move_axis(o[a], dx[a], e[a], dc[a], no[a]);
     }
@@ -125,13 +125,19 @@ __device__ void particle_global(const FusedArgs &A, const DevSpecies &D, uint32_
 
 // The LDS current window accumulates int64 fixed point: integer LDS atomics
 // are an order of magnitude faster than float ones on this LDS, and the tile's
-// sums become exact and independent of the order of the adds.
+// sums become exact and independent of the order of the adds.  The segment's
+// edge weights are formed in FP32 with the particle's weight wq alone; the
+// charge factor q w d_c / (dt dV) enters in FP64 with the window's scale,
+// mult[c], in the conversion to fixed point.
 template <class TL>
-__device__ __forceinline__ void lds_add12(unsigned long long *sJ, int base, const float v[12],
-                                          double scale) {
+__device__ __forceinline__ void lds_add_segment(unsigned long long *sJ, int base, const float W[3],
+                                                const float D[3], float wq, const double mult[3]) {
+    const float amp[3] = {wq, wq, wq};
+    float v[12];
+    segment_weights(W, D, amp, v);
 #pragma unroll
     for (int q = 0; q < 12; ++q)
-        atomicAdd(sJ + base + edge_off<TL>(q), (unsigned long long)to_fixed(v[q], scale));
+        atomicAdd(sJ + base + edge_off<TL>(q), (unsigned long long)to_fixed(v[q], mult[q >> 2]));
 }
 
 typedef float __attribute__((address_space(1))) gfloat;
@@ -227,9 +233,8 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
     constexpr int FW3 = TL::FW3, FWX = TL::FWX, FWY = TL::FWY, JWX = TL::JWX, JWY = TL::JWY;
     constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
     const GridP &g = A.g;
-    const float r = D.r;
-    const float qcx = D.qc[0], qcy = D.qc[1], qcz = D.qc[2];
-    const float dtd0 = A.dtd[0], dtd1 = A.dtd[1], dtd2 = A.dtd[2];
+    const float r = D.r, r_lo = D.r_lo;
+    const double mult[3] = {A.jscale * D.qcd[0], A.jscale * D.qcd[1], A.jscale * D.qcd[2]};
     guint *CQ = (guint *)Wr.cell;
     gfloat *OXQ = (gfloat *)Wr.pos[0], *OYQ = (gfloat *)Wr.pos[1], *OZQ = (gfloat *)Wr.pos[2];
     gfloat *UXQ = (gfloat *)Wr.u[0], *UYQ = (gfloat *)Wr.u[1], *UZQ = (gfloat *)Wr.u[2];
@@ -306,10 +311,12 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
             Bp[1] = tri_lds_at<TL>(sFc[4] + (xh + yl + zh), fx, oy, fz);
             Bp[2] = tri_lds_at<TL>(sFc[5] + (xh + yh + zl), fx, fy, oz);
             float ux = b.ux[k], uy = b.uy[k], uz = b.uz[k], gam;
-            const float ig = boris_f32(ux, uy, uz, Ep, Bp, r, gam);
+            const float ig = boris_f32(ux, uy, uz, Ep, Bp, r, r_lo, gam);
             if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
             const float o[3] = {ox, oy, oz};
-            const float dx[3] = {ux * ig * dtd0, uy * ig * dtd1, uz * ig * dtd2};
+            const float dx[3] = {move_cells(ux * ig, A.dtd[0], A.dtd_lo[0]),
+                                 move_cells(uy * ig, A.dtd[1], A.dtd_lo[1]),
+                                 move_cells(uz * ig, A.dtd[2], A.dtd_lo[2])};
             if (!(fmaxf(fmaxf(fabsf(dx[0]), fabsf(dx[1])), fabsf(dx[2])) < 1.f))
                 fbits |= EMPIC_FAULT_FAST;
             float e[3], no[3];
@@ -317,7 +324,7 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
 #pragma unroll
             for (int a = 0; a < 3; ++a) move_axis_sel(o[a], dx[a], e[a], dc[a], no[a]);
             const float wq = b.w[k];
-            const float amp[3] = {qcx * wq, qcy * wq, qcz * wq};
+
             const int jb = lx + JWX * (ly + JWY * lz);
             const bool cross = (dc[0] | dc[1] | dc[2]) != 0;
             // first segment: the whole move inside the cell, or from the start
@@ -330,9 +337,7 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
                 DA[a] = dc[a] != 0 ? xr - o[a] : half * dx[a];
                 WA[a] = fmaf(0.5f, DA[a], o[a]);
             }
-            float v[12];
-            segment_weights(WA, DA, amp, v);
-            lds_add12<TL>(sJ, jb, v, A.jscale);
+            lds_add_segment<TL>(sJ, jb, WA, DA, wq, mult);
             // second segment of the crossing particles: from the relay point
             // to the end, in the cell + dc; queued as the move itself (the
             // segment is worked out when the queue is deposited)
@@ -359,8 +364,8 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
                 if (now) {
                     float WB[3], DB[3];
                     second_segment(o, dx, dc, WB, DB);
-                    segment_weights(WB, DB, amp, v);
-                    lds_add12<TL>(sJ, jb + dc[0] + JWX * (dc[1] + JWY * dc[2]), v, A.jscale);
+                    lds_add_segment<TL>(sJ, jb + dc[0] + JWX * (dc[1] + JWY * dc[2]), WB, DB, wq,
+                                        mult);
                 }
             }
             if constexpr (INTERIOR) {
@@ -552,14 +557,13 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
             const uint32_t code = __float_as_uint(a.w);
             const int dc[3] = {(int)((code >> 11) & 3u) - 1, (int)((code >> 13) & 3u) - 1,
                                (int)((code >> 15) & 3u) - 1};
-            const float *qc = A.tbl[code >> 17].qc;
-            const float amp[3] = {qc[0] * bq.w, qc[1] * bq.w, qc[2] * bq.w};
+            const double *qcd = A.tbl[code >> 17].qcd;
+            const double mult[3] = {A.jscale * qcd[0], A.jscale * qcd[1], A.jscale * qcd[2]};
             const float o[3] = {a.x, a.y, a.z}, dx[3] = {bq.x, bq.y, bq.z};
-            float WB[3], DB[3], v[12];
+            float WB[3], DB[3];
             second_segment(o, dx, dc, WB, DB);
-            segment_weights(WB, DB, amp, v);
-            lds_add12<TL>(sJ, (int)(code & 0x7FFu) + dc[0] + JWX * (dc[1] + JWY * dc[2]), v,
-                          A.jscale);
+            lds_add_segment<TL>(sJ, (int)(code & 0x7FFu) + dc[0] + JWX * (dc[1] + JWY * dc[2]),
+                                WB, DB, bq.w, mult);
         }
         __syncthreads();
     }
@@ -643,7 +647,7 @@ __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
 // ---------------------------------------------------------------------------
 __global__ void k_dry_push_f32(GridP g, const float *Ex, const float *Ey, const float *Ez,
                                const float *Bx, const float *By, const float *Bz, SpeciesP sp,
-                               float r, double *partial, uint32_t *fault) {
+                               float r, float r_lo, double *partial, uint32_t *fault) {
     __shared__ double sm[16];
     const float *E[3] = {Ex, Ey, Ez};
     const float *Bb[3] = {Bx, By, Bz};
@@ -661,7 +665,7 @@ __global__ void k_dry_push_f32(GridP g, const float *Ex, const float *Ey, const 
         float Ep[3], Bp[3];
         gather_global(g, E, Bb, cell_i(c), cell_j(c), cell_k(c), ox, oy, oz, Ep, Bp);
         float gam;
-        boris_f32(ux, uy, uz, Ep, Bp, r, gam);
+        boris_f32(ux, uy, uz, Ep, Bp, r, r_lo, gam);
         if (!isfinite(gam)) atomicOr(fault, (uint32_t)EMPIC_FAULT_NONFINITE);
         const double uu = (double)ux * ux + (double)uy * uy + (double)uz * uz;
         const double wp = WP ? (double)WP[p] : sp.w_species;
@@ -1224,6 +1228,15 @@ void launch_inject(const SpeciesP &sp, const int lo[3], const int nc[3], const i
                        nc[0], nc[1], nc[2], per[0], per[1], per[2], w, next_id, reserve);
 }
 
+void fill_species_consts(DevSpecies &D, const GridP &g, double q, double m, double w) {
+    split_f32(q * g.dt / (2.0 * m), D.r, D.r_lo);
+    const double dV = g.d[0] * g.d[1] * g.d[2];
+    for (int a = 0; a < 3; ++a) {
+        D.qcd[a] = q * w * g.d[a] / (g.dt * dV);
+        D.qc[a] = (float)D.qcd[a];
+    }
+}
+
 void launch_write_species(DevSpecies *dst, const DevSpecies &v, hipStream_t s) {
     hipLaunchKernelGGL(k_write_species, dim3(1), dim3(1), 0, s, dst, v);
 }
@@ -1253,7 +1266,7 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
         A.E[a] = E[a];
         A.Bb[a] = Bbar[a];
         A.J[a] = J[a];
-        A.dtd[a] = (float)(g.dt / g.d[a]);
+        split_f32(g.dt / g.d[a], A.dtd[a], A.dtd_lo[a]);
     }
     A.tbl = tbl;
     A.nsp = nsp;
@@ -1279,9 +1292,10 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
 void launch_dry_push_f32(const GridP &g, float *const E[3], float *const Bbar[3],
                          const SpeciesP &sp, double *partial_slot, uint32_t *fault,
                          hipStream_t s) {
-    const float r = (float)(sp.q * g.dt / (2.0 * sp.m));
+    float r, r_lo;
+    split_f32(sp.q * g.dt / (2.0 * sp.m), r, r_lo);
     hipLaunchKernelGGL(k_dry_push_f32, dim3(RED_BLOCKS), dim3(256), 0, s, g, E[0], E[1], E[2],
-                       Bbar[0], Bbar[1], Bbar[2], sp, r, partial_slot, fault);
+                       Bbar[0], Bbar[1], Bbar[2], sp, r, r_lo, partial_slot, fault);
 }
 
 void launch_kinetic_f32(const SpeciesP &sp, double *partial_slot, hipStream_t s) {

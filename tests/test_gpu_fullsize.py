@@ -69,14 +69,19 @@ def test_full_size_lwfa_slab_sampled():
 def test_lwfa_box_2000_steps():
     """The wakefield box for its stated 2000 steps (the pulse crosses most of
     the slab): every 100 steps the fault word, the continuity residual of
-    that step, the particle count and a finite total energy; at the end one
-    step with sampled particles and J inside boxes on the pulse's path
-    compared with the oracle."""
+    that step, a finite total energy and a particle count that never grows;
+    at the end, where the lost particles started, then one step with sampled
+    particles and J inside boxes on the pulse's path compared with the
+    oracle.  Particles leave through the absorbing walls: the pulse is
+    polarised along y and its field at the y walls (about 0.08 of the peak,
+    a quiver of most of a cell) carries the electrons of the layer next to
+    those walls out of the box behind the pulse (1.0% of them by step 1800)."""
     w = W.lwfa_slab()
     from paper_2609_16575_amd.sim import Sim
     g = Sim(w, precision="fp32")
     n0 = w.n_particles
     g.diagnostics()
+    prev = n0
     for k in range(20):
         g.step(99)
         g.diagnostics()
@@ -85,8 +90,15 @@ def test_lwfa_box_2000_steps():
         assert d["fault_word"] & ~16 == 0, (k, d)
         assert d["cont_valid"] and d["cont_max"] <= 1e-5 * d["rho_max"], (k, d)
         assert np.isfinite(d["U_tot"]) and d["U_tot"] > 0, (k, d)
-        assert 0.99 * n0 <= d["n_particles"][0] <= n0, (k, d["n_particles"])
+        assert 0.97 * n0 <= d["n_particles"][0] <= prev, (k, d["n_particles"], prev)
+        prev = d["n_particles"][0]
     assert d["step"] == 2000
+    _, _, ids = g.particles(0)
+    lost = np.setdiff1d(np.arange(n0), ids)
+    assert len(lost) == n0 - prev
+    y0 = w.species[0].pos[lost, 1] / w.d[1]
+    near = (y0 < 16) | (y0 > w.n[1] - 16)
+    assert np.mean(near) >= 0.99, (len(lost), int(np.sum(~near)))
     # the pulse has travelled about 940 cells along x
     rng = np.random.default_rng(3)
     x = w.species[0].pos[:, 0] / w.d[0]
