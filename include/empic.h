@@ -179,6 +179,9 @@ typedef struct {
     double cont_max, rho_max;
     int32_t cont_valid;
     uint32_t fault_word;
+    /* storage slots in use: the live particles and, on the FP32 path, those
+     * removed (through an absorbing wall or behind the window) since the last
+     * sort, which drops them */
     int64_t n_particles[EMPIC_MAX_SPECIES];
     int64_t fallback_particles; /* cumulative count of out-of-window particles */
 } empic_diag;
