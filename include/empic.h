@@ -199,6 +199,30 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
                           void *hip_stream, void *workspace, size_t workspace_bytes,
                           empic_sim **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): empic_create with
+ * the library's own static workspace in place of a caller's.  The workspace
+ * is a device array of EMPIC_STATIC_SCRATCH_BYTES that every GPU the library
+ * runs on holds until the process ends; it serves one live handle per device
+ * at a time.  The handle itself sits in static host storage.  The call
+ * allocates nothing (no hipMalloc, hipHostMalloc or heap); the caller still
+ * owns and passes the fields and particle buffers.
+ *   - Grid and sizes as empic_create; EMPIC_E_CAPACITY when
+ *     empic_workspace_bytes(g, max_species, max_capacity) exceeds
+ *     EMPIC_STATIC_SCRATCH_BYTES.
+ *   - EMPIC_E_ARG when a handle of this call still lives on the current
+ *     device (empic_destroy releases it), or when hip_stream belongs to
+ *     another device than the current one.
+ *   - EMPIC_E_UNSUPPORTED for the adaptive sort (sort_every = -1 on the FP32
+ *     path), which needs pinned host memory; give a fixed cadence.
+ *   - The handle uses the current device's array; the array keeps what the
+ *     previous handle left in it, and the call clears what the kernels need
+ *     zero, as empic_create does.  Calls on the handle from several threads
+ *     at once race on the array (as on any handle). */
+#define EMPIC_STATIC_SCRATCH_BYTES (64u << 20)
+empic_status empic_create_static(const empic_grid_desc *g, int32_t max_species,
+                                 int64_t max_capacity, void *hip_stream, empic_sim **out);
+
 /* Bind the six field arrays and the current density, each ext0*ext1*ext2
  * elements of float (FP32_CELLREL) or double (FP64_PLAIN).  E = E^n,
  * B = B^{n-1/2}; J is written by every step (J^{n+1/2} of the last step). */

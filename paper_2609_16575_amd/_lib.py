@@ -17,6 +17,8 @@ FP32_CELLREL, FP64_PLAIN = 0, 1
 
 STATUS = {0: "EMPIC_OK", 1: "EMPIC_E_ARG", 2: "EMPIC_E_STATE", 3: "EMPIC_E_HIP", 4: "EMPIC_E_CFL",
           5: "EMPIC_E_CAPACITY", 6: "EMPIC_E_NONFINITE", 7: "EMPIC_E_UNSUPPORTED"}
+OK, E_ARG, E_STATE, E_HIP, E_CFL, E_CAPACITY, E_NONFINITE, E_UNSUPPORTED = range(8)
+STATIC_SCRATCH_BYTES = 64 << 20  # EMPIC_STATIC_SCRATCH_BYTES
 FAULT_NONFINITE, FAULT_FAST, FAULT_OFFSET, FAULT_CELL, FAULT_FALLBACK = 1, 2, 4, 8, 16
 
 
@@ -86,6 +88,8 @@ SIGNATURES = {
     "empic_workspace_bytes": (C.c_size_t, [C.POINTER(GridDesc), C.c_int32, C.c_int64]),
     "empic_create": (C.c_int, [C.POINTER(GridDesc), C.c_int32, C.c_int64, _P, _P, C.c_size_t,
                                C.POINTER(_P)]),
+    "empic_create_static": (C.c_int, [C.POINTER(GridDesc), C.c_int32, C.c_int64, _P,
+                                      C.POINTER(_P)]),
     "empic_bind_fields": (C.c_int, [_P, _P * 3, _P * 3, _P * 3]),
     "empic_add_species": (C.c_int, [_P, C.POINTER(SpeciesDesc), C.c_int64,
                                     C.POINTER(ParticleBuffers), C.POINTER(ParticleBuffers),

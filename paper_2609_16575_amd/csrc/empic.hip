@@ -9,12 +9,20 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
 #include "internal.hpp"
 
 using namespace empic;
+
+// The workspace of empic_create_static: each GPU the library runs on holds
+// its own copy until the process ends.  In host code the name is a host-side
+// stand-in, never passed to a kernel or a copy: the device address comes from
+// hipGetSymbolAddress, once per device, and is kept per device.
+static __device__ __align__(256) unsigned char scratch[EMPIC_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -182,6 +190,7 @@ struct empic_sim {
     std::vector<TimedEvent> events;
     double t_ms[3] = {0, 0, 0};
     long long t_n[3] = {0, 0, 0};
+    int static_dev = -1;  // >= 0: the handle of empic_create_static on that device
 };
 
 namespace {
@@ -491,22 +500,10 @@ void update_jscale(empic_sim *s) {
     s->jscale = std::ldexp(1.0, (int)std::floor(std::log2(std::ldexp(1.0, 48) / B)));
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t empic_workspace_bytes(const empic_grid_desc *g, int32_t max_species, int64_t max_capacity) {
-    if (!g || max_species < 1 || max_species > EMPIC_MAX_SPECIES || max_capacity < 0) return 0;
-    for (int a = 0; a < 3; ++a)
-        if (g->n[a] < 1) return 0;
-    return layout(g, max_species, max_capacity).total;
-}
-
-empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t max_capacity,
-                          void *hip_stream, void *workspace, size_t workspace_bytes,
-                          empic_sim **out) {
-    if (!g || !out || !workspace) return EMPIC_E_ARG;
-    *out = nullptr;
+// Checks of empic_create and empic_create_static on the grid and sizes; the
+// workspace layout on success.
+empic_status validate_create(const empic_grid_desc *g, int32_t max_species, int64_t max_capacity,
+                             Layout &L) {
     if (max_species < 1 || max_species > EMPIC_MAX_SPECIES || max_capacity < 0) return EMPIC_E_ARG;
     if (g->precision != EMPIC_FP32_CELLREL && g->precision != EMPIC_FP64_PLAIN) return EMPIC_E_ARG;
     double inv2 = 0.0;
@@ -534,16 +531,20 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
     if (g->precision == EMPIC_FP64_PLAIN && (g->bc[0] || g->bc[1] || g->bc[2]))
         return EMPIC_E_UNSUPPORTED;
     if (max_capacity >= (1LL << 31)) return EMPIC_E_UNSUPPORTED;
-    if (((uintptr_t)workspace & (ALIGN - 1)) != 0) return EMPIC_E_ARG;
-    const Layout L = layout(g, max_species, max_capacity);
-    if (workspace_bytes < L.total) return EMPIC_E_ARG;
+    L = layout(g, max_species, max_capacity);
+    return EMPIC_OK;
+}
 
-    empic_sim *s = new empic_sim();
+// Fill a fresh handle: carve the workspace ws (L.total bytes), zero what the
+// kernels expect zero, set up the adaptive sort's host ring.  False on a HIP
+// error (the caller releases the handle).
+bool init_handle(empic_sim *s, const empic_grid_desc *g, const Layout &L, int32_t max_species,
+                 int64_t max_capacity, void *hip_stream, char *ws) {
     s->desc = *g;
     grid_info(g, s->g, s->ti);
     s->L = L;
     s->stream = (hipStream_t)hip_stream;
-    s->ws = (char *)workspace;
+    s->ws = ws;
     const size_t es = g->precision == EMPIC_FP64_PLAIN ? 8 : 4;
     for (int a = 0; a < 3; ++a) s->Bbar[a] = s->ws + L.Bbar + (size_t)a * s->g.V * es;
     s->fault = (uint32_t *)(s->ws + L.fault);
@@ -585,10 +586,89 @@ empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t
     }
     if (!ok || hipGetLastError() != hipSuccess) {
         (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
+// At most one live handle of empic_create_static per device, on the
+// device's copy of `scratch`.
+constexpr int STATIC_MAX_DEVICES = 64;
+struct StaticSlot {
+    char *scratch = nullptr;  // the device address of `scratch` on this device
+    bool in_use = false;
+    alignas(empic_sim) unsigned char mem[sizeof(empic_sim)];  // the handle itself
+};
+StaticSlot g_static[STATIC_MAX_DEVICES];
+std::mutex g_static_mu;
+
+}  // namespace
+
+extern "C" {
+
+size_t empic_workspace_bytes(const empic_grid_desc *g, int32_t max_species, int64_t max_capacity) {
+    if (!g || max_species < 1 || max_species > EMPIC_MAX_SPECIES || max_capacity < 0) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (g->n[a] < 1) return 0;
+    return layout(g, max_species, max_capacity).total;
+}
+
+empic_status empic_create(const empic_grid_desc *g, int32_t max_species, int64_t max_capacity,
+                          void *hip_stream, void *workspace, size_t workspace_bytes,
+                          empic_sim **out) {
+    if (!g || !out || !workspace) return EMPIC_E_ARG;
+    *out = nullptr;
+    Layout L;
+    const empic_status st = validate_create(g, max_species, max_capacity, L);
+    if (st != EMPIC_OK) return st;
+    if (((uintptr_t)workspace & (ALIGN - 1)) != 0) return EMPIC_E_ARG;
+    if (workspace_bytes < L.total) return EMPIC_E_ARG;
+    empic_sim *s = new empic_sim();
+    if (!init_handle(s, g, L, max_species, max_capacity, hip_stream, (char *)workspace)) {
         release_adaptive(s);
         delete s;
         return EMPIC_E_HIP;
     }
+    *out = s;
+    return EMPIC_OK;
+}
+
+empic_status empic_create_static(const empic_grid_desc *g, int32_t max_species,
+                                 int64_t max_capacity, void *hip_stream, empic_sim **out) {
+    if (!g || !out) return EMPIC_E_ARG;
+    *out = nullptr;
+    Layout L;
+    const empic_status st = validate_create(g, max_species, max_capacity, L);
+    if (st != EMPIC_OK) return st;
+    if (L.total > (size_t)EMPIC_STATIC_SCRATCH_BYTES) return EMPIC_E_CAPACITY;
+    // the adaptive sort policy needs pinned host memory; a fixed cadence does not
+    if (g->sort_every < 0 && g->precision == EMPIC_FP32_CELLREL) return EMPIC_E_UNSUPPORTED;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES) return EMPIC_E_HIP;
+    if (hip_stream) {
+        int sdev = -1;
+        if (hipStreamGetDevice((hipStream_t)hip_stream, &sdev) != hipSuccess) return EMPIC_E_HIP;
+        if (sdev != dev) return EMPIC_E_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticSlot &slot = g_static[dev];
+    if (slot.in_use) return EMPIC_E_ARG;
+    if (!slot.scratch) {
+        // the device's own copy of the array, looked up once with the device current
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return EMPIC_E_HIP;
+        }
+        slot.scratch = (char *)p;
+    }
+    empic_sim *s = new (slot.mem) empic_sim();  // placement: no allocation
+    s->static_dev = dev;
+    if (!init_handle(s, g, L, max_species, max_capacity, hip_stream, slot.scratch)) {
+        s->~empic_sim();
+        return EMPIC_E_HIP;
+    }
+    slot.in_use = true;
     *out = s;
     return EMPIC_OK;
 }
@@ -1276,6 +1356,13 @@ void empic_destroy(empic_sim *s) {
     for (TimedEvent &t : s->events) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
+    }
+    if (s->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        StaticSlot &slot = g_static[s->static_dev];
+        s->~empic_sim();
+        slot.in_use = false;
+        return;
     }
     delete s;
 }

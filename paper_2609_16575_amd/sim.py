@@ -27,11 +27,14 @@ class Sim:
 
     precision: "fp32" (cell-relative FP32, sorted, fused kernel) or "fp64"
     (plain FP64 global positions).  `workload` is a
-    paper_2609_16575_amd.workloads.Workload.
+    paper_2609_16575_amd.workloads.Workload.  static_workspace=True creates
+    the handle with empic_create_static (the library's per-device workspace,
+    one live handle per device; no device allocation by the library).
     """
 
     def __init__(self, workload, precision: str = "fp32", device: Optional[str] = None,
-                 sort_every: Optional[int] = None, capacity_slack: float = 0.0):
+                 sort_every: Optional[int] = None, capacity_slack: float = 0.0,
+                 static_workspace: bool = False):
         import torch
         self.torch = torch
         self.L = LB.lib()
@@ -77,16 +80,26 @@ class Sim:
         d.sort_every = int(workload.sort_every if sort_every is None else sort_every)
         self.sort_every = d.sort_every
         self.desc = d
-        wsb = self.L.empic_workspace_bytes(C.byref(d), max(nsp, 1), max_cap)
-        if wsb == 0:
-            raise LB.EmpicError(1, "bad grid for the workspace size")
-        self.ws = torch.empty(int(wsb), dtype=torch.uint8, device=self.dev)
         self.stream = torch.cuda.current_stream(self.dev)
         h = C.c_void_p()
-        st = self.L.empic_create(C.byref(d), max(nsp, 1), max_cap, C.c_void_p(self.stream.cuda_stream),
-                                 C.c_void_p(_ptr(self.ws)), int(wsb), C.byref(h))
-        if st != 0:
-            raise LB.EmpicError(st, "empic_create failed")
+        if static_workspace:
+            # the library's own per-device workspace (empic_create_static)
+            self.ws = None
+            with torch.cuda.device(self.dev):
+                st = self.L.empic_create_static(C.byref(d), max(nsp, 1), max_cap,
+                                                C.c_void_p(self.stream.cuda_stream), C.byref(h))
+            if st != 0:
+                raise LB.EmpicError(st, "empic_create_static failed")
+        else:
+            wsb = self.L.empic_workspace_bytes(C.byref(d), max(nsp, 1), max_cap)
+            if wsb == 0:
+                raise LB.EmpicError(1, "bad grid for the workspace size")
+            self.ws = torch.empty(int(wsb), dtype=torch.uint8, device=self.dev)
+            st = self.L.empic_create(C.byref(d), max(nsp, 1), max_cap,
+                                     C.c_void_p(self.stream.cuda_stream),
+                                     C.c_void_p(_ptr(self.ws)), int(wsb), C.byref(h))
+            if st != 0:
+                raise LB.EmpicError(st, "empic_create failed")
         self.h = h
         arr = C.c_void_p * 3
         LB.check(h, self.L.empic_bind_fields(h, arr(*[_ptr(self.E[a]) for a in range(3)]),

@@ -85,3 +85,22 @@ def test_null_handle_calls(L):
     assert L.empic_sync(None) == 1
     assert L.empic_last_error(None) == b"null handle"
     L.empic_destroy(None)
+
+
+def test_static_create_refusals_before_device_work(L):
+    """empic_create_static answers these from the host, before any HIP call."""
+    txt = open(HEADER).read()
+    m = re.search(r"#define EMPIC_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == LB.STATIC_SCRATCH_BYTES
+    h = C.c_void_p()
+    big = _desc(n=(256, 256, 256))
+    assert L.empic_workspace_bytes(C.byref(big), 1, 1 << 24) > LB.STATIC_SCRATCH_BYTES
+    assert L.empic_create_static(C.byref(big), 1, 1 << 24, None, C.byref(h)) == LB.E_CAPACITY
+    assert L.empic_create_static(C.byref(_desc(sort_every=-1)), 1, 64, None,
+                                 C.byref(h)) == LB.E_UNSUPPORTED
+    g = _desc(d=(1.0, 0.5, 2.0))
+    g.dt = 1.01 / (1 + 4 + 0.25) ** 0.5
+    assert L.empic_create_static(C.byref(g), 1, 64, None, C.byref(h)) == LB.E_CFL
+    assert L.empic_create_static(None, 1, 64, None, C.byref(h)) == LB.E_ARG
+    assert L.empic_create_static(C.byref(_desc()), 1, 64, None, None) == LB.E_ARG
+    assert not h.value
