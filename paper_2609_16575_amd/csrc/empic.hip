@@ -31,7 +31,7 @@ inline size_t up_align(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t Bbar, fault, table, partials, result, rho_cur, rho_prev, tile_off, counts, scan, rank,
-        fb_list, adj, filt, mur, total;
+        fb_list, adj, jfix, filt, mur, total;
     size_t tile_off_stride;
     long long mur_stride;
 };
@@ -99,6 +99,8 @@ Layout layout(const empic_grid_desc *d, int max_species, long long max_capacity)
     o += up_align((size_t)max_capacity * max_species * 8);
     L.adj = o;      // adjoint accumulators (FP32 path): gather lam_E, lam_Bbar, lam_B'
     o += d->precision == EMPIC_FP64_PLAIN ? 0 : up_align((size_t)9 * g.V * 4);
+    L.jfix = o;     // FP32 path: the step's current as int64 sums (units 1/jscale)
+    o += d->precision == EMPIC_FP64_PLAIN ? 0 : up_align((size_t)3 * g.V * 8);
     L.filt = o;     // current filter: the second buffer of its passes
     o += up_align((size_t)3 * g.V * es);
     long long ps = 0;
@@ -158,6 +160,7 @@ struct empic_sim {
     int2 *fb_list = nullptr;
     unsigned *fb_count = nullptr;
     float *adj = nullptr;
+    unsigned long long *jfix[3]{};  // FP32 path: the current as exact int64 sums
     void *E[3]{}, *B[3]{}, *J[3]{};
     bool bound = false;
     SpeciesState sp[EMPIC_MAX_SPECIES];
@@ -354,8 +357,11 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
                      s->g.bc[2] == EMPIC_BC_PEC;
     TimedEvent t;
     ev_begin(s, t, 1);
-    // 1. Faraday + temporal centring of B; J zeroed for this step's deposit
-    launch_faraday<T>(s->g, E, B, Bb, J, true, s->stream);
+    // 1. Faraday + temporal centring of B; J (FP64) or its fixed-point sums
+    // (FP32) zeroed for this step's deposit
+    constexpr bool f32 = sizeof(T) == 4;
+    launch_faraday<T>(s->g, E, B, Bb, f32 ? nullptr : J, f32 ? s->jfix : nullptr, true,
+                      s->stream);
     ev_end(s, t);
     // 2. gather, Boris, move, ZigZag for every species
     if constexpr (sizeof(T) == 4) {
@@ -373,7 +379,7 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
             }
             for (int pass = 0; pass < 2; ++pass)
                 launch_push_fused(s->g, s->ti, (float *const *)E, (float *const *)Bb,
-                                  (float *const *)J, tbl, s->nsp, rmask, wmask, s->fault,
+                                  s->jfix, tbl, s->nsp, rmask, wmask, s->fault,
                                   s->fallback, s->fb_list, s->fb_count,
                                   (long long)s->max_capacity * s->max_species, s->jscale,
                                   pass == 1, s->stream, pass == 0 ? tp.a : nullptr,
@@ -387,15 +393,23 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
                             species_params(s, i, 0), s->sp[i].host_count, s->fault, s->stream);
         ev_end(s, t);
     }
-    // 3. current filter, Ampere-Maxwell, external source, absorbing faces
+    // 3. current filter, Ampere-Maxwell, external source, absorbing faces.
+    // FP32 path: J = the fixed-point sums, converted once (by Ampere itself
+    // when there is no filter)
     ev_begin(s, t, 1);
+    const long long *const *jf = f32 ? (const long long *const *)s->jfix : nullptr;
+    const double jinv = 1.0 / s->jscale;
     if (s->filter_passes || s->filter_comp) {
+        if (f32) {
+            launch_j_from_fixed(s->g, (float *const *)J, jf, jinv, s->stream);
+            jf = nullptr;
+        }
         T *tmp[3];
         for (int c = 0; c < 3; ++c) tmp[c] = (T *)s->filt + (size_t)c * s->g.V;
         launch_filter<T>(s->g, J, tmp, s->filter_passes, s->filter_comp, s->stream);
     }
     if (absorbing) launch_mur_save<T>(s->g, E, (T *)s->mur, s->L.mur_stride, s->stream);
-    launch_ampere<T>(s->g, E, B, J, s->stream);
+    launch_ampere<T>(s->g, E, B, J, jf, jinv, s->stream);
     if (s->laser.enabled) launch_laser<T>(s->g, E, s->laser, (s->nstep + 0.5) * s->g.dt, s->stream);
     if (absorbing) launch_mur_apply<T>(s->g, E, (const T *)s->mur, s->L.mur_stride, s->stream);
     if (pec) launch_pec<T>(s->g, E, s->stream);
@@ -562,6 +576,9 @@ bool init_handle(empic_sim *s, const empic_grid_desc *g, const Layout &L, int32_
     s->mur = s->ws + L.mur;
     s->fb_list = (int2 *)(s->ws + L.fb_list);
     s->adj = (float *)(s->ws + L.adj);
+    if (g->precision == EMPIC_FP32_CELLREL)
+        for (int a = 0; a < 3; ++a)
+            s->jfix[a] = (unsigned long long *)(s->ws + L.jfix) + (size_t)a * s->g.V;
     s->fb_count = (unsigned *)(s->ws + L.fault + 16);
     s->max_species = max_species;
     s->max_capacity = max_capacity;
@@ -952,7 +969,7 @@ empic_status empic_diagnostics(empic_sim *s, empic_diag *out) {
         launch_gauss<double>(s->g, E, s->rho_cur, s->rho_bg, s->partials, s->stream);
         if (cont) launch_continuity<double>(s->g, J, s->rho_cur, s->rho_prev, s->partials, s->stream);
         launch_field_energy<double>(s->g, E, B, s->partials, s->stream);
-        launch_faraday<double>(s->g, E, B, Bb, nullptr, false, s->stream);
+        launch_faraday<double>(s->g, E, B, Bb, nullptr, nullptr, false, s->stream);
         for (int i = 0; i < s->nsp; ++i) {
             const SpeciesP p = species_params(s, i, 0);
             launch_kinetic_f64(p, s->sp[i].host_count, s->partials + (Q_KM + i) * PSTRIDE, s->stream);
@@ -965,7 +982,7 @@ empic_status empic_diagnostics(empic_sim *s, empic_diag *out) {
         launch_gauss<float>(s->g, E, s->rho_cur, s->rho_bg, s->partials, s->stream);
         if (cont) launch_continuity<float>(s->g, J, s->rho_cur, s->rho_prev, s->partials, s->stream);
         launch_field_energy<float>(s->g, E, B, s->partials, s->stream);
-        launch_faraday<float>(s->g, E, B, Bb, nullptr, false, s->stream);
+        launch_faraday<float>(s->g, E, B, Bb, nullptr, nullptr, false, s->stream);
         for (int i = 0; i < s->nsp; ++i) {
             const SpeciesP p = species_params(s, i, s->sp[i].cur);
             launch_kinetic_f32(p, s->partials + (Q_KM + i) * PSTRIDE, s->stream);
@@ -1188,7 +1205,7 @@ empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adj
         if (!E[a] || !B[a] || !lE[a] || !lB[a]) return fail(s, EMPIC_E_ARG, "null field array");
     }
     // centred B of the state
-    launch_faraday<float>(s->g, E, B, Bb, nullptr, false, s->stream);
+    launch_faraday<float>(s->g, E, B, Bb, nullptr, nullptr, false, s->stream);
     SpeciesP sp[EMPIC_MAX_SPECIES];
     const int32_t *tiles[EMPIC_MAX_SPECIES] = {};
     float *lx[EMPIC_MAX_SPECIES][3], *lu[EMPIC_MAX_SPECIES][3];

@@ -67,7 +67,9 @@ __global__ void k_faraday(GridP g, const T *__restrict__ Ex, const T *__restrict
                           const T *__restrict__ Ez, T *__restrict__ Bx, T *__restrict__ By,
                           T *__restrict__ Bz, T *__restrict__ Bbx, T *__restrict__ Bby,
                           T *__restrict__ Bbz, T *__restrict__ Jx, T *__restrict__ Jy,
-                          T *__restrict__ Jz, int write_B) {
+                          T *__restrict__ Jz, unsigned long long *__restrict__ Jfx,
+                          unsigned long long *__restrict__ Jfy, unsigned long long *__restrict__ Jfz,
+                          int write_B) {
     Pt q;
     if (!make_point(g, q)) return;
     const long long p = q.p;
@@ -75,6 +77,11 @@ __global__ void k_faraday(GridP g, const T *__restrict__ Ex, const T *__restrict
         Jx[p] = T(0);
         Jy[p] = T(0);
         Jz[p] = T(0);
+    }
+    if (Jfx) {  // the fixed-point current of the FP32 path
+        Jfx[p] = 0ull;
+        Jfy[p] = 0ull;
+        Jfz[p] = 0ull;
     }
     // dt as a pair of T (the low part is zero in FP64): no systematic error
     // from its rounding in the FP32 updates
@@ -107,32 +114,68 @@ __global__ void k_faraday(GridP g, const T *__restrict__ Ex, const T *__restrict
     }
 }
 
+// J in units of 1/jscale (int64, exact sums of the deposit) -> T, one rounding
+template <typename T>
+__device__ __forceinline__ T j_from_fixed(long long x, double jinv) {
+    return (T)((double)x * jinv);
+}
+
+// With Jf (the FP32 path): J is first formed from the fixed-point sums and
+// written out, at every point, then used.
 template <typename T>
 __global__ void k_ampere(GridP g, T *__restrict__ Ex, T *__restrict__ Ey, T *__restrict__ Ez,
                          const T *__restrict__ Bx, const T *__restrict__ By,
-                         const T *__restrict__ Bz, const T *__restrict__ Jx,
-                         const T *__restrict__ Jy, const T *__restrict__ Jz) {
+                         const T *__restrict__ Bz, T *__restrict__ Jx, T *__restrict__ Jy,
+                         T *__restrict__ Jz, const long long *__restrict__ Jfx,
+                         const long long *__restrict__ Jfy, const long long *__restrict__ Jfz,
+                         double jinv) {
     Pt q;
     if (!make_point(g, q)) return;
     const long long p = q.p;
+    T jx, jy, jz;
+    if (Jfx) {
+        jx = j_from_fixed<T>(Jfx[p], jinv);
+        jy = j_from_fixed<T>(Jfy[p], jinv);
+        jz = j_from_fixed<T>(Jfz[p], jinv);
+        Jx[p] = jx;
+        Jy[p] = jy;
+        Jz[p] = jz;
+    } else {
+        jx = Jx[p];
+        jy = Jy[p];
+        jz = Jz[p];
+    }
     const T dt = (T)g.dt, dt_lo = (T)(g.dt - (double)dt);  // see k_faraday
     const T ix = (T)g.inv_d[0], iy = (T)g.inv_d[1], iz = (T)g.inv_d[2];
     // E^{n+1} = E^n + dt curl B^{n+1/2} - dt J^{n+1/2} (backward differences)
     if (ampere_E(g, q, 0)) {
         const T curl = (Bz[p] - Bz[p + dn(g, q, 1)]) * iy - (By[p] - By[p + dn(g, q, 2)]) * iz;
-        const T x = curl - Jx[p];
+        const T x = curl - jx;
         Ex[p] = Ex[p] + dt * x + dt_lo * x;
     }
     if (ampere_E(g, q, 1)) {
         const T curl = (Bx[p] - Bx[p + dn(g, q, 2)]) * iz - (Bz[p] - Bz[p + dn(g, q, 0)]) * ix;
-        const T x = curl - Jy[p];
+        const T x = curl - jy;
         Ey[p] = Ey[p] + dt * x + dt_lo * x;
     }
     if (ampere_E(g, q, 2)) {
         const T curl = (By[p] - By[p + dn(g, q, 0)]) * ix - (Bx[p] - Bx[p + dn(g, q, 1)]) * iy;
-        const T x = curl - Jz[p];
+        const T x = curl - jz;
         Ez[p] = Ez[p] + dt * x + dt_lo * x;
     }
+}
+
+// J = the fixed-point sums converted (before the current filter)
+__global__ void k_j_from_fixed(GridP g, float *__restrict__ Jx, float *__restrict__ Jy,
+                               float *__restrict__ Jz, const long long *__restrict__ Jfx,
+                               const long long *__restrict__ Jfy,
+                               const long long *__restrict__ Jfz, double jinv) {
+    Pt q;
+    if (!make_point(g, q)) return;
+    const long long p = q.p;
+    Jx[p] = j_from_fixed<float>(Jfx[p], jinv);
+    Jy[p] = j_from_fixed<float>(Jfy[p], jinv);
+    Jz[p] = j_from_fixed<float>(Jfz[p], jinv);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,16 +420,25 @@ dim3 reduction_grid(const GridP &g) {
 
 template <typename T>
 void launch_faraday(const GridP &g, T *const E[3], T *const B[3], T *const Bbar[3],
-                    T *const J[3], bool write_B, hipStream_t s) {
+                    T *const J[3], unsigned long long *const Jf[3], bool write_B, hipStream_t s) {
     hipLaunchKernelGGL(k_faraday<T>, point_grid(g), dim3(64, 4), 0, s, g, E[0], E[1], E[2], B[0],
                        B[1], B[2], Bbar[0], Bbar[1], Bbar[2], J ? J[0] : nullptr,
-                       J ? J[1] : nullptr, J ? J[2] : nullptr, write_B ? 1 : 0);
+                       J ? J[1] : nullptr, J ? J[2] : nullptr, Jf ? Jf[0] : nullptr,
+                       Jf ? Jf[1] : nullptr, Jf ? Jf[2] : nullptr, write_B ? 1 : 0);
 }
 
 template <typename T>
-void launch_ampere(const GridP &g, T *const E[3], T *const B[3], T *const J[3], hipStream_t s) {
+void launch_ampere(const GridP &g, T *const E[3], T *const B[3], T *const J[3],
+                   const long long *const Jf[3], double jinv, hipStream_t s) {
     hipLaunchKernelGGL(k_ampere<T>, point_grid(g), dim3(64, 4), 0, s, g, E[0], E[1], E[2], B[0],
-                       B[1], B[2], J[0], J[1], J[2]);
+                       B[1], B[2], J[0], J[1], J[2], Jf ? Jf[0] : nullptr, Jf ? Jf[1] : nullptr,
+                       Jf ? Jf[2] : nullptr, jinv);
+}
+
+void launch_j_from_fixed(const GridP &g, float *const J[3], const long long *const Jf[3],
+                         double jinv, hipStream_t s) {
+    hipLaunchKernelGGL(k_j_from_fixed, point_grid(g), dim3(64, 4), 0, s, g, J[0], J[1], J[2],
+                       Jf[0], Jf[1], Jf[2], jinv);
 }
 
 template <typename T>
@@ -477,9 +529,10 @@ void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *p
 
 #define EMPIC_INST(T)                                                                          \
     template void launch_faraday<T>(const GridP &, T *const[3], T *const[3], T *const[3],      \
-                                    T *const[3], bool, hipStream_t);                           \
+                                    T *const[3], unsigned long long *const[3], bool,           \
+                                    hipStream_t);                                              \
     template void launch_ampere<T>(const GridP &, T *const[3], T *const[3], T *const[3],       \
-                                   hipStream_t);                                               \
+                                   const long long *const[3], double, hipStream_t);            \
     template void launch_mur_save<T>(const GridP &, T *const[3], T *, long long, hipStream_t); \
     template void launch_mur_apply<T>(const GridP &, T *const[3], const T *, long long,        \
                                       hipStream_t);                                            \

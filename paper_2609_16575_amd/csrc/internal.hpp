@@ -171,11 +171,17 @@ dim3 reduction_grid(const GridP &g);
 // ---------------------------------------------------------------------------
 // Launchers (defined in the kernel translation units).
 // ---------------------------------------------------------------------------
+// Faraday + centring of B; zeroes J (FP64 path) or the fixed-point Jf (FP32
+// path) when given
 template <typename T>
 void launch_faraday(const GridP &g, T *const E[3], T *const B[3], T *const Bbar[3],
-                    T *const J[3], bool write_B, hipStream_t s);
+                    T *const J[3], unsigned long long *const Jf[3], bool write_B, hipStream_t s);
+// Ampere-Maxwell; with Jf, J is first set to Jf * jinv (FP32 path)
 template <typename T>
-void launch_ampere(const GridP &g, T *const E[3], T *const B[3], T *const J[3], hipStream_t s);
+void launch_ampere(const GridP &g, T *const E[3], T *const B[3], T *const J[3],
+                   const long long *const Jf[3], double jinv, hipStream_t s);
+void launch_j_from_fixed(const GridP &g, float *const J[3], const long long *const Jf[3],
+                         double jinv, hipStream_t s);
 template <typename T>
 void launch_mur_save(const GridP &g, T *const E[3], T *planes, long long plane_stride,
                      hipStream_t s);
@@ -208,12 +214,14 @@ template <typename T>
 void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *partials,
                          hipStream_t s);
 
-// FP32 cell-relative path.  fallback_pass = false launches the fused tile
+// FP32 cell-relative path; the current goes to Jf as int64 multiples of
+// 1/jscale.  fallback_pass = false launches the fused tile
 // kernel, true the follow-up pass over particles that left their tile window;
 // that pass also writes the cumulative out-of-window count to `publish`
 // (device-accessible pinned host memory) when it is not null.
 void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
-                       float *const Bbar[3], float *const J[3], const DevSpecies *tbl, int nsp,
+                       float *const Bbar[3], unsigned long long *const Jf[3],
+                       const DevSpecies *tbl, int nsp,
                        unsigned cur_mask, unsigned wr_mask, uint32_t *fault, unsigned long long *fallback,
                        int2 *fb_list, unsigned *fb_count, long long fb_cap, double jscale,
                        bool fallback_pass, hipStream_t s, hipEvent_t ev_start = nullptr,

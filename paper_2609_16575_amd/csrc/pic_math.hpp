@@ -238,13 +238,6 @@ __device__ __forceinline__ long long to_fixed(float x, double scale) {
     return __double_as_longlong(t) - 0x4338000000000000LL;
 }
 
-// int64 fixed point -> float: x inv with x converted exactly in two halves
-// (one rounding in the FMA, as a direct conversion), then rounded to FP32
-__device__ __forceinline__ float from_fixed(long long x, double inv) {
-    const double d = fma((double)(int)(x >> 32), 4294967296.0, (double)(uint32_t)x);
-    return (float)(d * inv);
-}
-
 __device__ __forceinline__ int local_axis(const GridP &g, int a, int c, int wo) {
     if (g.bc[a] == EMPIC_BC_PERIODIC) {
         int m = c - wo - 1;

@@ -41,13 +41,13 @@ struct FusedArgs {
     TileInfo ti;
     const float *E[3];
     const float *Bb[3];
-    float *J[3];
+    unsigned long long *Jf[3];  // the step's current in units of 1/jscale (int64 sums)
     const DevSpecies *tbl;  // species parameters (device memory)
     int nsp;
     unsigned cur_mask;      // bit s: buffer set species s is read from
     unsigned wr_mask;       // bit s: buffer set species s is written to (the same for a step in place)
     float dtd[3], dtd_lo[3];  // dt / d_a as FP32 pairs (split_f32)
-    double jscale, jinv;    // fixed-point scale of the LDS current window and its inverse
+    double jscale, jinv;    // fixed-point scale of the current (LDS window and Jf) and its inverse
     uint32_t *fault;
     unsigned long long *fallback;  // cumulative count of out-of-window particles
     int2 *fb_list;                 // (species, slot) of this step's out-of-window particles
@@ -56,9 +56,11 @@ struct FusedArgs {
     unsigned long long *publish;   // host-visible copy of *fallback (k_push_fallback), or null
 };
 
-// global atomic deposit of one segment's 12 values at cell (ci,cj,ck)
-__device__ void deposit_global(const GridP &g, float *const J[3], int ci, int cj, int ck,
-                               const float v[12]) {
+// global atomic deposit of one segment's 12 values at cell (ci,cj,ck), in
+// the fixed point of the tile windows (mult[c]: the scale times the charge
+// factor of component c)
+__device__ void deposit_global(const GridP &g, unsigned long long *const Jf[3], int ci, int cj,
+                               int ck, const float v[12], const double mult[3]) {
     const int cell[3] = {ci, cj, ck};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -72,8 +74,8 @@ __device__ void deposit_global(const GridP &g, float *const J[3], int ci, int cj
             if (gx < 0 || gy < 0 || gz < 0) continue;
             const int gc = c == 0 ? gx : (c == 1 ? gy : gz);
             if (g.bc[c] != EMPIC_BC_PERIODIC && gc >= g.n[c]) continue;  // padding
-            atomicAdd(J[c] + gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz),
-                      v[4 * c + q]);
+            atomicAdd(Jf[c] + gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz),
+                      (unsigned long long)to_fixed(v[4 * c + q], mult[c]));
         }
     }
 }
@@ -99,20 +101,23 @@ __device__ void particle_global(const FusedArgs &A, const DevSpecies &D, uint32_
         if (!(fabsf(dx[a]) < 1.f)) fbits |= EMPIC_FAULT_FAST;
         move_axis(o[a], dx[a], e[a], dc[a], no[a]);
     }
-    const float amp[3] = {D.qc[0] * wq, D.qc[1] * wq, D.qc[2] * wq};
+    // as in the tile kernel: weights with the particle's weight in FP32, the
+    // charge factor in FP64 in the conversion to fixed point
+    const float amp[3] = {wq, wq, wq};
+    const double mult[3] = {A.jscale * D.qcd[0], A.jscale * D.qcd[1], A.jscale * D.qcd[2]};
     float v[12];
     if ((dc[0] | dc[1] | dc[2]) == 0) {
         const float W[3] = {fmaf(0.5f, dx[0], o[0]), fmaf(0.5f, dx[1], o[1]),
                             fmaf(0.5f, dx[2], o[2])};
         segment_weights(W, dx, amp, v);  // one straight segment in this cell
-        deposit_global(g, A.J, ci, cj, ck, v);
+        deposit_global(g, A.Jf, ci, cj, ck, v, mult);
     } else {
         float WA[3], DA[3], WB[3], DB[3];
         zigzag_split(o, dx, e, dc, WA, DA, WB, DB);
         segment_weights(WA, DA, amp, v);
-        deposit_global(g, A.J, ci, cj, ck, v);
+        deposit_global(g, A.Jf, ci, cj, ck, v, mult);
         segment_weights(WB, DB, amp, v);
-        deposit_global(g, A.J, ci + dc[0], cj + dc[1], ck + dc[2], v);
+        deposit_global(g, A.Jf, ci + dc[0], cj + dc[1], ck + dc[2], v, mult);
     }
     int ni, nj, nk;
     const int ok = (int)new_cell(g, 0, ci, dc[0], ni) & (int)new_cell(g, 1, cj, dc[1], nj) &
@@ -567,7 +572,8 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
         }
         __syncthreads();
     }
-    // add the tile's current to global J (non-zero entries only); a thread
+    // add the tile's current to the global fixed-point sums (non-zero entries
+    // only: integer adds, so the sums do not depend on their order); a thread
     // owns one (x, y) column of the window at every ZG-th z, the same points
     // of the three components
     {
@@ -590,7 +596,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
                     for (int comp = 0; comp < 3; ++comp) {
                         const long long fx = (long long)sJ[comp * JW3 + r];
                         if (fx == 0 || skip[comp]) continue;
-                        atomicAdd(A.J[comp] + gx + gy + gz, from_fixed(fx, A.jinv));
+                        atomicAdd(A.Jf[comp] + gx + gy + gz, (unsigned long long)fx);
                     }
                 }
             }
@@ -1254,7 +1260,8 @@ void launch_fused(const FusedArgs &A, int nb, hipStream_t s, hipEvent_t ev_start
 }  // namespace
 
 void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
-                       float *const Bbar[3], float *const J[3], const DevSpecies *tbl, int nsp,
+                       float *const Bbar[3], unsigned long long *const Jf[3],
+                       const DevSpecies *tbl, int nsp,
                        unsigned cur_mask, unsigned wr_mask, uint32_t *fault, unsigned long long *fallback,
                        int2 *fb_list, unsigned *fb_count, long long fb_cap, double jscale,
                        bool fallback_pass, hipStream_t s, hipEvent_t ev_start,
@@ -1265,7 +1272,7 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
     for (int a = 0; a < 3; ++a) {
         A.E[a] = E[a];
         A.Bb[a] = Bbar[a];
-        A.J[a] = J[a];
+        A.Jf[a] = Jf[a];
         split_f32(g.dt / g.d[a], A.dtd[a], A.dtd_lo[a]);
     }
     A.tbl = tbl;

@@ -104,12 +104,17 @@ def forward_loss(args):
     return _loss(o, _mask(o.E.shape))
 
 
-def adjoint(round32):
+def adjoint(rnd=None):
+    """Loss and chained-adjoint gradients of the run; rnd(o), if given, is
+    applied to the state at the start and after every step (True: the
+    FP32 storage rounding of _round_fp32)."""
+    if rnd is True:
+        rnd = _round_fp32
     t0 = time.time()
     o, w = _sim(EPS)
     m = _mask(o.E.shape)
-    if round32:
-        _round_fp32(o)
+    if rnd:
+        rnd(o)
     x0 = o.species[0].pos.copy()
     ckpt = {}
     trace = []
@@ -117,8 +122,8 @@ def adjoint(round32):
         if n % K == 0:
             ckpt[n] = o.state()
         o.step(1)
-        if round32:
-            _round_fp32(o)
+        if rnd:
+            rnd(o)
         trace.append(_loss(o, m))
     L = trace[-1]
     lE = np.where(m[None], o.dV * o.E, 0.0)
@@ -131,12 +136,12 @@ def adjoint(round32):
         for _ in range(min(K, STEPS - seg)):
             states.append(o.state())
             o.step(1)
-            if round32:
-                _round_fp32(o)
+            if rnd:
+                rnd(o)
         for st in reversed(states):
             o.set_state(st)
             lE, lB, lX, lU = o.step_vjp(lE, lB, lX, lU)
-        print("round32=%d segment %d done, %.0f s" % (round32, seg, time.time() - t0), flush=True)
+        print("rounded=%d segment %d done, %.0f s" % (bool(rnd), seg, time.time() - t0), flush=True)
     S = np.sin(2 * np.pi * x0[:, 0] / (w.n[0] * w.d[0]))
     g_eps = float(np.sum(lU[0][:, 0] * S))
     g_dir = float(np.sum(lU[0] * _direction()))
