@@ -28,30 +28,38 @@ from __future__ import annotations
 import numpy as np
 
 
-def _shape(x, lo):
-    """CIC weights of position x (cell units) on the nodes lo, lo + 1, lo + 2."""
-    nodes = lo + np.arange(3)
-    return np.maximum(0.0, 1.0 - np.abs(x - nodes))
+def _shape(x, lo, order=1, count=3):
+    """Weights of position x (cell units) on the nodes lo .. lo + count - 1:
+    CIC max(0, 1 - |x - i|) (order 1) or the quadratic B-spline (order 2)."""
+    t = np.abs(x - (lo + np.arange(count)))
+    if order == 1:
+        return np.maximum(0.0, 1.0 - t)
+    return np.where(t <= 0.5, 0.75 - t * t, np.where(t < 1.5, 0.5 * (1.5 - t) ** 2, 0.0))
 
 
-def esirkepov(n, d, dt, xi0, xi1, q, J):
+def esirkepov(n, d, dt, xi0, xi1, q, J, order=1):
     """Add the current of one particle of charge q moving xi0 -> xi1 (cell
     units, |xi1 - xi0| < 1 per axis, xi0 inside the periodic box) into J
-    ([3][n_z][n_y][n_x], J_a on its edges)."""
+    ([3][n_z][n_y][n_x], J_a on its edges); order 1 (CIC) or 2 (b_2)."""
     xi0 = np.asarray(xi0, dtype=np.float64)
     xi1 = np.asarray(xi1, dtype=np.float64)
-    lo = np.minimum(np.floor(xi0), np.floor(xi1)).astype(np.int64)
-    S0 = [_shape(xi0[a], lo[a]) for a in range(3)]
-    dS = [_shape(xi1[a], lo[a]) - S0[a] for a in range(3)]
+    if order == 1:
+        lo = np.minimum(np.floor(xi0), np.floor(xi1)).astype(np.int64)
+        K = 3
+    else:
+        lo = np.minimum(np.floor(xi0 + 0.5), np.floor(xi1 + 0.5)).astype(np.int64) - 1
+        K = 4
+    S0 = [_shape(xi0[a], lo[a], order, K) for a in range(3)]
+    dS = [_shape(xi1[a], lo[a], order, K) - S0[a] for a in range(3)]
     dV = d[0] * d[1] * d[2]
-    idx = [np.mod(lo[a] + np.arange(3), n[a]) for a in range(3)]
+    idx = [np.mod(lo[a] + np.arange(K), n[a]) for a in range(3)]
     for c in range(3):
         b1, b2 = (c + 1) % 3, (c + 2) % 3
         # transverse factor on the (b1, b2) node pairs
         T = (np.outer(S0[b1], S0[b2]) + 0.5 * np.outer(dS[b1], S0[b2])
              + 0.5 * np.outer(S0[b1], dS[b2]) + np.outer(dS[b1], dS[b2]) / 3.0)
-        W = np.zeros((3, 3, 3))  # [x][y][z] over the particle's nodes
-        for l in range(3):
+        W = np.zeros((K, K, K))  # [x][y][z] over the particle's nodes
+        for l in range(K):
             sl = [slice(None)] * 3
             sl[c] = l
             # T is indexed [b1][b2]; place it on the axes (b1, b2) of W

@@ -593,6 +593,192 @@ void orc_push_deposit(const orc_grid *g, const double *E, const double *Bbar, do
 }
 
 /* ------------------------------------------------------------------------ */
+/* Second-order shapes (the shape-function equation of Sec. 2.4 with l = 1; */
+/* the paper runs l = 0 and names higher orders as an extension, Sec. 5).   */
+/* A super-particle with the triangular cloud b_1 weighs the grid with      */
+/* b_2 = b_1 * b_0, the quadratic B-spline:                                 */
+/*   b_2(t) = 3/4 - t^2 for |t| <= 1/2, (3/2 - |t|)^2 / 2 for |t| <= 3/2.   */
+/* A point at t (sub-grid index units) touches the nearest index            */
+/* m = floor(t + 1/2) and its two neighbours.                               */
+/* ------------------------------------------------------------------------ */
+static double b2(double t) {
+    const double a = fabs(t);
+    if (a <= 0.5) return 0.75 - a * a;
+    if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+    return 0.0;
+}
+
+/* one component from its Yee sub-grid (stag as for gather_one) */
+static double gather2_one(const orc_grid *g, const double *F, const int stag[3],
+                          const double xi[3]) {
+    double t[3];
+    int64_t m[3];
+    for (int a = 0; a < 3; ++a) {
+        t[a] = xi[a] - 0.5 * stag[a];
+        m[a] = (int64_t)floor(t[a] + 0.5);
+    }
+    double s = 0.0;
+    for (int64_t k = m[2] - 1; k <= m[2] + 1; ++k)
+        for (int64_t j = m[1] - 1; j <= m[1] + 1; ++j)
+            for (int64_t i = m[0] - 1; i <= m[0] + 1; ++i) {
+                const int64_t ip = at(g, i, j, k);
+                if (ip < 0) continue;
+                s += b2(t[0] - (double)i) * b2(t[1] - (double)j) * b2(t[2] - (double)k) * F[ip];
+            }
+    return s;
+}
+
+void orc_gather2(const orc_grid *g, const double *E, const double *Bbar, const double pos[3],
+                 double Ep[3], double Bp[3]) {
+    const int64_t V = vol_of(g);
+    double xi[3];
+    for (int a = 0; a < 3; ++a) xi[a] = pos[a] / g->d[a];
+    for (int c = 0; c < 3; ++c) {
+        int se[3], sb[3];
+        for (int a = 0; a < 3; ++a) {
+            se[a] = stag_E(c, a);
+            sb[a] = stag_B(c, a);
+        }
+        Ep[c] = gather2_one(g, E + c * V, se, xi);
+        Bp[c] = gather2_one(g, Bbar + c * V, sb, xi);
+    }
+}
+
+/* Esirkepov's decomposition (Esirkepov 2001) of one move xi0 -> xi1 (cell  */
+/* units, |xi1 - xi0| < 1 per axis) with the b_2 weights S on the nodes     */
+/* lo .. lo+3 that cover both positions:                                    */
+/*   W_c = dS_c (S0_b S0_e + dS_b S0_e / 2 + S0_b dS_e / 2 + dS_b dS_e / 3) */
+/* ((b, e) the other two axes, dS = S1 - S0), and discrete continuity fixes  */
+/* J_c on the edge between nodes l and l+1 along c as the running sum        */
+/* -q d_c / (dt dV) sum_{l' <= l} W_c(l').                                  */
+static void esirkepov2(const orc_grid *g, double *J, const double xi0[3], const double xi1[3],
+                       double qsp) {
+    const double dV = g->d[0] * g->d[1] * g->d[2];
+    int64_t lo[3];
+    double S0[3][4], dS[3][4];
+    for (int a = 0; a < 3; ++a) {
+        const int64_t m0 = (int64_t)floor(xi0[a] + 0.5), m1 = (int64_t)floor(xi1[a] + 0.5);
+        lo[a] = (m0 < m1 ? m0 : m1) - 1;
+        for (int l = 0; l < 4; ++l) {
+            S0[a][l] = b2(xi0[a] - (double)(lo[a] + l));
+            dS[a][l] = b2(xi1[a] - (double)(lo[a] + l)) - S0[a][l];
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        const int b = (c + 1) % 3, e = (c + 2) % 3;
+        const double scale = -qsp * g->d[c] / (g->dt * dV);
+        for (int lb = 0; lb < 4; ++lb)
+            for (int le = 0; le < 4; ++le) {
+                const double T = S0[b][lb] * S0[e][le] + 0.5 * dS[b][lb] * S0[e][le] +
+                                 0.5 * S0[b][lb] * dS[e][le] + dS[b][lb] * dS[e][le] / 3.0;
+                double run = 0.0;
+                for (int l = 0; l < 4; ++l) {
+                    run += dS[c][l] * T;
+                    int64_t p[3];
+                    p[c] = lo[c] + l;
+                    p[b] = lo[b] + lb;
+                    p[e] = lo[e] + le;
+                    if (run != 0.0) add_edge(g, J, c, p[0], p[1], p[2], scale * run);
+                }
+            }
+    }
+}
+
+/* EZ at second order (Steiniger et al., the hybrid the paper names in      */
+/* Sec. 2.5): a move that crosses a cell of the b_2 stencil (the planes      */
+/* between half-integers, i.e. the cells of the ZigZag rule shifted by 1/2)  */
+/* is split at the ZigZag relay point, so that each part stays in one such   */
+/* cell, and each part gets Esirkepov's decomposition.  READING: a move      */
+/* inside one cell is one part (ZigZag's mid-point split is the same thing   */
+/* at first order, where the weights are linear in the position; at second   */
+/* order it would add a loop current).                                       */
+void orc_ez2(const orc_grid *g, double *J, const double xi1[3], const double xi2[3],
+             double qsp) {
+    int cross = 0;
+    for (int a = 0; a < 3; ++a) cross |= floor(xi1[a] + 0.5) != floor(xi2[a] + 0.5);
+    if (!cross) {
+        esirkepov2(g, J, xi1, xi2, qsp);
+        return;
+    }
+    double xr[3];
+    for (int a = 0; a < 3; ++a) {
+        /* the cell of the b_2 stencil: m = floor(xi + 1/2), planes m +- 1/2 */
+        const double m1 = floor(xi1[a] + 0.5), m2 = floor(xi2[a] + 0.5);
+        const double lo = fmin(m1, m2) + 0.5, hi = fmax(m1, m2) - 0.5;
+        xr[a] = fmin(lo, fmax(hi, 0.5 * (xi1[a] + xi2[a])));
+    }
+    esirkepov2(g, J, xi1, xr, qsp);
+    esirkepov2(g, J, xr, xi2, qsp);
+}
+
+/* orc_push_deposit with second-order shapes: b_2 gather, Boris, move, EZ.  */
+void orc_push_deposit2(const orc_grid *g, const double *E, const double *Bbar, double *J,
+                       int64_t np, double *pos, double *u, int8_t *alive, const double *wpp,
+                       double q, double m, double w, int dry, double *kin) {
+    const double r = q * g->dt / (2.0 * m);
+    double L[3];
+    for (int a = 0; a < 3; ++a) L[a] = g->n[a] * g->d[a];
+    double ksum = 0.0;
+    for (int64_t p = 0; p < np; ++p) {
+        if (alive && !alive[p]) continue;
+        const double wp = wpp ? wpp[p] : w;
+        double Ep[3], Bp[3], un[3];
+        orc_gather2(g, E, Bbar, pos + 3 * p, Ep, Bp);
+        for (int a = 0; a < 3; ++a) un[a] = u[3 * p + a];
+        orc_boris(un, Ep, Bp, r);
+        const double uu = un[0] * un[0] + un[1] * un[1] + un[2] * un[2];
+        const double gm = sqrt(1.0 + uu);
+        ksum += wp * m * uu / (gm + 1.0);
+        if (dry) continue;
+        double xi1[3], xi2[3];
+        for (int a = 0; a < 3; ++a) {
+            xi1[a] = pos[3 * p + a] / g->d[a];
+            xi2[a] = xi1[a] + g->dt * un[a] / (gm * g->d[a]);
+        }
+        if (J) orc_ez2(g, J, xi1, xi2, q * wp);
+        for (int a = 0; a < 3; ++a) {
+            u[3 * p + a] = un[a];
+            double x = pos[3 * p + a] + g->dt * un[a] / gm;
+            if (g->bc[a] == ORC_PERIODIC) {
+                if (x >= L[a]) x -= L[a];
+                if (x < 0.0) {
+                    x += L[a];
+                    if (x >= L[a]) x = 0.0;
+                }
+            } else if (x < 0.0 || x >= L[a]) {
+                if (alive) alive[p] = 0;
+            }
+            pos[3 * p + a] = x;
+        }
+    }
+    if (kin) *kin += ksum;
+}
+
+/* b_2 charge density at nodes, rho += (q_sp / dV) prod_a b_2(xi_a - i_a).  */
+void orc_rho2(const orc_grid *g, int64_t np, const double *pos, const int8_t *alive,
+              const double *wpp, double q, double w, double *rho) {
+    const double dV = g->d[0] * g->d[1] * g->d[2];
+    for (int64_t p = 0; p < np; ++p) {
+        if (alive && !alive[p]) continue;
+        const double qsp = q * (wpp ? wpp[p] : w);
+        double t[3];
+        int64_t m[3];
+        for (int a = 0; a < 3; ++a) {
+            t[a] = pos[3 * p + a] / g->d[a];
+            m[a] = (int64_t)floor(t[a] + 0.5);
+        }
+        for (int64_t k = m[2] - 1; k <= m[2] + 1; ++k)
+            for (int64_t j = m[1] - 1; j <= m[1] + 1; ++j)
+                for (int64_t i = m[0] - 1; i <= m[0] + 1; ++i) {
+                    const int64_t ip = at(g, i, j, k);
+                    if (ip < 0) continue;
+                    rho[ip] += qsp / dV * b2(t[0] - (double)i) * b2(t[1] - (double)j) *
+                               b2(t[2] - (double)k);
+                }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sec. 2.5: CIC charge density at nodes, rho += (q_sp / dV) prod_a w_a.     */
 /* ------------------------------------------------------------------------ */
 void orc_rho(const orc_grid *g, int64_t np, const double *pos, const int8_t *alive,

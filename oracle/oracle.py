@@ -76,6 +76,11 @@ def lib():
     L.orc_push_deposit.argtypes = [G, _D, _D, _D, C.c_int64, _D, _D, _I8, _D, C.c_double,
                                    C.c_double, C.c_double, C.c_int, C.c_int, _D]
     L.orc_rho.argtypes = [G, C.c_int64, _D, _I8, _D, C.c_double, C.c_double, _D]
+    L.orc_gather2.argtypes = [G, _D, _D, _D, _D, _D]
+    L.orc_ez2.argtypes = [G, _D, _D, _D, C.c_double]
+    L.orc_push_deposit2.argtypes = [G, _D, _D, _D, C.c_int64, _D, _D, _I8, _D, C.c_double,
+                                    C.c_double, C.c_double, C.c_int, _D]
+    L.orc_rho2.argtypes = [G, C.c_int64, _D, _I8, _D, C.c_double, C.c_double, _D]
     L.orc_div_nodes.argtypes = [G, _D, _D]
     L.orc_energy_E.argtypes = [G, _D]
     L.orc_energy_E.restype = C.c_double
@@ -155,6 +160,7 @@ class OracleSim:
         self.rho_bg = 0.0
         self.nstep = 0
         self.midpoint_only = False
+        self.shape_order = 1  # 2: b_2 weighting (triangular clouds), EZ deposit
 
     # -- set-up --------------------------------------------------------------
     @property
@@ -241,6 +247,11 @@ class OracleSim:
             L.orc_faraday(g, _p(self.E), _p(self.B), _p(self.Bbar))
             self.J[...] = 0.0
             for s in self.species:
+                if self.shape_order == 2:
+                    L.orc_push_deposit2(g, _p(self.E), _p(self.Bbar), _p(self.J), s.np,
+                                        _p(s.pos), _p(s.u), _p8(s.alive), _p(s.wpp), s.q, s.m,
+                                        s.w, 0, None)
+                    continue
                 L.orc_push_deposit(g, _p(self.E), _p(self.Bbar), _p(self.J), s.np, _p(s.pos),
                                    _p(s.u), _p8(s.alive), _p(s.wpp), s.q, s.m, s.w,
                                    int(self.midpoint_only), 0, None)
@@ -268,6 +279,7 @@ class OracleSim:
         of E^n, B^{n-1/2}, x^n, u^{n-1/2}.  The state is not changed.
         """
         assert all(b == PERIODIC for b in self.bc), "adjoint needs a periodic grid"
+        assert self.shape_order == 1, "adjoint of the first-order step only"
         L = lib()
         g = C.byref(self.g)
         Bh = self.B.copy()
@@ -312,8 +324,8 @@ class OracleSim:
         sel = range(len(self.species)) if species is None else [species]
         for i in sel:
             s = self.species[i]
-            L.orc_rho(C.byref(self.g), s.np, _p(s.pos), _p8(s.alive), _p(s.wpp), s.q, s.w,
-                      _p(out))
+            f = L.orc_rho2 if self.shape_order == 2 else L.orc_rho
+            f(C.byref(self.g), s.np, _p(s.pos), _p8(s.alive), _p(s.wpp), s.q, s.w, _p(out))
         if with_background:
             out += self.rho_bg
         return out
@@ -337,9 +349,13 @@ class OracleSim:
             k = C.c_double(0.0)
             u = s.u.copy()
             pos = s.pos.copy()
-            L.orc_push_deposit(C.byref(self.g), _p(self.E), _p(Bbar), None, s.np, _p(pos),
-                               _p(u), _p8(None if s.alive is None else s.alive.copy()),
-                               _p(s.wpp), s.q, s.m, s.w, 0, 1, C.byref(k))
+            alive = _p8(None if s.alive is None else s.alive.copy())
+            if self.shape_order == 2:
+                L.orc_push_deposit2(C.byref(self.g), _p(self.E), _p(Bbar), None, s.np, _p(pos),
+                                    _p(u), alive, _p(s.wpp), s.q, s.m, s.w, 1, C.byref(k))
+            else:
+                L.orc_push_deposit(C.byref(self.g), _p(self.E), _p(Bbar), None, s.np, _p(pos),
+                                   _p(u), alive, _p(s.wpp), s.q, s.m, s.w, 0, 1, C.byref(k))
             out.append(k.value)
         return out
 
@@ -383,6 +399,21 @@ def zigzag(grid: _Grid, shape, xi1, xi2, qsp, midpoint_only=False, J=None):
     J = np.zeros(shape) if J is None else J
     lib().orc_zigzag(C.byref(grid), _p(J), _p(np.asarray(xi1, dtype=np.float64)),
                      _p(np.asarray(xi2, dtype=np.float64)), float(qsp), int(midpoint_only))
+    return J
+
+
+def gather2(grid: _Grid, E, Bbar, pos):
+    Ep = np.zeros(3)
+    Bp = np.zeros(3)
+    lib().orc_gather2(C.byref(grid), _p(E), _p(Bbar), _p(np.asarray(pos, dtype=np.float64)),
+                      _p(Ep), _p(Bp))
+    return Ep, Bp
+
+
+def ez2(grid: _Grid, shape, xi1, xi2, qsp, J=None):
+    J = np.zeros(shape) if J is None else J
+    lib().orc_ez2(C.byref(grid), _p(J), _p(np.asarray(xi1, dtype=np.float64)),
+                  _p(np.asarray(xi2, dtype=np.float64)), float(qsp))
     return J
 
 
