@@ -306,6 +306,18 @@ empic_status empic_set_injection(empic_sim *s, int32_t sp, const int32_t per_cel
  * the filter into account. */
 empic_status empic_set_filter(empic_sim *s, int32_t passes, int32_t compensate);
 
+/* Particle shape order (the shape-function equation of Sec. 2.4, B-spline
+ * b_l of the cloud; the paper runs l = 0, Sec. 5 names higher orders).
+ * order 1 (the default): CIC weighting (b_1), ZigZag current.  order 2: the
+ * triangular cloud b_1 weighs the grid with the quadratic B-spline b_2 --
+ * 27-point gather of every component from its own Yee sub-grid, b_2 charge
+ * for the diagnostics, and the EZ current (Sec. 2.5): a move that crosses a
+ * cell of the b_2 stencil (between half-integer planes) is split at the
+ * ZigZag relay point and each part gets Esirkepov's decomposition.  Order 2:
+ * FP32 path on periodic three-dimensional grids (else EMPIC_E_UNSUPPORTED);
+ * empic_step_vjp refuses it.  EMPIC_E_ARG for other orders. */
+empic_status empic_set_shape_order(empic_sim *s, int32_t order);
+
 /* Advance the state by nsteps PIC cycles (Sec. 2.2): Faraday with temporal
  * centring of B -> gather, Boris, move, ZigZag deposit for every species ->
  * current filter -> Ampere-Maxwell -> laser source -> Mur faces -> PEC walls

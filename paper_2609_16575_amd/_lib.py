@@ -91,6 +91,7 @@ SIGNATURES = {
     "empic_create_static": (C.c_int, [C.POINTER(GridDesc), C.c_int32, C.c_int64, _P,
                                       C.POINTER(_P)]),
     "empic_bind_fields": (C.c_int, [_P, _P * 3, _P * 3, _P * 3]),
+    "empic_set_shape_order": (C.c_int, [_P, C.c_int32]),
     "empic_add_species": (C.c_int, [_P, C.POINTER(SpeciesDesc), C.c_int64,
                                     C.POINTER(ParticleBuffers), C.POINTER(ParticleBuffers),
                                     C.POINTER(C.c_int32)]),

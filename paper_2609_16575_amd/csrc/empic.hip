@@ -902,6 +902,21 @@ empic_status empic_set_filter(empic_sim *s, int32_t passes, int32_t compensate) 
     return EMPIC_OK;
 }
 
+empic_status empic_set_shape_order(empic_sim *s, int32_t order) {
+    EMPIC_GUARD(s);
+    if (order != 1 && order != 2) return fail(s, EMPIC_E_ARG, "shape order 1 or 2");
+    if (order == 2) {
+        if (fp64(s))
+            return fail(s, EMPIC_E_UNSUPPORTED, "second-order shapes: FP32 path only");
+        if (s->g.bc[0] || s->g.bc[1] || s->g.bc[2] || s->ti.slab)
+            return fail(s, EMPIC_E_UNSUPPORTED,
+                        "second-order shapes: periodic three-dimensional grids only");
+    }
+    s->g.shape_order = order;
+    s->rho_prev_step = -1;  // the next continuity residual compares like with like
+    return EMPIC_OK;
+}
+
 empic_status empic_sort(empic_sim *s) {
     EMPIC_GUARD(s);
     if (fp64(s)) return EMPIC_OK;  // the plain path keeps its order
@@ -1192,6 +1207,8 @@ empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adj
     if (!st || !lam || !s->bound) return fail(s, EMPIC_E_ARG, "null state or adjoint");
     if (fp64(s) || s->g.bc[0] || s->g.bc[1] || s->g.bc[2])
         return fail(s, EMPIC_E_UNSUPPORTED, "the adjoint needs the FP32 path on a periodic grid");
+    if (s->g.shape_order != 1)
+        return fail(s, EMPIC_E_UNSUPPORTED, "the adjoint is of the first-order (CIC) step");
     float *E[3], *B[3], *Bb[3], *lE[3], *lB[3], *lEg[3], *lBb[3], *tB[3];
     for (int a = 0; a < 3; ++a) {
         E[a] = (float *)st->E[a];

@@ -20,6 +20,7 @@ struct GridP {
     double inv_d[3];
     double dt;
     long long V;  // ext0 * ext1 * ext2
+    int shape_order = 1;  // 1: CIC weighting (the paper's); 2: b_2 weighting, EZ current
 };
 
 // Drift margin: particles up to MARGIN cells outside their tile (moved since

@@ -57,6 +57,155 @@ __device__ inline float tri_global(const GridP &g, const float *F, int i0, int j
     return lerpf(lerpf(c00, c10, fy), lerpf(c01, c11, fy), fz);
 }
 
+// ---------------------------------------------------------------------------
+// Second-order shapes (the shape-function equation of Sec. 2.4 with l = 1):
+// weighting by the quadratic B-spline b_2 on the nearest index m of a
+// sub-grid and its two neighbours.  For a point at m + d, |d| <= 1/2:
+//   b_2(d + 1) = (1/2 - d)^2 / 2, b_2(d) = 3/4 - d^2, b_2(d - 1) = (1/2 + d)^2 / 2
+// (weights of m - 1, m, m + 1).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void b2_w(float d, float w[3]) {
+    const float a = 0.5f - d, b = 0.5f + d;
+    w[0] = 0.5f * a * a;
+    w[1] = fmaf(-d, d, 0.75f);
+    w[2] = 0.5f * b * b;
+}
+
+// Stencil of an in-cell offset o on one axis, relative to the particle's
+// cell: node (integer) sub-grids m = (o >= 1/2), d = o - m; half-integer
+// sub-grids (index i at i + 1/2) m = 0, d = o - 1/2.
+__device__ __forceinline__ void b2_node(float o, int &m, float &d) {
+    m = o >= 0.5f ? 1 : 0;
+    d = o - (float)m;
+}
+
+// 27-point b_2 interpolation from global memory (m: nearest index per axis;
+// points outside an absorbing axis' array contribute zero)
+__device__ inline float tri2_global(const GridP &g, const float *F, int m0, int m1, int m2,
+                                    const float wx[3], const float wy[3], const float wz[3]) {
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int gz = gaxis(g, 2, m2 - 1 + k);
+        if (gz < 0) continue;
+        float sy = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int gy = gaxis(g, 1, m1 - 1 + j);
+            if (gy < 0) continue;
+            float sx = 0.f;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int gx = gaxis(g, 0, m0 - 1 + i);
+                if (gx < 0) continue;
+                sx = fmaf(wx[i], F[gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz)], sx);
+            }
+            sy = fmaf(wy[j], sx, sy);
+        }
+        s = fmaf(wz[k], sy, s);
+    }
+    return s;
+}
+
+// E and Bbar at a particle with b_2 weights, each component from its own
+// Yee sub-grid (Ex half-integer along x, Bx half-integer along y and z, ...)
+__device__ inline void gather2_global(const GridP &g, const float *const E[3],
+                                      const float *const Bb[3], int ci, int cj, int ck, float ox,
+                                      float oy, float oz, float Ep[3], float Bp[3]) {
+    const int c[3] = {ci, cj, ck};
+    const float o[3] = {ox, oy, oz};
+    int mn[3], mh[3];
+    float wn[3][3], wh[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int m;
+        float d;
+        b2_node(o[a], m, d);
+        mn[a] = c[a] + m;
+        b2_w(d, wn[a]);
+        mh[a] = c[a];
+        b2_w(o[a] - 0.5f, wh[a]);
+    }
+    Ep[0] = tri2_global(g, E[0], mh[0], mn[1], mn[2], wh[0], wn[1], wn[2]);
+    Ep[1] = tri2_global(g, E[1], mn[0], mh[1], mn[2], wn[0], wh[1], wn[2]);
+    Ep[2] = tri2_global(g, E[2], mn[0], mn[1], mh[2], wn[0], wn[1], wh[2]);
+    Bp[0] = tri2_global(g, Bb[0], mn[0], mh[1], mh[2], wn[0], wh[1], wh[2]);
+    Bp[1] = tri2_global(g, Bb[1], mh[0], mn[1], mh[2], wh[0], wn[1], wh[2]);
+    Bp[2] = tri2_global(g, Bb[2], mh[0], mh[1], mn[2], wh[0], wh[1], wn[2]);
+}
+
+// Esirkepov's decomposition of one part of a move that stays in the b_2
+// cell m (relative to the particle's cell) on every axis, from sA to sB
+// (offsets relative to the particle's cell).  With S0 = b_2 weights at sA,
+// dS = (weights at sB) - S0 on the nodes m - 1 .. m + 1 of each axis,
+//   W_c = dS_c (S0_b S0_e + dS_b S0_e / 2 + S0_b dS_e / 2 + dS_b dS_e / 3),
+// and J_c on the edge between nodes l and l + 1 along c is -(sum of W_c up
+// to l) times the charge factor (the third running sum is zero).  sink(c, x,
+// y, z, v) receives v for the edge or node index (x, y, z) relative to the
+// particle's cell; v still lacks the charge factor of component c.
+template <class Sink>
+__device__ __forceinline__ void ez2_part(const float sA[3], const float sB[3], const int m[3],
+                                         float wq, Sink &sink) {
+    float S0[3][3], dS[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float w1[3];
+        b2_w(sA[a] - (float)m[a], S0[a]);
+        b2_w(sB[a] - (float)m[a], w1);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dS[a][i] = w1[i] - S0[a][i];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int b = c == 2 ? 0 : c + 1, e = c == 0 ? 2 : c - 1;
+        const int bb = b < e ? b : e, ee = b < e ? e : b;  // T[ib][ie] over (b, e)
+        const float r0 = -wq * dS[c][0], r1 = -wq * (dS[c][0] + dS[c][1]);
+#pragma unroll
+        for (int ib = 0; ib < 3; ++ib)
+#pragma unroll
+            for (int ie = 0; ie < 3; ++ie) {
+                const float T = fmaf(dS[bb][ib], fmaf(0.5f, S0[ee][ie], dS[ee][ie] * (1.f / 3.f)),
+                                     S0[bb][ib] * fmaf(0.5f, dS[ee][ie], S0[ee][ie]));
+                int idx[3];
+                idx[bb] = m[bb] - 1 + ib;
+                idx[ee] = m[ee] - 1 + ie;
+                idx[c] = m[c] - 1;
+                sink(c, idx[0], idx[1], idx[2], r0 * T);
+                idx[c] = m[c];
+                sink(c, idx[0], idx[1], idx[2], r1 * T);
+            }
+    }
+}
+
+// The EZ current of a move from offset o by dx (cell units, relative to the
+// particle's cell): one Esirkepov part inside one b_2 cell, else two parts
+// split at the ZigZag relay point (the crossed half-integer plane on a
+// crossing axis, the mid-point on the others).
+template <class Sink>
+__device__ __forceinline__ void ez2_move(const float o[3], const float dx[3], float wq,
+                                         Sink &sink) {
+    float s1[3];
+    int m0[3], m1[3];
+    bool cross = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s1[a] = o[a] + dx[a];
+        m0[a] = o[a] >= 0.5f ? 1 : 0;
+        m1[a] = (int)floorf(s1[a] + 0.5f);
+        cross = cross || m0[a] != m1[a];
+    }
+    if (!cross) {
+        ez2_part(o, s1, m0, wq, sink);
+        return;
+    }
+    float r[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        r[a] = m0[a] != m1[a] ? (float)max(m0[a], m1[a]) - 0.5f : 0.5f * (o[a] + s1[a]);
+    ez2_part(o, r, m0, wq, sink);
+    ez2_part(r, s1, m1, wq, sink);
+}
+
 __device__ __forceinline__ void half_axis(float o, int l, int &h, float &fh) {
     if (o < 0.5f) {
         h = l - 1;

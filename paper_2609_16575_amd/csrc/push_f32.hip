@@ -80,14 +80,31 @@ __device__ void deposit_global(const GridP &g, unsigned long long *const Jf[3], 
     }
 }
 
+// Order-2 current of a particle into the global fixed-point sums
+struct GlobalSink2 {
+    const GridP &g;
+    unsigned long long *const *Jf;
+    int cell[3];
+    const double *mult;
+    __device__ void operator()(int c, int x, int y, int z, float v) const {
+        const int gx = gaxis(g, 0, cell[0] + x), gy = gaxis(g, 1, cell[1] + y),
+                  gz = gaxis(g, 2, cell[2] + z);
+        if (gx < 0 || gy < 0 || gz < 0 || v == 0.f) return;
+        atomicAdd(Jf[c] + gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz),
+                  (unsigned long long)to_fixed(v, mult[c]));
+    }
+};
+
 // Whole particle through global memory (drifted out of the LDS window).
+template <int ORDER>
 __device__ void particle_global(const FusedArgs &A, const DevSpecies &D, uint32_t &c, float &ox,
                                              float &oy, float &oz, float &ux, float &uy,
                                              float &uz, float wq, uint32_t &fbits) {
     const GridP &g = A.g;
     const int ci = cell_i(c), cj = cell_j(c), ck = cell_k(c);
     float Ep[3], Bp[3];
-    gather_global(g, A.E, A.Bb, ci, cj, ck, ox, oy, oz, Ep, Bp);
+    if constexpr (ORDER == 2) gather2_global(g, A.E, A.Bb, ci, cj, ck, ox, oy, oz, Ep, Bp);
+    else gather_global(g, A.E, A.Bb, ci, cj, ck, ox, oy, oz, Ep, Bp);
     float gam;
     const float ig = boris_f32(ux, uy, uz, Ep, Bp, D.r, D.r_lo, gam);
     if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
@@ -106,7 +123,10 @@ __device__ void particle_global(const FusedArgs &A, const DevSpecies &D, uint32_
     const float amp[3] = {wq, wq, wq};
     const double mult[3] = {A.jscale * D.qcd[0], A.jscale * D.qcd[1], A.jscale * D.qcd[2]};
     float v[12];
-    if ((dc[0] | dc[1] | dc[2]) == 0) {
+    if constexpr (ORDER == 2) {
+        GlobalSink2 sink{g, A.Jf, {ci, cj, ck}, mult};
+        ez2_move(o, dx, wq, sink);
+    } else if ((dc[0] | dc[1] | dc[2]) == 0) {
         const float W[3] = {fmaf(0.5f, dx[0], o[0]), fmaf(0.5f, dx[1], o[1]),
                             fmaf(0.5f, dx[2], o[2])};
         segment_weights(W, dx, amp, v);  // one straight segment in this cell
@@ -419,6 +439,173 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
     }
 }
 
+// 27-point b_2 interpolation from the LDS field window of one component;
+// (x, y, z): window index of the stencil's first point (nearest index - 1)
+template <class TL>
+__device__ __forceinline__ float tri2_lds(const float *F, int x, int y, int z, const float wx[3],
+                                          const float wy[3], const float wz[3]) {
+    constexpr int FWX = TL::FWX, FWY = TL::FWY;
+    const float *p = F + x + FWX * (y + FWY * z);
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float sy = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float *row = p + FWX * (j + FWY * k);
+            sy = fmaf(wy[j], fmaf(wx[2], row[2], fmaf(wx[1], row[1], wx[0] * row[0])), sy);
+        }
+        s = fmaf(wz[k], sy, s);
+    }
+    return s;
+}
+
+// Order-2 current of a particle into the LDS window (fixed point)
+struct LdsSink2 {
+    unsigned long long *sJ;
+    int jb;  // window index of the particle's cell
+    int JWX, JWY, JW3;
+    const double *mult;
+    __device__ __forceinline__ void operator()(int c, int x, int y, int z, float v) const {
+        atomicAdd(sJ + c * JW3 + jb + x + JWX * (y + JWY * z),
+                  (unsigned long long)to_fixed(v, mult[c]));
+    }
+};
+
+// One species of one tile with second-order shapes: the b_2 gather from the
+// LDS field window, Boris, move, and the EZ current into the LDS window.
+// The windows of the first-order kernel hold the b_2 stencils of the
+// particles inside their tile (no drift margin): the others take the global
+// path of k_push_fallback.
+template <class TL, int P>
+__device__ __forceinline__ void push_species2(const FusedArgs &A, const DevSpecies &D,
+                                              const SpeciesP &S, const SpeciesP &Wr, int beg,
+                                              int end, const TileCtx &T, const float *sF,
+                                              unsigned long long *sJ, int s, uint32_t &fbits,
+                                              unsigned &nfb) {
+    typedef float VF __attribute__((ext_vector_type(P)));
+    typedef uint32_t VU __attribute__((ext_vector_type(P)));
+    constexpr int FW3 = TL::FW3, JWX = TL::JWX, JWY = TL::JWY, JW3 = TL::JW3;
+    constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
+    const GridP &g = A.g;
+    const float r = D.r, r_lo = D.r_lo;
+    const double mult[3] = {A.jscale * D.qcd[0], A.jscale * D.qcd[1], A.jscale * D.qcd[2]};
+    guint *CQ = (guint *)Wr.cell;
+    gfloat *OXQ = (gfloat *)Wr.pos[0], *OYQ = (gfloat *)Wr.pos[1], *OZQ = (gfloat *)Wr.pos[2];
+    gfloat *UXQ = (gfloat *)Wr.u[0], *UYQ = (gfloat *)Wr.u[1], *UZQ = (gfloat *)Wr.u[2];
+    const int base0 = batch_base0<P>(beg) + (int)threadIdx.x * P;
+    Batch<P> b;
+    for (int base = base0; base < end; base += PUSH_THREADS * P) {
+        load_batch<P>(S, base, b);
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int p = base + k;
+            const uint32_t c = b.c[k];
+            if (!(p >= beg && p < end && c != DEAD)) continue;
+            const int lx = local_axis(g, 0, cell_i(c), T.wo[0]);
+            const int ly = local_axis(g, 1, cell_j(c), T.wo[1]);
+            const int lz = local_axis(g, 2, cell_k(c), T.wo[2]);
+            // inside the tile: window indices MARGIN + 1 .. MARGIN + T
+            if (!((unsigned)(lx - MARGIN - 1) < (unsigned)TX &&
+                  (unsigned)(ly - MARGIN - 1) < (unsigned)TY &&
+                  (unsigned)(lz - MARGIN - 1) < (unsigned)TZ)) {
+                ++nfb;
+                const unsigned slot = atomicAdd(A.fb_count, 1u);
+                if (slot < (unsigned long long)A.fb_cap) A.fb_list[slot] = make_int2(s, p);
+                else fbits |= EMPIC_FAULT_CELL;
+                continue;
+            }
+            const float o[3] = {b.ox[k], b.oy[k], b.oz[k]};
+            if (!(fminf(fminf(o[0], o[1]), o[2]) >= 0.f && fmaxf(fmaxf(o[0], o[1]), o[2]) < 1.f))
+                fbits |= EMPIC_FAULT_OFFSET;
+            const int l[3] = {lx, ly, lz};
+            int xn[3], xh[3];  // window index of each stencil's first point
+            float wn[3][3], wh[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                int m;
+                float d;
+                b2_node(o[a], m, d);
+                xn[a] = l[a] + m - 1;
+                b2_w(d, wn[a]);
+                xh[a] = l[a] - 1;
+                b2_w(o[a] - 0.5f, wh[a]);
+            }
+            float Ep[3], Bp[3];
+            Ep[0] = tri2_lds<TL>(sF + 0 * FW3, xh[0], xn[1], xn[2], wh[0], wn[1], wn[2]);
+            Ep[1] = tri2_lds<TL>(sF + 1 * FW3, xn[0], xh[1], xn[2], wn[0], wh[1], wn[2]);
+            Ep[2] = tri2_lds<TL>(sF + 2 * FW3, xn[0], xn[1], xh[2], wn[0], wn[1], wh[2]);
+            Bp[0] = tri2_lds<TL>(sF + 3 * FW3, xn[0], xh[1], xh[2], wn[0], wh[1], wh[2]);
+            Bp[1] = tri2_lds<TL>(sF + 4 * FW3, xh[0], xn[1], xh[2], wh[0], wn[1], wh[2]);
+            Bp[2] = tri2_lds<TL>(sF + 5 * FW3, xh[0], xh[1], xn[2], wh[0], wh[1], wn[2]);
+            float ux = b.ux[k], uy = b.uy[k], uz = b.uz[k], gam;
+            const float ig = boris_f32(ux, uy, uz, Ep, Bp, r, r_lo, gam);
+            if (!isfinite(gam)) fbits |= EMPIC_FAULT_NONFINITE;
+            const float dx[3] = {move_cells(ux * ig, A.dtd[0], A.dtd_lo[0]),
+                                 move_cells(uy * ig, A.dtd[1], A.dtd_lo[1]),
+                                 move_cells(uz * ig, A.dtd[2], A.dtd_lo[2])};
+            if (!(fmaxf(fmaxf(fabsf(dx[0]), fabsf(dx[1])), fabsf(dx[2])) < 1.f))
+                fbits |= EMPIC_FAULT_FAST;
+            LdsSink2 sink{sJ, lx + JWX * (ly + JWY * lz), JWX, JWY, JW3, mult};
+            ez2_move(o, dx, b.w[k], sink);
+            float e[3], no[3];
+            int dc[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) move_axis_sel(o[a], dx[a], e[a], dc[a], no[a]);
+            int ni, nj, nk;
+            const int in = (int)new_cell(g, 0, cell_i(c), dc[0], ni) &
+                           (int)new_cell(g, 1, cell_j(c), dc[1], nj) &
+                           (int)new_cell(g, 2, cell_k(c), dc[2], nk);
+            b.c[k] = in ? pack_cell(ni, nj, nk) : DEAD;
+            b.ox[k] = no[0];
+            b.oy[k] = no[1];
+            b.oz[k] = no[2];
+            b.ux[k] = ux;
+            b.uy[k] = uy;
+            b.uz[k] = uz;
+        }
+        if (base >= beg && base + P <= end) {
+            __builtin_nontemporal_store(b.c, (VU *)(CQ + base));
+            __builtin_nontemporal_store(b.ox, (VF *)(OXQ + base));
+            __builtin_nontemporal_store(b.oy, (VF *)(OYQ + base));
+            __builtin_nontemporal_store(b.oz, (VF *)(OZQ + base));
+            __builtin_nontemporal_store(b.ux, (VF *)(UXQ + base));
+            __builtin_nontemporal_store(b.uy, (VF *)(UYQ + base));
+            __builtin_nontemporal_store(b.uz, (VF *)(UZQ + base));
+        } else {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const int p = base + k;
+                if (p < beg || p >= end) continue;
+                CQ[p] = b.c[k];
+                OXQ[p] = b.ox[k];
+                OYQ[p] = b.oy[k];
+                OZQ[p] = b.oz[k];
+                UXQ[p] = b.ux[k];
+                UYQ[p] = b.uy[k];
+                UZQ[p] = b.uz[k];
+            }
+        }
+    }
+}
+
+template <class TL>
+__device__ __forceinline__ void push_tile2(const FusedArgs &A, const TileCtx &T, int tile,
+                                           const float *sF, unsigned long long *sJ,
+                                           uint32_t &fbits, unsigned &nfb) {
+    for (int s = 0; s < A.nsp; ++s) {
+        const DevSpecies &D = A.tbl[s];
+        const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
+        const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
+        const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
+        if (beg >= end) continue;
+        if (end - beg <= 2 * PUSH_THREADS)
+            push_species2<TL, 1>(A, D, S, Wr, beg, end, T, sF, sJ, s, fbits, nfb);
+        else
+            push_species2<TL, PPT>(A, D, S, Wr, beg, end, T, sF, sJ, s, fbits, nfb);
+    }
+}
+
 // Every species of one tile (sparse ones one particle per thread, so that all
 // the workgroup's waves work; dense ones four per thread).
 template <class TL, bool INTERIOR>
@@ -445,7 +632,7 @@ __device__ __forceinline__ void push_tile(const FusedArgs &A, const TileCtx &T, 
     }
 }
 
-template <class TL>
+template <class TL, int ORDER>
 __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
     constexpr int FWX = TL::FWX, FWY = TL::FWY, FWZ = TL::FWZ, FW3 = TL::FW3;
@@ -472,7 +659,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     // together with the field window: one memory latency for both
     const SpeciesP &S0 = A.tbl[0].p[A.cur_mask & 1u];
     const int beg0 = S0.tile_off[tile], end0 = S0.tile_off[tile + 1];
-    const bool sparse0 = end0 > beg0 && end0 - beg0 <= 2 * PUSH_THREADS;
+    const bool sparse0 = ORDER == 1 && end0 > beg0 && end0 - beg0 <= 2 * PUSH_THREADS;
     Batch<1> pre1;
     if (sparse0 && beg0 + (int)threadIdx.x < end0) load_batch<1>(S0, beg0 + (int)threadIdx.x, pre1);
 
@@ -545,7 +732,9 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     uint32_t fbits = 0;
     unsigned nfb = 0;
     const SegQueue Q = {sQ, &sQn};
-    if (interior)
+    if constexpr (ORDER == 2)
+        push_tile2<TL>(A, T, tile, sF, sJ, fbits, nfb);
+    else if (interior)
         push_tile<TL, true>(A, T, tile, sparse0, beg0, end0, pre1, sF, sJ, Q, fbits, nfb);
     else
         push_tile<TL, false>(A, T, tile, sparse0, beg0, end0, pre1, sF, sJ, Q, fbits, nfb);
@@ -553,7 +742,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     else if (nfb) atomicOr(A.fault, (uint32_t)EMPIC_FAULT_FALLBACK);
     if (nfb) atomicAdd(A.fallback, (unsigned long long)nfb);
     __syncthreads();
-    if constexpr (TL::QCAP > 0) {
+    if constexpr (TL::QCAP > 0 && ORDER == 1) {
         // the queued second segments
         static_assert(TL::JW3 <= 2048, "window index in the 11 bits of a queue entry's code");
         const int nq = (int)min(sQn, (unsigned)TL::QCAP);
@@ -607,6 +796,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
 // Out-of-window particles of this step, whole particle through global memory
 // (gather from E and Bbar, global atomic deposit).  The last workgroup to
 // finish resets the list for the next step.
+template <int ORDER>
 __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
     const unsigned n = *(volatile unsigned *)A.fb_count;
     const unsigned m = n < (unsigned long long)A.fb_cap ? n : (unsigned)A.fb_cap;
@@ -621,7 +811,7 @@ __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
         float ox = ((float *)S.pos[0])[p], oy = ((float *)S.pos[1])[p], oz = ((float *)S.pos[2])[p];
         float ux = ((float *)S.u[0])[p], uy = ((float *)S.u[1])[p], uz = ((float *)S.u[2])[p];
         const float wq = (S.per_particle_w && S.w) ? ((const float *)S.w)[p] : 1.f;
-        particle_global(A, D, c, ox, oy, oz, ux, uy, uz, wq, fbits);
+        particle_global<ORDER>(A, D, c, ox, oy, oz, ux, uy, uz, wq, fbits);
         Wr.cell[p] = c;
         ((float *)Wr.pos[0])[p] = ox;
         ((float *)Wr.pos[1])[p] = oy;
@@ -669,7 +859,10 @@ __global__ void k_dry_push_f32(GridP g, const float *Ex, const float *Ey, const 
         float ux = ((const float *)sp.u[0])[p], uy = ((const float *)sp.u[1])[p],
               uz = ((const float *)sp.u[2])[p];
         float Ep[3], Bp[3];
-        gather_global(g, E, Bb, cell_i(c), cell_j(c), cell_k(c), ox, oy, oz, Ep, Bp);
+        if (g.shape_order == 2)
+            gather2_global(g, E, Bb, cell_i(c), cell_j(c), cell_k(c), ox, oy, oz, Ep, Bp);
+        else
+            gather_global(g, E, Bb, cell_i(c), cell_j(c), cell_k(c), ox, oy, oz, Ep, Bp);
         float gam;
         boris_f32(ux, uy, uz, Ep, Bp, r, r_lo, gam);
         if (!isfinite(gam)) atomicOr(fault, (uint32_t)EMPIC_FAULT_NONFINITE);
@@ -697,6 +890,42 @@ __global__ void k_kinetic_f32(SpeciesP sp, double *partial) {
     }
     const double t = block_reduce<false>(ks, sm);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// b_2 charge density at nodes (second-order shapes), FP64 global atomics
+__global__ void k_rho2_f32(GridP g, SpeciesP sp, double *rho) {
+    const long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (p >= *sp.count) return;
+    const uint32_t c = sp.cell[p];
+    if (c == DEAD) return;
+    const float *WP = (sp.per_particle_w && sp.w) ? (const float *)sp.w : nullptr;
+    const double dV = g.d[0] * g.d[1] * g.d[2];
+    const double qsp = sp.q * (WP ? (double)WP[p] : sp.w_species);
+    const int ci[3] = {cell_i(c), cell_j(c), cell_k(c)};
+    int m[3];
+    double w[3][3];
+    for (int a = 0; a < 3; ++a) {
+        const double o = ((const float *)sp.pos[a])[p];
+        m[a] = ci[a] + (o >= 0.5 ? 1 : 0);
+        const double d = o - (o >= 0.5 ? 1.0 : 0.0);
+        w[a][0] = 0.5 * (0.5 - d) * (0.5 - d);
+        w[a][1] = 0.75 - d * d;
+        w[a][2] = 0.5 * (0.5 + d) * (0.5 + d);
+    }
+    for (int k = 0; k < 3; ++k) {
+        const int gz = gaxis(g, 2, m[2] - 1 + k);
+        if (gz < 0) continue;
+        for (int j = 0; j < 3; ++j) {
+            const int gy = gaxis(g, 1, m[1] - 1 + j);
+            if (gy < 0) continue;
+            for (int i = 0; i < 3; ++i) {
+                const int gx = gaxis(g, 0, m[0] - 1 + i);
+                if (gx < 0) continue;
+                atomicAdd(rho + gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz),
+                          qsp / dV * w[0][i] * w[1][j] * w[2][k]);
+            }
+        }
+    }
 }
 
 __global__ void k_rho_f32(GridP g, SpeciesP sp, double *rho) {
@@ -1248,14 +1477,14 @@ void launch_write_species(DevSpecies *dst, const DevSpecies &v, hipStream_t s) {
 }
 
 namespace {
-template <class TL>
+template <class TL, int ORDER>
 void launch_fused(const FusedArgs &A, int nb, hipStream_t s, hipEvent_t ev_start,
                   hipEvent_t ev_stop) {
     if (ev_start)  // timestamps taken by the dispatch itself
-        hipExtLaunchKernelGGL(k_push_fused<TL>, dim3(nb), dim3(PUSH_THREADS), 0, s, ev_start,
-                              ev_stop, 0, A);
+        hipExtLaunchKernelGGL((k_push_fused<TL, ORDER>), dim3(nb), dim3(PUSH_THREADS), 0, s,
+                              ev_start, ev_stop, 0, A);
     else
-        hipLaunchKernelGGL(k_push_fused<TL>, dim3(nb), dim3(PUSH_THREADS), 0, s, A);
+        hipLaunchKernelGGL((k_push_fused<TL, ORDER>), dim3(nb), dim3(PUSH_THREADS), 0, s, A);
 }
 }  // namespace
 
@@ -1289,11 +1518,14 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
     A.publish = publish;
     const int nb = 8 * ((ti.ntiles + 7) / 8);
     if (fallback_pass)
-        hipLaunchKernelGGL(k_push_fallback, dim3(64), dim3(256), 0, s, A);
+        hipLaunchKernelGGL(g.shape_order == 2 ? k_push_fallback<2> : k_push_fallback<1>, dim3(64),
+                           dim3(256), 0, s, A);
     else if (ti.slab)
-        launch_fused<TileSlab>(A, nb, s, ev_start, ev_stop);
+        launch_fused<TileSlab, 1>(A, nb, s, ev_start, ev_stop);  // order 2 is refused on slab grids
+    else if (g.shape_order == 2)
+        launch_fused<TileCube, 2>(A, nb, s, ev_start, ev_stop);
     else
-        launch_fused<TileCube>(A, nb, s, ev_start, ev_stop);
+        launch_fused<TileCube, 1>(A, nb, s, ev_start, ev_stop);
 }
 
 void launch_dry_push_f32(const GridP &g, float *const E[3], float *const Bbar[3],
@@ -1312,6 +1544,10 @@ void launch_kinetic_f32(const SpeciesP &sp, double *partial_slot, hipStream_t s)
 void launch_rho_f32(const GridP &g, const TileInfo &ti, bool tiles_valid, double scale,
                     const SpeciesP &sp, double *rho, hipStream_t s) {
     if (sp.capacity <= 0) return;
+    if (g.shape_order == 2) {
+        hipLaunchKernelGGL(k_rho2_f32, dim3(nblk(sp.capacity, 256)), dim3(256), 0, s, g, sp, rho);
+        return;
+    }
     const unsigned nb = 8 * ((ti.ntiles + 7) / 8);
     if (tiles_valid && ti.slab)
         hipLaunchKernelGGL(k_rho_tiles<TileSlab>, dim3(nb), dim3(256), 0, s, g, ti, sp, scale, rho);

@@ -30,11 +30,12 @@ class Sim:
     paper_2609_16575_amd.workloads.Workload.  static_workspace=True creates
     the handle with empic_create_static (the library's per-device workspace,
     one live handle per device; no device allocation by the library).
+    shape_order=2: second-order shapes (b_2 weighting, EZ current).
     """
 
     def __init__(self, workload, precision: str = "fp32", device: Optional[str] = None,
                  sort_every: Optional[int] = None, capacity_slack: float = 0.0,
-                 static_workspace: bool = False):
+                 static_workspace: bool = False, shape_order: int = 1):
         import torch
         self.torch = torch
         self.L = LB.lib()
@@ -109,6 +110,8 @@ class Sim:
         for i, s in enumerate(workload.species):
             self._add_species(s, self.caps[i])
         LB.check(h, self.L.empic_set_background(h, float(workload.rho_bg)))
+        if shape_order != 1:
+            LB.check(h, self.L.empic_set_shape_order(h, int(shape_order)))
         if workload.laser is not None:
             Ls = workload.laser
             ld = LB.LaserDesc(Ls.a0, Ls.w0, Ls.tau, Ls.t0, Ls.omega0, Ls.yc, Ls.zc, int(Ls.i_s), 1,

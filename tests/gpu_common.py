@@ -4,8 +4,9 @@ import numpy as np
 from oracle import oracle as O
 
 
-def oracle_from(w, E0=None, B0=None):
+def oracle_from(w, E0=None, B0=None, order=1):
     sim = O.OracleSim(w.n, w.d, w.dt, w.bc)
+    sim.shape_order = order
     if E0 is not None:
         sim.E[...] = E0
     if B0 is not None:
@@ -61,13 +62,14 @@ def compare_state(gpu, orc, w, sp_tol, f_tol, label=""):
     return errs
 
 
-def check_box_currents(g, w, boxes, tol, margin=2):
+def check_box_currents(g, w, boxes, tol, margin=2, order=1):
     """One step of the GPU run `g`, with J compared element-wise with the
     oracle's inside each box (lo, hi) of cells: the oracle takes the GPU's
     fields and every particle within `margin` cells of the box (a particle
-    moves at most one cell, so these are all that deposit inside it) and
-    steps once.  Returns the largest relative difference (to max |J| over
-    the box)."""
+    moves at most one cell, so these are all that deposit inside it; a
+    second-order stencil reaches one cell further: margin 3) and steps once
+    with the given shape order.  Returns the largest relative difference (to
+    max |J| over the box)."""
     E, B, _ = g.fields()
     parts = []
     for i in range(len(w.species)):
@@ -85,6 +87,7 @@ def check_box_currents(g, w, boxes, tol, margin=2):
     g.step(1)
     _, _, Jg = g.fields()
     o = O.OracleSim(w.n, w.d, w.dt, w.bc)
+    o.shape_order = order
     o.E[...] = E
     o.B[...] = B
     for i, (P, U, I) in enumerate(parts):
