@@ -16,7 +16,9 @@ the fused FP32 particle kernel; its roofline entry uses the algorithmic bytes
 56 per particle (28 read + 28 written) + 36 per cell (E and centred B read,
 J written) per launch over its HIP-event-timed average duration.  The
 "adjoint" entry times a 50-step forward + adjoint on a 128^3 anisotropic
-plasma (see adjoint_leg).
+plasma (see adjoint_leg); "shape_order_2" the same plasma stepped with
+second-order shapes (b_2 weighting, EZ current).  cpu_baseline: the FP64
+oracle on one core, 2 steps of a 64^3 box of the same plasma.
 """
 from __future__ import annotations
 
@@ -83,7 +85,9 @@ def traffic_from_counters(nbytes_alg):
 
 
 def cpu_baseline(n=(64, 64, 64), steps=2):
-    """The FP64 oracle (single thread) on a 64^3 box of the same workload."""
+    """The FP64 oracle (single thread) on a 64^3 box of the same plasma (same
+    density, temperatures and cell size), 2 steps: 10-20 s of CPU work.
+    One step of the whole 128^3 box takes about a minute on one core."""
     from oracle import oracle as O
     from paper_2609_16575_amd import workloads as W
     w = W.thermal_two_species(n=n)
@@ -95,8 +99,8 @@ def cpu_baseline(n=(64, 64, 64), steps=2):
     dt = time.perf_counter() - t0
     return {"value": w.n_particles * steps / dt, "unit": "particle-pushes/s", "cores": 1,
             "kind": "oracle",
-            "sample": "%d steps of the same workload on a %dx%dx%d box (%d particles), "
-                      "single-threaded FP64 C, %.1f s" % (steps, *n, w.n_particles, dt)}
+            "sample": "%d steps of the same plasma on a %dx%dx%d box (%d particles), "
+                      "single-threaded FP64 C, %.1f s" % (steps, *w.n, w.n_particles, dt)}
 
 
 def adjoint_leg(torch, n=128, steps=50, K=10):
@@ -246,7 +250,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64", "adjoint", "fields"], default=None)
+    ap.add_argument("--only", choices=["fp32", "order2", "fp64", "adjoint", "fields"],
+                    default=None)
     ap.add_argument("--workload", choices=["thermal", "lwfa", "weibel256", "lwfa2d"],
                     default="thermal", help="thermal (the benchmark) or another workload's FP32 step")
     args = ap.parse_args()
@@ -303,6 +308,27 @@ def main():
         out["fp32_checks"] = {"fault_word": d["fault_word"],
                               "fallback_particles": d["fallback_particles"],
                               "U_tot": d["U_tot"]}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+
+    if args.only in (None, "order2"):
+        # the same plasma with second-order shapes (b_2 weighting, EZ current)
+        sim = Sim(w, precision="fp32", sort_every=-1, shape_order=2)
+        _log("order-2 sim ready")
+        wall, kt = time_steps(sim, args.steps, args.warmup, torch, events="push")
+        d = sim.diagnostics()
+        push_ms = kt["push_ms"] / max(kt["push_n"], 1)
+        nbytes = 56.0 * npart + 36.0 * ncell
+        achieved = nbytes / (push_ms * 1e-3) / 1e9
+        out["shape_order_2"] = {
+            "value": npart * args.steps / wall, "unit": "particle-pushes/s",
+            "ms_per_step": 1e3 * wall / args.steps,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_push_fused (order 2)", "avg_ms": push_ms,
+                         "algorithmic_bytes_per_launch": nbytes},
+            "fault_word": d["fault_word"], "fallback_particles": d["fallback_particles"]}
         sim.close()
         del sim
         torch.cuda.empty_cache()
