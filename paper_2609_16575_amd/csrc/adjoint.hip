@@ -40,7 +40,7 @@ namespace {
 constexpr int ADJ_THREADS = 256;   // particle pass
 constexpr int SCAT_THREADS = 512;  // scatter pass
 constexpr int APPT = 1;            // particles per thread and pass-1 iteration
-constexpr int SPPT = 2;            // consecutive particles per thread in pass 2
+constexpr int SPPT = 4;            // consecutive particles per thread in pass 2
 constexpr int EB = 31;             // fixed point: contributions below 2^EB
 typedef float vfA __attribute__((ext_vector_type(APPT)));
 typedef uint32_t vuA __attribute__((ext_vector_type(APPT)));
@@ -563,7 +563,8 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
 // units of 2^(tile_exp - 31): every contribution is below 2^31 there and is
 // rounded to an int32 (error <= 2^-32 of the tile's largest |lam|); one
 // entry takes at most one contribution per particle, so the sum cannot
-// overflow.  Lanes of a wave take particles 16 apart, in different cells.
+// overflow.  A lane takes SPPT consecutive particles and the lanes of a wave
+// are SPPT x 8 = 32 particles apart, in different cells.
 template <class TL>
 __global__ __launch_bounds__(SCAT_THREADS) void k_adj_scatter(AdjArgs A, AdjSpecies S) {
     constexpr int FWX = TL::FWX, FWY = TL::FWY, FW3 = TL::FW3;

@@ -31,7 +31,7 @@ inline size_t up_align(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t Bbar, fault, table, partials, result, rho_cur, rho_prev, tile_off, counts, scan, rank,
-        fb_list, adj, jfix, filt, mur, total;
+        fb_list, fb_mask, adj, jfix, filt, mur, total;
     size_t tile_off_stride;
     long long mur_stride;
 };
@@ -95,7 +95,9 @@ Layout layout(const empic_grid_desc *d, int max_species, long long max_capacity)
     o += up_align(((size_t)(ti.NK + 1023) / 1024 + 2) * 4);
     L.rank = o;
     o += up_align((size_t)max_capacity * 4);
-    L.fb_list = o;  // out-of-window list: every slot of every species fits
+    L.fb_mask = o;  // out-of-window marks of the FP32 step: one bit per slot and species
+    o += up_align((size_t)max_species * (size_t)((max_capacity + 31) / 32) * 4);
+    L.fb_list = o;  // out-of-window list of the adjoint: every slot of every species fits
     o += up_align((size_t)max_capacity * max_species * 8);
     L.adj = o;      // adjoint accumulators (FP32 path): gather lam_E, lam_Bbar, lam_B'
     o += d->precision == EMPIC_FP64_PLAIN ? 0 : up_align((size_t)9 * g.V * 4);
@@ -158,6 +160,8 @@ struct empic_sim {
     int32_t *counts = nullptr, *scan_blocks = nullptr, *rank = nullptr;
     void *mur = nullptr;
     int2 *fb_list = nullptr;
+    uint32_t *fb_mask = nullptr;
+    long long mask_words = 0;
     unsigned *fb_count = nullptr;
     float *adj = nullptr;
     unsigned long long *jfix[3]{};  // FP32 path: the current as exact int64 sums
@@ -380,8 +384,8 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
             for (int pass = 0; pass < 2; ++pass)
                 launch_push_fused(s->g, s->ti, (float *const *)E, (float *const *)Bb,
                                   s->jfix, tbl, s->nsp, rmask, wmask, s->fault,
-                                  s->fallback, s->fb_list, s->fb_count,
-                                  (long long)s->max_capacity * s->max_species, s->jscale,
+                                  s->fallback, s->fb_mask, s->mask_words, s->fb_count,
+                                  s->jscale,
                                   pass == 1, s->stream, pass == 0 ? tp.a : nullptr,
                                   pass == 0 ? tp.b : nullptr, pass == 1 ? publish : nullptr);
             if (s->timing) s->events.push_back(tp);
@@ -575,6 +579,8 @@ bool init_handle(empic_sim *s, const empic_grid_desc *g, const Layout &L, int32_
     s->rank = (int32_t *)(s->ws + L.rank);
     s->mur = s->ws + L.mur;
     s->fb_list = (int2 *)(s->ws + L.fb_list);
+    s->fb_mask = (uint32_t *)(s->ws + L.fb_mask);
+    s->mask_words = (max_capacity + 31) / 32;
     s->adj = (float *)(s->ws + L.adj);
     if (g->precision == EMPIC_FP32_CELLREL)
         for (int a = 0; a < 3; ++a)
@@ -586,8 +592,11 @@ bool init_handle(empic_sim *s, const empic_grid_desc *g, const Layout &L, int32_
         s->sp[i].tile_off = (int32_t *)(s->ws + L.tile_off + (size_t)i * L.tile_off_stride);
         s->sp[i].dcount = s->sp[i].tile_off + (s->ti.ntiles + 1);
     }
-    // zero the fault word, counters and the Bbar array (a fill kernel; no memset nodes)
+    // zero the fault word, counters, the out-of-window marks and the Bbar array
+    // (fill kernels; no memset nodes)
     launch_fill_i32((int32_t *)(s->ws + L.fault), 16, 0, s->stream);
+    launch_fill_i32((int32_t *)(s->ws + L.fb_mask),
+                    (long long)max_species * ((max_capacity + 31) / 32), 0, s->stream);
     launch_fill_i32((int32_t *)(s->ws + L.Bbar), (long long)(3 * s->g.V * es / 4), 0, s->stream);
     bool ok = true;
     if (g->sort_every < 0 && g->precision == EMPIC_FP32_CELLREL) {

@@ -50,9 +50,9 @@ struct FusedArgs {
     double jscale, jinv;    // fixed-point scale of the current (LDS window and Jf) and its inverse
     uint32_t *fault;
     unsigned long long *fallback;  // cumulative count of out-of-window particles
-    int2 *fb_list;                 // (species, slot) of this step's out-of-window particles
-    unsigned *fb_count;            // [0] entries in fb_list, [1] block ticket of k_push_fallback
-    long long fb_cap;
+    uint32_t *fb_mask;             // bit p of species s's words: slot p is out of its window
+    long long mask_words;          // words per species in fb_mask
+    unsigned *fb_count;            // [0] particles marked this step, [1] block ticket of k_push_fallback
     unsigned long long *publish;   // host-visible copy of *fallback (k_push_fallback), or null
 };
 
@@ -214,6 +214,18 @@ __device__ __forceinline__ void second_segment(const float o[3], const float dx[
     }
 }
 
+// Marks particle (s, p) for k_push_fallback when `outside`: a bit in the
+// out-of-window mask, set by an atomic whose result is not waited for (a
+// list slot claimed with a returning atomic made every wave with such a
+// particle wait for the round trip).  True when marked.
+__device__ __forceinline__ bool list_fallback(const FusedArgs &A, bool outside, int s, int p,
+                                              unsigned &nfb) {
+    if (!outside) return false;
+    ++nfb;
+    atomicOr(A.fb_mask + (long long)s * A.mask_words + (p >> 5), 1u << (p & 31));
+    return true;
+}
+
 // Queue of second ZigZag segments (TL::QCAP entries of 32 bytes): per entry
 // the particle's offset o and move dx (cell units), a code word (the
 // current-window index of its cell in bits 0-10, the cell step + 1 per axis
@@ -304,16 +316,12 @@ __device__ __forceinline__ void push_species(const FusedArgs &A, const DevSpecie
                 ly = local_axis(g, 1, cell_j(c), T.wo[1]);
                 lz = local_axis(g, 2, cell_k(c), T.wo[2]);
             }
-            if (!((unsigned)(lx - 1) < (unsigned)LHI_X && (unsigned)(ly - 1) < (unsigned)LHI_Y &&
-                  (unsigned)(lz - 1) < (unsigned)LHI_Z)) {
-                // drifted out of the tile window since the last sort: pushed
-                // by k_push_fallback
-                ++nfb;
-                const unsigned slot = atomicAdd(A.fb_count, 1u);
-                if (slot < (unsigned long long)A.fb_cap) A.fb_list[slot] = make_int2(s, p);
-                else fbits |= EMPIC_FAULT_CELL;
-                continue;
-            }
+            // drifted out of the tile window since the last sort: listed for
+            // k_push_fallback
+            const bool outside = !((unsigned)(lx - 1) < (unsigned)LHI_X &&
+                                   (unsigned)(ly - 1) < (unsigned)LHI_Y &&
+                                   (unsigned)(lz - 1) < (unsigned)LHI_Z);
+            if (list_fallback(A, outside, s, p, nfb)) continue;
             const float ox = b.ox[k], oy = b.oy[k], oz = b.oz[k];
             // a NaN offset is caught below as a non-finite momentum
             if (!(fminf(fminf(ox, oy), oz) >= 0.f && fmaxf(fmaxf(ox, oy), oz) < 1.f))
@@ -506,15 +514,10 @@ __device__ __forceinline__ void push_species2(const FusedArgs &A, const DevSpeci
             const int ly = local_axis(g, 1, cell_j(c), T.wo[1]);
             const int lz = local_axis(g, 2, cell_k(c), T.wo[2]);
             // inside the tile: window indices MARGIN + 1 .. MARGIN + T
-            if (!((unsigned)(lx - MARGIN - 1) < (unsigned)TX &&
-                  (unsigned)(ly - MARGIN - 1) < (unsigned)TY &&
-                  (unsigned)(lz - MARGIN - 1) < (unsigned)TZ)) {
-                ++nfb;
-                const unsigned slot = atomicAdd(A.fb_count, 1u);
-                if (slot < (unsigned long long)A.fb_cap) A.fb_list[slot] = make_int2(s, p);
-                else fbits |= EMPIC_FAULT_CELL;
-                continue;
-            }
+            const bool outside = !((unsigned)(lx - MARGIN - 1) < (unsigned)TX &&
+                                   (unsigned)(ly - MARGIN - 1) < (unsigned)TY &&
+                                   (unsigned)(lz - MARGIN - 1) < (unsigned)TZ);
+            if (list_fallback(A, outside, s, p, nfb)) continue;
             const float o[3] = {b.ox[k], b.oy[k], b.oz[k]};
             if (!(fminf(fminf(o[0], o[1]), o[2]) >= 0.f && fmaxf(fmaxf(o[0], o[1]), o[2]) < 1.f))
                 fbits |= EMPIC_FAULT_OFFSET;
@@ -740,7 +743,10 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
         push_tile<TL, false>(A, T, tile, sparse0, beg0, end0, pre1, sF, sJ, Q, fbits, nfb);
     if (fbits) atomicOr(A.fault, fbits | (nfb ? EMPIC_FAULT_FALLBACK : 0u));
     else if (nfb) atomicOr(A.fault, (uint32_t)EMPIC_FAULT_FALLBACK);
-    if (nfb) atomicAdd(A.fallback, (unsigned long long)nfb);
+    if (nfb) {
+        atomicAdd(A.fallback, (unsigned long long)nfb);
+        atomicAdd(A.fb_count, nfb);
+    }
     __syncthreads();
     if constexpr (TL::QCAP > 0 && ORDER == 1) {
         // the queued second segments
@@ -794,34 +800,44 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
 }
 
 // Out-of-window particles of this step, whole particle through global memory
-// (gather from E and Bbar, global atomic deposit).  The last workgroup to
-// finish resets the list for the next step.
+// (gather from E and Bbar, global atomic deposit): the marked bits of the
+// mask, each word cleared once read.  Nothing to scan when the step marked
+// none.  The last workgroup to finish resets the count for the next step.
 template <int ORDER>
 __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
     const unsigned n = *(volatile unsigned *)A.fb_count;
-    const unsigned m = n < (unsigned long long)A.fb_cap ? n : (unsigned)A.fb_cap;
     uint32_t fbits = 0;
-    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
-        const int2 e = A.fb_list[t];
-        const DevSpecies &D = A.tbl[e.x];
-        const SpeciesP &S = D.p[(A.cur_mask >> e.x) & 1u];
-        const SpeciesP &Wr = D.p[(A.wr_mask >> e.x) & 1u];
-        const int p = e.y;
-        uint32_t c = S.cell[p];
-        float ox = ((float *)S.pos[0])[p], oy = ((float *)S.pos[1])[p], oz = ((float *)S.pos[2])[p];
-        float ux = ((float *)S.u[0])[p], uy = ((float *)S.u[1])[p], uz = ((float *)S.u[2])[p];
-        const float wq = (S.per_particle_w && S.w) ? ((const float *)S.w)[p] : 1.f;
-        particle_global<ORDER>(A, D, c, ox, oy, oz, ux, uy, uz, wq, fbits);
-        Wr.cell[p] = c;
-        ((float *)Wr.pos[0])[p] = ox;
-        ((float *)Wr.pos[1])[p] = oy;
-        ((float *)Wr.pos[2])[p] = oz;
-        ((float *)Wr.u[0])[p] = ux;
-        ((float *)Wr.u[1])[p] = uy;
-        ((float *)Wr.u[2])[p] = uz;
+    const long long nw = (long long)A.nsp * A.mask_words;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; n != 0 && t < nw;
+         t += (long long)gridDim.x * blockDim.x) {
+        uint32_t bits = A.fb_mask[t];
+        if (!bits) continue;
+        A.fb_mask[t] = 0u;
+        const int s = (int)(t / A.mask_words);
+        const int p0 = (int)(t - (long long)s * A.mask_words) * 32;
+        const DevSpecies &D = A.tbl[s];
+        const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
+        const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
+        while (bits) {
+            const int p = p0 + __builtin_ctz(bits);
+            bits &= bits - 1u;
+            uint32_t c = S.cell[p];
+            float ox = ((float *)S.pos[0])[p], oy = ((float *)S.pos[1])[p],
+                  oz = ((float *)S.pos[2])[p];
+            float ux = ((float *)S.u[0])[p], uy = ((float *)S.u[1])[p], uz = ((float *)S.u[2])[p];
+            const float wq = (S.per_particle_w && S.w) ? ((const float *)S.w)[p] : 1.f;
+            particle_global<ORDER>(A, D, c, ox, oy, oz, ux, uy, uz, wq, fbits);
+            Wr.cell[p] = c;
+            ((float *)Wr.pos[0])[p] = ox;
+            ((float *)Wr.pos[1])[p] = oy;
+            ((float *)Wr.pos[2])[p] = oz;
+            ((float *)Wr.u[0])[p] = ux;
+            ((float *)Wr.u[1])[p] = uy;
+            ((float *)Wr.u[2])[p] = uz;
+        }
     }
     if (fbits) atomicOr(A.fault, fbits);
-    // reset the list once every workgroup has read the count
+    // reset the count once every workgroup has read it
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -1492,7 +1508,8 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
                        float *const Bbar[3], unsigned long long *const Jf[3],
                        const DevSpecies *tbl, int nsp,
                        unsigned cur_mask, unsigned wr_mask, uint32_t *fault, unsigned long long *fallback,
-                       int2 *fb_list, unsigned *fb_count, long long fb_cap, double jscale,
+                       uint32_t *fb_mask, long long mask_words, unsigned *fb_count,
+                       double jscale,
                        bool fallback_pass, hipStream_t s, hipEvent_t ev_start,
                        hipEvent_t ev_stop, unsigned long long *publish) {
     FusedArgs A;
@@ -1512,14 +1529,16 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
     A.jinv = 1.0 / jscale;
     A.fault = fault;
     A.fallback = fallback;
-    A.fb_list = fb_list;
+    A.fb_mask = fb_mask;
+    A.mask_words = mask_words;
     A.fb_count = fb_count;
-    A.fb_cap = fb_cap;
     A.publish = publish;
     const int nb = 8 * ((ti.ntiles + 7) / 8);
     if (fallback_pass)
-        hipLaunchKernelGGL(g.shape_order == 2 ? k_push_fallback<2> : k_push_fallback<1>, dim3(64),
-                           dim3(256), 0, s, A);
+        // a grid that fills the chip: after many steps without a sort (or with
+        // order 2, which keeps no drift margin) the list is long
+        hipLaunchKernelGGL(g.shape_order == 2 ? k_push_fallback<2> : k_push_fallback<1>,
+                           dim3(1024), dim3(256), 0, s, A);
     else if (ti.slab)
         launch_fused<TileSlab, 1>(A, nb, s, ev_start, ev_stop);  // order 2 is refused on slab grids
     else if (g.shape_order == 2)
