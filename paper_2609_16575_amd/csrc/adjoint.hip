@@ -163,9 +163,8 @@ struct AdjArgs {
     float dtd[3], dtd_lo[3];  // dt / d_a and dt as FP32 pairs (split_f32)
     float inv_d[3];
     float dt, dt_lo;
-    int *fb_list;        // slots of this species' particles outside their tile window
-    unsigned *fb_count;  // entries in fb_list
-    long long fb_cap;
+    uint32_t *fb_mask;   // bit p: slot p of this species is outside its tile window
+    unsigned *fb_count;  // marked particles
     float *l6[6];        // per slot: lam_Ep, lam_Bp from pass 1 (scratch)
     int *tile_exp;       // per tile: exponent bound of its lam_Ep, lam_Bp
 };
@@ -515,14 +514,11 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
                 }
             } else {
                 // drifted more than MARGIN cells out of its tile since the sort:
-                // listed for k_adj_fallback (its adjoints stay as loaded here)
-                const unsigned slot = atomicAdd(A.fb_count, 1u);
-                if (slot < (unsigned long long)A.fb_cap) {
-                    A.fb_list[slot] = p;
-                    continue;
-                }
-                particle_vjp(gacc, A, S, gl, o, u, w4[k], lx, lu, l6);
-                scatter_global(gacc, A.lEg, A.lBb, gl, o, l6);
+                // marked for k_adj_fallback (its adjoints stay as loaded here);
+                // atomics whose results are not waited for
+                atomicOr(A.fb_mask + (p >> 5), 1u << (p & 31));
+                atomicAdd(A.fb_count, 1u);
+                continue;
             }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -639,15 +635,22 @@ __global__ __launch_bounds__(SCAT_THREADS) void k_adj_scatter(AdjArgs A, AdjSpec
     }
 }
 
-// Listed out-of-window particles, entirely through global memory.
-__global__ __launch_bounds__(256) void k_adj_fallback(AdjArgs A, AdjSpecies S) {
+// Marked out-of-window particles, entirely through global memory: the set
+// bits of the species' mask words, each word cleared once read (nothing to
+// scan when none was marked).
+__global__ __launch_bounds__(256) void k_adj_fallback(AdjArgs A, AdjSpecies S, long long words) {
     const unsigned n = *(volatile unsigned *)A.fb_count;
-    const unsigned m = n < (unsigned long long)A.fb_cap ? n : (unsigned)A.fb_cap;
     const GlobAcc gacc{A.g.n[0], A.g.n[1], A.g.n[2], A.g.ext[0], A.g.ext[1],
                        {A.E[0], A.E[1], A.E[2]}, {A.Bb[0], A.Bb[1], A.Bb[2]},
                        {A.lJ[0], A.lJ[1], A.lJ[2]}};
-    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
-        const int p = A.fb_list[t];
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; n != 0 && t < words;
+         t += (long long)gridDim.x * blockDim.x) {
+      uint32_t bits = A.fb_mask[t];
+      if (!bits) continue;
+      A.fb_mask[t] = 0u;
+      while (bits) {
+        const int p = (int)(t * 32) + __builtin_ctz(bits);
+        bits &= bits - 1u;
         const uint32_t c = S.cell[p];
         const int gl[3] = {cell_i(c), cell_j(c), cell_k(c)};
         const float o[3] = {S.pos[0][p], S.pos[1][p], S.pos[2][p]};
@@ -663,6 +666,7 @@ __global__ __launch_bounds__(256) void k_adj_fallback(AdjArgs A, AdjSpecies S) {
             S.lx[a][p] = lx[a];
             S.lu[a][p] = lu[a];
         }
+      }
     }
 }
 
@@ -756,8 +760,8 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
                      float *const lEg[3],
                      float *const lBb[3], float *const tB[3], const SpeciesP *sp,
                      const int32_t *const *tile_off, float *const (*lx)[3],
-                     float *const (*lu)[3], int nsp, int *fb_list, unsigned *fb_count,
-                     long long fb_cap, float *const (*l6)[6], int *tile_exp, hipStream_t s) {
+                     float *const (*lu)[3], int nsp, uint32_t *fb_mask, unsigned *fb_count,
+                     float *const (*l6)[6], int *tile_exp, hipStream_t s) {
     for (int a = 0; a < 3; ++a) {
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, lEg[a], g.V);
         hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, lBb[a], g.V);
@@ -775,7 +779,7 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
         A.inv_d[a] = (float)(1.0 / g.d[a]);
     }
     split_f32(g.dt, A.dt, A.dt_lo);
-    A.fb_list = fb_list;
+    A.fb_mask = fb_mask;
     A.fb_count = fb_count;
     A.tile_exp = tile_exp;
     const double dV = g.d[0] * g.d[1] * g.d[2];
@@ -796,7 +800,6 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
         split_f32(sp[i].q * g.dt / (2.0 * sp[i].m), S.r, S.r_lo);
         const double w = sp[i].per_particle_w ? 1.0 : sp[i].w_species;
         for (int a = 0; a < 3; ++a) split_f32(sp[i].q * w * g.d[a] / (g.dt * dV), S.qc[a], S.qc_lo[a]);
-        A.fb_cap = fb_cap < sp[i].capacity ? fb_cap : sp[i].capacity;
         for (int q = 0; q < 6; ++q) A.l6[q] = l6[i][q];
         launch_fill_i32((int32_t *)fb_count, 1, 0, s);
         if (ti.slab)
@@ -805,7 +808,8 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
         else
             hipLaunchKernelGGL(k_adj_particles<TileCube>, dim3(nblocks), dim3(ADJ_THREADS), 0, s,
                                A, S);
-        hipLaunchKernelGGL(k_adj_fallback, dim3(64), dim3(256), 0, s, A, S);
+        hipLaunchKernelGGL(k_adj_fallback, dim3(1024), dim3(256), 0, s, A, S,
+                           (long long)((sp[i].capacity + 31) / 32));
         launch_fill_i32((int32_t *)fb_count, 1, 0, s);  // the step kernels expect it empty
         if (ti.slab)
             hipLaunchKernelGGL(k_adj_scatter<TileSlab>, dim3(nblocks), dim3(SCAT_THREADS), 0, s,

@@ -31,7 +31,7 @@ inline size_t up_align(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t Bbar, fault, table, partials, result, rho_cur, rho_prev, tile_off, counts, scan, rank,
-        fb_list, fb_mask, adj, jfix, filt, mur, total;
+        fb_mask, adj, jfix, filt, mur, total;
     size_t tile_off_stride;
     long long mur_stride;
 };
@@ -95,10 +95,8 @@ Layout layout(const empic_grid_desc *d, int max_species, long long max_capacity)
     o += up_align(((size_t)(ti.NK + 1023) / 1024 + 2) * 4);
     L.rank = o;
     o += up_align((size_t)max_capacity * 4);
-    L.fb_mask = o;  // out-of-window marks of the FP32 step: one bit per slot and species
+    L.fb_mask = o;  // out-of-window marks (FP32 step, adjoint): one bit per slot and species
     o += up_align((size_t)max_species * (size_t)((max_capacity + 31) / 32) * 4);
-    L.fb_list = o;  // out-of-window list of the adjoint: every slot of every species fits
-    o += up_align((size_t)max_capacity * max_species * 8);
     L.adj = o;      // adjoint accumulators (FP32 path): gather lam_E, lam_Bbar, lam_B'
     o += d->precision == EMPIC_FP64_PLAIN ? 0 : up_align((size_t)9 * g.V * 4);
     L.jfix = o;     // FP32 path: the step's current as int64 sums (units 1/jscale)
@@ -159,7 +157,6 @@ struct empic_sim {
     double *partials = nullptr, *result = nullptr, *rho_cur = nullptr, *rho_prev = nullptr;
     int32_t *counts = nullptr, *scan_blocks = nullptr, *rank = nullptr;
     void *mur = nullptr;
-    int2 *fb_list = nullptr;
     uint32_t *fb_mask = nullptr;
     long long mask_words = 0;
     unsigned *fb_count = nullptr;
@@ -578,7 +575,6 @@ bool init_handle(empic_sim *s, const empic_grid_desc *g, const Layout &L, int32_
     s->scan_blocks = (int32_t *)(s->ws + L.scan);
     s->rank = (int32_t *)(s->ws + L.rank);
     s->mur = s->ws + L.mur;
-    s->fb_list = (int2 *)(s->ws + L.fb_list);
     s->fb_mask = (uint32_t *)(s->ws + L.fb_mask);
     s->mask_words = (max_capacity + 31) / 32;
     s->adj = (float *)(s->ws + L.adj);
@@ -1284,8 +1280,7 @@ empic_status empic_step_vjp(empic_sim *s, const empic_state *st, const empic_adj
         for (int a = 0; a < 3; ++a) lJdep[a] = fl[a];
     }
     launch_step_vjp(s->g, s->ti, E, Bb, lE, lJdep, lB, lEg, lBb, tB, sp, tiles, lx, lu, s->nsp,
-                    (int *)s->fb_list, s->fb_count,
-                    2 * (long long)s->max_capacity * s->max_species, l6, s->counts, s->stream);
+                    s->fb_mask, s->fb_count, l6, s->counts, s->stream);
     return check_launch(s, "step_vjp");
 }
 

@@ -273,8 +273,8 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
                      float *const lEg[3],
                      float *const lBb[3], float *const tB[3], const SpeciesP *sp,
                      const int32_t *const *tile_off, float *const (*lx)[3],
-                     float *const (*lu)[3], int nsp, int *fb_list, unsigned *fb_count,
-                     long long fb_cap, float *const (*l6)[6], int *tile_exp, hipStream_t s);
+                     float *const (*lu)[3], int nsp, uint32_t *fb_mask, unsigned *fb_count,
+                     float *const (*l6)[6], int *tile_exp, hipStream_t s);
 // adjoint of a recorded sort: lam[perm[j]] = lam_post[j] (scratch: 6 x cap floats)
 void launch_sort_vjp(const int32_t *perm, long long cap, float *const lx[3], float *const lu[3],
                      float *const scratch[6], hipStream_t s);
