@@ -39,10 +39,13 @@ constexpr int TC = 256;  // cells per tile (every shape)
 // cross a cell face deposit their first segment at once and queue the
 // second, which the workgroup deposits after the tile's particles); 0: no
 // queue, the second segment is deposited at once.
-template <int X, int Y, int Z, int Q>
+// FE: extra field-window points past the upper end of each axis (the
+// second-order stencil of a node sub-grid reaches one point further).
+template <int X, int Y, int Z, int Q, int FE = 0>
 struct TileT {
     static constexpr int TX = X, TY = Y, TZ = Z, QCAP = Q;
-    static constexpr int FWX = X + 2 * MARGIN + 2, FWY = Y + 2 * MARGIN + 2, FWZ = Z + 2 * MARGIN + 2;
+    static constexpr int FWX = X + 2 * MARGIN + 2 + FE, FWY = Y + 2 * MARGIN + 2 + FE,
+                         FWZ = Z + 2 * MARGIN + 2 + FE;
     static constexpr int JWX = X + 2 * MARGIN + 3, JWY = Y + 2 * MARGIN + 3, JWZ = Z + 2 * MARGIN + 3;
     static constexpr int FW3 = FWX * FWY * FWZ, JW3 = JWX * JWY * JWZ;
     static constexpr int LHI_X = X + 2 * MARGIN, LHI_Y = Y + 2 * MARGIN, LHI_Z = Z + 2 * MARGIN;
@@ -61,6 +64,10 @@ using TileCube = TileT<8, 8, 4, 512>;
 // 34.6 KB + 45.9 KB, still two workgroups in a CU's 160 KB of LDS, which
 // leaves no room for a crossing queue.
 using TileSlab = TileT<16, 2, 8, 0>;
+// Second-order shapes (three-dimensional grids): the 8 x 8 x 4 tile with a
+// 13 x 13 x 9 field window (36.5 KB) and the same current window, no queue:
+// 73 KB, two workgroups per CU.
+using TileCube2 = TileT<8, 8, 4, 0, 1>;
 
 // A constant c of the FP32 path as the pair (hi, lo) of FP32 numbers with
 // hi = c rounded and lo = c - hi rounded.  Products c x are formed as

@@ -140,12 +140,15 @@ __device__ inline void gather2_global(const GridP &g, const float *const E[3],
 // dS = (weights at sB) - S0 on the nodes m - 1 .. m + 1 of each axis,
 //   W_c = dS_c (S0_b S0_e + dS_b S0_e / 2 + S0_b dS_e / 2 + dS_b dS_e / 3),
 // and J_c on the edge between nodes l and l + 1 along c is -(sum of W_c up
-// to l) times the charge factor (the third running sum is zero).  sink(c, x,
-// y, z, v) receives v for the edge or node index (x, y, z) relative to the
-// particle's cell; v still lacks the charge factor of component c.
+// to l) times the charge factor (the third running sum is zero).
+// sink.origin(x, y, z) receives the part's first node m - 1 per axis
+// (relative to the particle's cell), then sink(c, x, y, z, v) the value v for
+// the edge or node index origin + (x, y, z), with x, y, z known at compile
+// time once unrolled; v still lacks the charge factor of component c.
 template <class Sink>
 __device__ __forceinline__ void ez2_part(const float sA[3], const float sB[3], const int m[3],
                                          float wq, Sink &sink) {
+    sink.origin(m[0] - 1, m[1] - 1, m[2] - 1);
     float S0[3][3], dS[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -167,11 +170,11 @@ __device__ __forceinline__ void ez2_part(const float sA[3], const float sB[3], c
                 const float T = fmaf(dS[bb][ib], fmaf(0.5f, S0[ee][ie], dS[ee][ie] * (1.f / 3.f)),
                                      S0[bb][ib] * fmaf(0.5f, dS[ee][ie], S0[ee][ie]));
                 int idx[3];
-                idx[bb] = m[bb] - 1 + ib;
-                idx[ee] = m[ee] - 1 + ie;
-                idx[c] = m[c] - 1;
+                idx[bb] = ib;
+                idx[ee] = ie;
+                idx[c] = 0;
                 sink(c, idx[0], idx[1], idx[2], r0 * T);
-                idx[c] = m[c];
+                idx[c] = 1;
                 sink(c, idx[0], idx[1], idx[2], r1 * T);
             }
     }

@@ -86,9 +86,15 @@ struct GlobalSink2 {
     unsigned long long *const *Jf;
     int cell[3];
     const double *mult;
+    int o[3] = {0, 0, 0};
+    __device__ void origin(int x, int y, int z) {
+        o[0] = cell[0] + x;
+        o[1] = cell[1] + y;
+        o[2] = cell[2] + z;
+    }
     __device__ void operator()(int c, int x, int y, int z, float v) const {
-        const int gx = gaxis(g, 0, cell[0] + x), gy = gaxis(g, 1, cell[1] + y),
-                  gz = gaxis(g, 2, cell[2] + z);
+        const int gx = gaxis(g, 0, o[0] + x), gy = gaxis(g, 1, o[1] + y),
+                  gz = gaxis(g, 2, o[2] + z);
         if (gx < 0 || gy < 0 || gz < 0 || v == 0.f) return;
         atomicAdd(Jf[c] + gx + (long long)g.ext[0] * (gy + (long long)g.ext[1] * gz),
                   (unsigned long long)to_fixed(v, mult[c]));
@@ -468,23 +474,30 @@ __device__ __forceinline__ float tri2_lds(const float *F, int x, int y, int z, c
     return s;
 }
 
-// Order-2 current of a particle into the LDS window (fixed point)
+// Order-2 current of a particle into the LDS window (fixed point): one base
+// address per part, the constant offsets of its 54 entries folded into the
+// LDS instructions
+template <class TL>
 struct LdsSink2 {
     unsigned long long *sJ;
     int jb;  // window index of the particle's cell
-    int JWX, JWY, JW3;
     const double *mult;
+    unsigned long long *b = nullptr;
+    __device__ __forceinline__ void origin(int x, int y, int z) {
+        b = sJ + jb + x + TL::JWX * (y + TL::JWY * z);
+    }
     __device__ __forceinline__ void operator()(int c, int x, int y, int z, float v) const {
-        atomicAdd(sJ + c * JW3 + jb + x + JWX * (y + JWY * z),
+        atomicAdd(b + c * TL::JW3 + x + TL::JWX * (y + TL::JWY * z),
                   (unsigned long long)to_fixed(v, mult[c]));
     }
 };
 
 // One species of one tile with second-order shapes: the b_2 gather from the
 // LDS field window, Boris, move, and the EZ current into the LDS window.
-// The windows of the first-order kernel hold the b_2 stencils of the
-// particles inside their tile (no drift margin): the others take the global
-// path of k_push_fallback.
+// Particles up to MARGIN cells outside their tile, as at first order: the
+// field window (one point longer per axis, TileCube2) holds every gather
+// stencil; the current of a particle whose move takes its stencil past the
+// current window goes to the global fixed-point sums instead.
 template <class TL, int P>
 __device__ __forceinline__ void push_species2(const FusedArgs &A, const DevSpecies &D,
                                               const SpeciesP &S, const SpeciesP &Wr, int beg,
@@ -493,8 +506,7 @@ __device__ __forceinline__ void push_species2(const FusedArgs &A, const DevSpeci
                                               unsigned &nfb) {
     typedef float VF __attribute__((ext_vector_type(P)));
     typedef uint32_t VU __attribute__((ext_vector_type(P)));
-    constexpr int FW3 = TL::FW3, JWX = TL::JWX, JWY = TL::JWY, JW3 = TL::JW3;
-    constexpr int TX = TL::TX, TY = TL::TY, TZ = TL::TZ;
+    constexpr int FW3 = TL::FW3, JWX = TL::JWX, JWY = TL::JWY;
     const GridP &g = A.g;
     const float r = D.r, r_lo = D.r_lo;
     const double mult[3] = {A.jscale * D.qcd[0], A.jscale * D.qcd[1], A.jscale * D.qcd[2]};
@@ -513,10 +525,9 @@ __device__ __forceinline__ void push_species2(const FusedArgs &A, const DevSpeci
             const int lx = local_axis(g, 0, cell_i(c), T.wo[0]);
             const int ly = local_axis(g, 1, cell_j(c), T.wo[1]);
             const int lz = local_axis(g, 2, cell_k(c), T.wo[2]);
-            // inside the tile: window indices MARGIN + 1 .. MARGIN + T
-            const bool outside = !((unsigned)(lx - MARGIN - 1) < (unsigned)TX &&
-                                   (unsigned)(ly - MARGIN - 1) < (unsigned)TY &&
-                                   (unsigned)(lz - MARGIN - 1) < (unsigned)TZ);
+            const bool outside = !((unsigned)(lx - 1) < (unsigned)TL::LHI_X &&
+                                   (unsigned)(ly - 1) < (unsigned)TL::LHI_Y &&
+                                   (unsigned)(lz - 1) < (unsigned)TL::LHI_Z);
             if (list_fallback(A, outside, s, p, nfb)) continue;
             const float o[3] = {b.ox[k], b.oy[k], b.oz[k]};
             if (!(fminf(fminf(o[0], o[1]), o[2]) >= 0.f && fmaxf(fmaxf(o[0], o[1]), o[2]) < 1.f))
@@ -549,8 +560,23 @@ __device__ __forceinline__ void push_species2(const FusedArgs &A, const DevSpeci
                                  move_cells(uz * ig, A.dtd[2], A.dtd_lo[2])};
             if (!(fmaxf(fmaxf(fabsf(dx[0]), fabsf(dx[1])), fabsf(dx[2])) < 1.f))
                 fbits |= EMPIC_FAULT_FAST;
-            LdsSink2 sink{sJ, lx + JWX * (ly + JWY * lz), JWX, JWY, JW3, mult};
-            ez2_move(o, dx, b.w[k], sink);
+            // the window indices the current's stencils span (first node
+            // m - 1 of the lower cell to m + 1 of the upper, per axis)
+            const int JW[3] = {JWX, JWY, TL::JWZ};
+            bool fits = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int m0 = o[a] >= 0.5f ? 1 : 0;
+                const int m1 = (int)floorf(o[a] + dx[a] + 0.5f);
+                fits = fits && l[a] + min(m0, m1) - 1 >= 0 && l[a] + max(m0, m1) + 1 < JW[a];
+            }
+            if (fits) {
+                LdsSink2<TL> sink{sJ, lx + JWX * (ly + JWY * lz), mult};
+                ez2_move(o, dx, b.w[k], sink);
+            } else {
+                GlobalSink2 sink{g, A.Jf, {cell_i(c), cell_j(c), cell_k(c)}, mult};
+                ez2_move(o, dx, b.w[k], sink);
+            }
             float e[3], no[3];
             int dc[3];
 #pragma unroll
@@ -1542,7 +1568,7 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
     else if (ti.slab)
         launch_fused<TileSlab, 1>(A, nb, s, ev_start, ev_stop);  // order 2 is refused on slab grids
     else if (g.shape_order == 2)
-        launch_fused<TileCube, 2>(A, nb, s, ev_start, ev_stop);
+        launch_fused<TileCube2, 2>(A, nb, s, ev_start, ev_stop);
     else
         launch_fused<TileCube, 1>(A, nb, s, ev_start, ev_stop);
 }
