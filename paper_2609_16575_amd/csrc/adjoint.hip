@@ -564,7 +564,9 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
 template <class TL>
 __global__ __launch_bounds__(SCAT_THREADS) void k_adj_scatter(AdjArgs A, AdjSpecies S) {
     constexpr int FWX = TL::FWX, FWY = TL::FWY, FW3 = TL::FW3;
-    __shared__ unsigned long long sA[6 * FW3];
+    // LDS layout of the window: row, plane and component strides (words)
+    constexpr int RX = FWX, PS = FWX * FWY, CS = FW3;
+    __shared__ unsigned long long sA[6 * CS];
     __shared__ int sG[3][TL::ROWS];
 
     const GridP &g = A.g;
@@ -578,7 +580,7 @@ __global__ __launch_bounds__(SCAT_THREADS) void k_adj_scatter(AdjArgs A, AdjSpec
     const int ee = max(et, -96);  // keeps the scale a finite float
     const int tid = threadIdx.x;
     window_rows<TL>(g, wo, sG);
-    for (int e = tid; e < 6 * FW3; e += SCAT_THREADS) sA[e] = 0ull;
+    for (int e = tid; e < 6 * CS; e += SCAT_THREADS) sA[e] = 0ull;
     __syncthreads();
     constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
     const float scale = ldexpf(1.f, EB - ee);  // at most 2^127
@@ -609,10 +611,10 @@ __global__ __launch_bounds__(SCAT_THREADS) void k_adj_scatter(AdjArgs A, AdjSpec
                 float f[3], w[8];
                 stagger(q, wl, o, cq, f);
                 tri_weights(f, v * scale, w);  // exact power-of-two scaling
-                unsigned long long *dst = sA + q * FW3 + cq[0] + FWX * (cq[1] + FWY * cq[2]);
+                unsigned long long *dst = sA + q * CS + cq[0] + RX * cq[1] + PS * cq[2];
 #pragma unroll
                 for (int oo = 0; oo < 8; ++oo)
-                    atomicAdd(dst + (oo & 1) + FWX * (((oo >> 1) & 1) + FWY * (oo >> 2)),
+                    atomicAdd(dst + (oo & 1) + RX * ((oo >> 1) & 1) + PS * (oo >> 2),
                               (unsigned long long)(long long)__float2int_rn(w[oo]));
             }
         }
@@ -627,7 +629,7 @@ __global__ __launch_bounds__(SCAT_THREADS) void k_adj_scatter(AdjArgs A, AdjSpec
         const int o = sG[0][lx] + sG[1][ly] + sG[2][lz];
 #pragma unroll
         for (int comp = 0; comp < 6; ++comp) {
-            const long long fx = (long long)sA[comp * FW3 + r];
+            const long long fx = (long long)sA[comp * CS + lx + RX * ly + PS * lz];
             if (fx == 0) continue;
             float *dst = comp < 3 ? A.lEg[comp] : A.lBb[comp - 3];
             atomicAdd(dst + o, (float)((double)fx * inv));

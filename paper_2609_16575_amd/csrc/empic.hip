@@ -31,7 +31,7 @@ inline size_t up_align(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t Bbar, fault, table, partials, result, rho_cur, rho_prev, tile_off, counts, scan, rank,
-        fb_mask, adj, jfix, filt, mur, total;
+        fb_mask, fb_tiles, adj, jfix, filt, mur, total;
     size_t tile_off_stride;
     long long mur_stride;
 };
@@ -97,6 +97,8 @@ Layout layout(const empic_grid_desc *d, int max_species, long long max_capacity)
     o += up_align((size_t)max_capacity * 4);
     L.fb_mask = o;  // out-of-window marks (FP32 step, adjoint): one bit per slot and species
     o += up_align((size_t)max_species * (size_t)((max_capacity + 31) / 32) * 4);
+    L.fb_tiles = o;  // tiles with marked particles in one step
+    o += up_align((size_t)ti.ntiles * 4);
     L.adj = o;      // adjoint accumulators (FP32 path): gather lam_E, lam_Bbar, lam_B'
     o += d->precision == EMPIC_FP64_PLAIN ? 0 : up_align((size_t)9 * g.V * 4);
     L.jfix = o;     // FP32 path: the step's current as int64 sums (units 1/jscale)
@@ -159,6 +161,7 @@ struct empic_sim {
     void *mur = nullptr;
     uint32_t *fb_mask = nullptr;
     long long mask_words = 0;
+    int *fb_tiles = nullptr;
     unsigned *fb_count = nullptr;
     float *adj = nullptr;
     unsigned long long *jfix[3]{};  // FP32 path: the current as exact int64 sums
@@ -381,8 +384,8 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
             for (int pass = 0; pass < 2; ++pass)
                 launch_push_fused(s->g, s->ti, (float *const *)E, (float *const *)Bb,
                                   s->jfix, tbl, s->nsp, rmask, wmask, s->fault,
-                                  s->fallback, s->fb_mask, s->mask_words, s->fb_count,
-                                  s->jscale,
+                                  s->fallback, s->fb_mask, s->mask_words, s->fb_tiles,
+                                  s->fb_count, s->jscale,
                                   pass == 1, s->stream, pass == 0 ? tp.a : nullptr,
                                   pass == 0 ? tp.b : nullptr, pass == 1 ? publish : nullptr);
             if (s->timing) s->events.push_back(tp);
@@ -576,6 +579,7 @@ bool init_handle(empic_sim *s, const empic_grid_desc *g, const Layout &L, int32_
     s->rank = (int32_t *)(s->ws + L.rank);
     s->mur = s->ws + L.mur;
     s->fb_mask = (uint32_t *)(s->ws + L.fb_mask);
+    s->fb_tiles = (int *)(s->ws + L.fb_tiles);
     s->mask_words = (max_capacity + 31) / 32;
     s->adj = (float *)(s->ws + L.adj);
     if (g->precision == EMPIC_FP32_CELLREL)

@@ -231,8 +231,8 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
                        float *const Bbar[3], unsigned long long *const Jf[3],
                        const DevSpecies *tbl, int nsp,
                        unsigned cur_mask, unsigned wr_mask, uint32_t *fault, unsigned long long *fallback,
-                       uint32_t *fb_mask, long long mask_words, unsigned *fb_count,
-                       double jscale,
+                       uint32_t *fb_mask, long long mask_words, int *fb_tiles,
+                       unsigned *fb_count, double jscale,
                        bool fallback_pass, hipStream_t s, hipEvent_t ev_start = nullptr,
                        hipEvent_t ev_stop = nullptr, unsigned long long *publish = nullptr);
 void launch_dry_push_f32(const GridP &g, float *const E[3], float *const Bbar[3],

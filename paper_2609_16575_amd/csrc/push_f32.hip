@@ -52,7 +52,9 @@ struct FusedArgs {
     unsigned long long *fallback;  // cumulative count of out-of-window particles
     uint32_t *fb_mask;             // bit p of species s's words: slot p is out of its window
     long long mask_words;          // words per species in fb_mask
-    unsigned *fb_count;            // [0] particles marked this step, [1] block ticket of k_push_fallback
+    int *fb_tiles;                 // tiles with marked particles this step
+    unsigned *fb_count;            // [0] particles marked this step, [1] block ticket of
+                                   // k_push_fallback, [2] entries in fb_tiles
     unsigned long long *publish;   // host-visible copy of *fallback (k_push_fallback), or null
 };
 
@@ -672,6 +674,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     __shared__ __align__(16) unsigned long long sJ[3 * JW3 + 1];
     __shared__ float4 sQ[QN];
     __shared__ unsigned sQn;
+    __shared__ unsigned sNfb;  // particles of this tile marked for k_push_fallback
     __shared__ int sG[3][ROWS];
     __shared__ int sPad[3][ROWS];
 
@@ -707,7 +710,10 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     const int tid = threadIdx.x;
 
     // global index tables of the window rows: x index, y*ext0, z*ext0*ext1
-    if (tid == 0) sQn = 0u;
+    if (tid == 0) {
+        sQn = 0u;
+        sNfb = 0u;
+    }
     if (tid < 3 * ROWS) {
         const int a = tid / ROWS, l = tid % ROWS;
         const int wl = a == 0 ? JWX : (a == 1 ? JWY : JWZ);
@@ -771,7 +777,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     else if (nfb) atomicOr(A.fault, (uint32_t)EMPIC_FAULT_FALLBACK);
     if (nfb) {
         atomicAdd(A.fallback, (unsigned long long)nfb);
-        atomicAdd(A.fb_count, nfb);
+        atomicAdd(&sNfb, nfb);
     }
     __syncthreads();
     if constexpr (TL::QCAP > 0 && ORDER == 1) {
@@ -823,27 +829,40 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
             }
         }
     }
+    // a tile with marked particles lists itself for k_push_fallback (last, so
+    // that no wave waits for this returning atomic before its own work)
+    if (tid == 0 && sNfb) {
+        atomicAdd(A.fb_count, sNfb);
+        A.fb_tiles[atomicAdd(A.fb_count + 2, 1u)] = tile;
+    }
 }
 
 // Out-of-window particles of this step, whole particle through global memory
-// (gather from E and Bbar, global atomic deposit): the marked bits of the
-// mask, each word cleared once read.  Nothing to scan when the step marked
-// none.  The last workgroup to finish resets the count for the next step.
+// (gather from E and Bbar, global atomic deposit): one workgroup per listed
+// tile reads the mask words of the tile's slot range, keeps the bits inside
+// the range (a word can straddle two tiles) and clears them.  The last
+// workgroup to finish resets the counts for the next step.
 template <int ORDER>
 __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
-    const unsigned n = *(volatile unsigned *)A.fb_count;
+    const unsigned ntl = *(volatile unsigned *)(A.fb_count + 2);
     uint32_t fbits = 0;
-    const long long nw = (long long)A.nsp * A.mask_words;
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; n != 0 && t < nw;
-         t += (long long)gridDim.x * blockDim.x) {
-        uint32_t bits = A.fb_mask[t];
-        if (!bits) continue;
-        A.fb_mask[t] = 0u;
-        const int s = (int)(t / A.mask_words);
-        const int p0 = (int)(t - (long long)s * A.mask_words) * 32;
+    for (unsigned e = blockIdx.x; e < ntl; e += gridDim.x)
+    for (int s = 0; s < A.nsp; ++s) {
+        const int tile = A.fb_tiles[e];
         const DevSpecies &D = A.tbl[s];
         const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
         const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
+        const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
+        if (beg >= end) continue;
+        const int w0 = beg >> 5, w1 = (end - 1) >> 5;
+        for (int w = w0 + (int)threadIdx.x; w <= w1; w += (int)blockDim.x) {
+        const int lo = w == w0 ? (beg & 31) : 0, hi = w == w1 ? ((end - 1) & 31) : 31;
+        const uint32_t range = (0xffffffffu >> (31 - hi)) & (0xffffffffu << lo);
+        uint32_t *mw = A.fb_mask + (long long)s * A.mask_words + w;
+        uint32_t bits = *mw & range;
+        if (!bits) continue;
+        atomicAnd(mw, ~bits);
+        const int p0 = w * 32;
         while (bits) {
             const int p = p0 + __builtin_ctz(bits);
             bits &= bits - 1u;
@@ -861,9 +880,10 @@ __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
             ((float *)Wr.u[1])[p] = uy;
             ((float *)Wr.u[2])[p] = uz;
         }
+        }
     }
     if (fbits) atomicOr(A.fault, fbits);
-    // reset the count once every workgroup has read it
+    // reset the counts once every workgroup has read them
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -871,6 +891,7 @@ __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
         if (ticket == gridDim.x - 1) {
             atomicExch(A.fb_count, 0u);
             atomicExch(A.fb_count + 1, 0u);
+            atomicExch(A.fb_count + 2, 0u);
             if (A.publish) {
                 // every tile workgroup of this step has finished: the count is final
                 *(volatile unsigned long long *)A.publish = *(volatile unsigned long long *)A.fallback;
@@ -1534,8 +1555,8 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
                        float *const Bbar[3], unsigned long long *const Jf[3],
                        const DevSpecies *tbl, int nsp,
                        unsigned cur_mask, unsigned wr_mask, uint32_t *fault, unsigned long long *fallback,
-                       uint32_t *fb_mask, long long mask_words, unsigned *fb_count,
-                       double jscale,
+                       uint32_t *fb_mask, long long mask_words, int *fb_tiles,
+                       unsigned *fb_count, double jscale,
                        bool fallback_pass, hipStream_t s, hipEvent_t ev_start,
                        hipEvent_t ev_stop, unsigned long long *publish) {
     FusedArgs A;
@@ -1557,6 +1578,7 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
     A.fallback = fallback;
     A.fb_mask = fb_mask;
     A.mask_words = mask_words;
+    A.fb_tiles = fb_tiles;
     A.fb_count = fb_count;
     A.publish = publish;
     const int nb = 8 * ((ti.ntiles + 7) / 8);
