@@ -393,10 +393,12 @@ empic_status empic_save_state(empic_sim *s, const empic_state *dst);
 empic_status empic_load_state(empic_sim *s, const empic_state *src);
 
 /* One step (as empic_step, without a sort) from state src into state dst:
- * the handle's fields are set to src's, particles are read from src's arrays
- * and written to dst's (the handle's own particle buffers are untouched),
- * tile offsets and slot count are carried over, ids and per-particle weights
- * copied unless dst shares src's arrays, and dst receives the new fields.
+ * src's fields are copied into dst's field arrays and stepped there (the
+ * handle's own E and B are untouched; its J receives the step's current),
+ * particles are read from src's arrays and written to dst's (the handle's
+ * own particle buffers are untouched), tile offsets and slot count are
+ * carried over, ids and per-particle weights copied unless dst shares src's
+ * arrays.
  * For re-computing the states between checkpoints without copying them.
  * src and dst must not share cell, offset or momentum arrays.  A state
  * carries no time: the handle's step count is left as it was, and a handle

@@ -1317,10 +1317,11 @@ empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_
         }
         if (dst->cell[i] == src->cell[i]) return fail(s, EMPIC_E_ARG, "source and destination overlap");
     }
-    // fields of the source into the handle's
+    // fields of the source into the destination's arrays, which the step then
+    // updates in place (the handle's own E and B are not touched)
     for (int a = 0; a < 3; ++a) {
-        EMPIC_HIP(hipMemcpyAsync(s->E[a], src->E[a], fb, hipMemcpyDeviceToDevice, s->stream));
-        EMPIC_HIP(hipMemcpyAsync(s->B[a], src->B[a], fb, hipMemcpyDeviceToDevice, s->stream));
+        EMPIC_HIP(hipMemcpyAsync(dst->E[a], src->E[a], fb, hipMemcpyDeviceToDevice, s->stream));
+        EMPIC_HIP(hipMemcpyAsync(dst->B[a], src->B[a], fb, hipMemcpyDeviceToDevice, s->stream));
     }
     // species table: set 0 = source state, set 1 = destination state
     const size_t tw = ((size_t)s->ti.ntiles + 2) * 4;
@@ -1353,12 +1354,19 @@ empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_
     }
     // the handle's own clock (diagnostics, sort schedule) does not move
     const long long nstep = s->nstep;
-    one_step<float>(s, s->xtable, 0, (int)((1u << s->nsp) - 1u));
-    s->nstep = nstep;
+    void *E0[3], *B0[3];
     for (int a = 0; a < 3; ++a) {
-        EMPIC_HIP(hipMemcpyAsync(dst->E[a], s->E[a], fb, hipMemcpyDeviceToDevice, s->stream));
-        EMPIC_HIP(hipMemcpyAsync(dst->B[a], s->B[a], fb, hipMemcpyDeviceToDevice, s->stream));
+        E0[a] = s->E[a];
+        B0[a] = s->B[a];
+        s->E[a] = dst->E[a];
+        s->B[a] = dst->B[a];
     }
+    one_step<float>(s, s->xtable, 0, (int)((1u << s->nsp) - 1u));
+    for (int a = 0; a < 3; ++a) {
+        s->E[a] = E0[a];
+        s->B[a] = B0[a];
+    }
+    s->nstep = nstep;
     s->rho_prev_step = -1;
     return check_launch(s, "step_state");
 }

@@ -405,10 +405,9 @@ def _global_cells(st, i, n):
 @pytest.mark.parametrize("case", ["periodic_two_species", "absorbing_weighted"])
 def test_step_state_matches_step_in_place(case):
     """empic_step_state from a saved state equals loading it and stepping in
-    place: after one step the particle records bit for bit (the LDS deposit
-    sums are exact; only the order of J's float flush differs), after four
-    to rounding (the fields differ in that order), removed particles
-    included; the handle's own particle buffers stay untouched."""
+    place, bit for bit (the FP32 step is deterministic): the particle records
+    and the fields after one step and after four, removed particles
+    included; the handle's own particle buffers and fields stay untouched."""
     w = W.thermal_two_species(n=(16, 16, 16), ppc=4) if case == "periodic_two_species" \
         else _hot_absorbing()
     g = _sim(w, sort_every=0)
@@ -418,10 +417,13 @@ def test_step_state_matches_step_in_place(case):
     own = [g.particles(i) for i in range(len(w.species))]
     nsp = len(w.species)
     a, b = g.save_state(), g.alloc_state()
+    E_own, B_own, _ = g.fields()
     g.step_state(a, b)
     for i in range(nsp):  # own buffers untouched
         P, U, I = g.particles(i)
         assert np.array_equal(P, own[i][0]) and np.array_equal(U, own[i][1])
+    E1, B1, _ = g.fields()
+    assert np.array_equal(E1, E_own) and np.array_equal(B1, B_own)
     g.load_state(st0)
     g.step(1)
     ref = g.save_state()
@@ -432,10 +434,8 @@ def test_step_state_matches_step_in_place(case):
             if b[k][i] is not None:
                 assert torch_equal(b[k][i][..., :N], ref[k][i][..., :N]), (case, k, i)
     for k in ("E", "B"):
-        x, y = b[k].double().cpu().numpy(), ref[k].double().cpu().numpy()
-        assert np.abs(x - y).max() <= 1e-6 * max(np.abs(y).max(), 1e-30), (case, k)
-    # three more steps state to state, against the in-place run (which is
-    # reloaded: a state-to-state step leaves its fields in the handle)
+        assert torch_equal(b[k], ref[k]), (case, k)
+    # three more steps state to state, against the in-place run
     for _ in range(3):
         g.step_state(b, a)
         a, b = b, a
@@ -449,15 +449,14 @@ def test_step_state_matches_step_in_place(case):
         live = ~np.isnan(xr[:, 0])
         dx = xa[live] - xr[live]
         dx -= np.asarray(w.n) * np.round(dx / np.asarray(w.n))
-        assert np.abs(dx).max() <= 1e-5, (case, i, np.abs(dx).max())
-        ua, ur = b["u"][i][:, :N].double().cpu().numpy(), ref["u"][i][:, :N].double().cpu().numpy()
-        assert np.abs(ua - ur)[:, live].max() <= 1e-5 * np.abs(ur[:, live]).max(), (case, i)
+        assert np.abs(dx).max() == 0.0, (case, i, np.abs(dx).max())
+        for k in ("cell", "pos", "u"):
+            assert torch_equal(b[k][i][..., :N], ref[k][i][..., :N]), (case, k, i)
     if case == "absorbing_weighted":
         N = int(ref["tiles"][0][-1].item())
         assert int((ref["cell"][0][:N] == -1).sum().item()) > 100  # particles were removed
     for k in ("E", "B"):
-        x, y = b[k].double().cpu().numpy(), ref[k].double().cpu().numpy()
-        assert np.abs(x - y).max() <= 1e-5 * max(np.abs(y).max(), 1e-30), (case, k)
+        assert torch_equal(b[k], ref[k]), (case, k)
 
 
 def torch_equal(x, y):
