@@ -1298,7 +1298,6 @@ empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_
     if (s->laser.enabled || s->port.enabled || s->window.enabled)
         return fail(s, EMPIC_E_UNSUPPORTED,
                     "step_state: a laser, port or moving window depends on the step's time");
-    const size_t fb = (size_t)s->g.V * 4;
     for (int a = 0; a < 3; ++a)
         if (!src->E[a] || !src->B[a] || !dst->E[a] || !dst->B[a])
             return fail(s, EMPIC_E_ARG, "null state field");
@@ -1319,9 +1318,16 @@ empic_status empic_step_state(empic_sim *s, const empic_state *src, const empic_
     }
     // fields of the source into the destination's arrays, which the step then
     // updates in place (the handle's own E and B are not touched)
-    for (int a = 0; a < 3; ++a) {
-        EMPIC_HIP(hipMemcpyAsync(dst->E[a], src->E[a], fb, hipMemcpyDeviceToDevice, s->stream));
-        EMPIC_HIP(hipMemcpyAsync(dst->B[a], src->B[a], fb, hipMemcpyDeviceToDevice, s->stream));
+    {
+        const float *from[6];
+        float *to[6];
+        for (int a = 0; a < 3; ++a) {
+            from[a] = (const float *)src->E[a];
+            from[3 + a] = (const float *)src->B[a];
+            to[a] = (float *)dst->E[a];
+            to[3 + a] = (float *)dst->B[a];
+        }
+        launch_copy6(from, to, s->g.V, s->stream);
     }
     // species table: set 0 = source state, set 1 = destination state
     const size_t tw = ((size_t)s->ti.ntiles + 2) * 4;

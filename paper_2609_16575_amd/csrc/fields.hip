@@ -165,6 +165,20 @@ __global__ void k_ampere(GridP g, T *__restrict__ Ex, T *__restrict__ Ey, T *__r
     }
 }
 
+// Six arrays of n floats copied in one launch (the fields of a state)
+struct Copy6 {
+    const float *src[6];
+    float *dst[6];
+};
+
+__global__ void k_copy6(Copy6 c, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) c.dst[a][i] = c.src[a][i];
+    }
+}
+
 // J = the fixed-point sums converted (before the current filter)
 __global__ void k_j_from_fixed(GridP g, float *__restrict__ Jx, float *__restrict__ Jy,
                                float *__restrict__ Jz, const long long *__restrict__ Jfx,
@@ -433,6 +447,18 @@ void launch_ampere(const GridP &g, T *const E[3], T *const B[3], T *const J[3],
     hipLaunchKernelGGL(k_ampere<T>, point_grid(g), dim3(64, 4), 0, s, g, E[0], E[1], E[2], B[0],
                        B[1], B[2], J[0], J[1], J[2], Jf ? Jf[0] : nullptr, Jf ? Jf[1] : nullptr,
                        Jf ? Jf[2] : nullptr, jinv);
+}
+
+void launch_copy6(const float *const src[6], float *const dst[6], long long n, hipStream_t s) {
+    Copy6 c;
+    for (int a = 0; a < 6; ++a) {
+        c.src[a] = src[a];
+        c.dst[a] = dst[a];
+    }
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_copy6, dim3((unsigned)nb), dim3(256), 0, s, c, n);
 }
 
 void launch_j_from_fixed(const GridP &g, float *const J[3], const long long *const Jf[3],

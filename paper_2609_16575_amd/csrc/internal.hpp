@@ -190,6 +190,8 @@ void launch_ampere(const GridP &g, T *const E[3], T *const B[3], T *const J[3],
                    const long long *const Jf[3], double jinv, hipStream_t s);
 void launch_j_from_fixed(const GridP &g, float *const J[3], const long long *const Jf[3],
                          double jinv, hipStream_t s);
+// dst[a][i] = src[a][i], six arrays of n floats, one launch
+void launch_copy6(const float *const src[6], float *const dst[6], long long n, hipStream_t s);
 template <typename T>
 void launch_mur_save(const GridP &g, T *const E[3], T *planes, long long plane_stride,
                      hipStream_t s);
