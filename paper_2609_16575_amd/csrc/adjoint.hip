@@ -398,6 +398,7 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
     __shared__ float sL[3 * JW3];
     __shared__ int sG[3][TL::ROWS];
     __shared__ int sE;
+    __shared__ unsigned sNfb;
 
     const GridP &g = A.g;
     int wo[3];
@@ -407,7 +408,10 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
     if (beg >= end) return;
     const int tid = threadIdx.x;
     window_rows<TL>(g, wo, sG);
-    if (tid == 0) sE = NO_EXP;
+    if (tid == 0) {
+        sE = NO_EXP;
+        sNfb = 0u;
+    }
     __syncthreads();
     // a thread owns the same window points of every component: the global
     // offset of a point is worked out once, and all loads of a window are
@@ -466,6 +470,7 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
                        {A.lJ[0], A.lJ[1], A.lJ[2]}};
     constexpr int LHI_X = TL::LHI_X, LHI_Y = TL::LHI_Y, LHI_Z = TL::LHI_Z;
     int emax = NO_EXP;
+    unsigned nfb = 0u;
     for (int base = (beg & ~(APPT - 1)) + tid * APPT; base < end; base += ADJ_THREADS * APPT) {
         const vuA c4 = *(const vuA *)(S.cell + base);
         const vfA ox4 = *(const vfA *)(S.pos[0] + base), oy4 = *(const vfA *)(S.pos[1] + base),
@@ -515,9 +520,10 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
             } else {
                 // drifted more than MARGIN cells out of its tile since the sort:
                 // marked for k_adj_fallback (its adjoints stay as loaded here);
-                // atomics whose results are not waited for
+                // an atomic whose result is not waited for; the count is
+                // summed per workgroup
                 atomicOr(A.fb_mask + (p >> 5), 1u << (p & 31));
-                atomicAdd(A.fb_count, 1u);
+                ++nfb;
                 continue;
             }
 #pragma unroll
@@ -550,8 +556,12 @@ __global__ __launch_bounds__(ADJ_THREADS, 3) void k_adj_particles(AdjArgs A, Adj
         }
     }
     if (emax != NO_EXP) atomicMax(&sE, emax);
+    if (nfb) atomicAdd(&sNfb, nfb);
     __syncthreads();
-    if (tid == 0) A.tile_exp[tile] = sE;
+    if (tid == 0) {
+        A.tile_exp[tile] = sE;
+        if (sNfb) atomicAdd(A.fb_count, sNfb);
+    }
 }
 
 // Pass 2, one workgroup per tile: the gather scatter of pass 1's lam_Ep,

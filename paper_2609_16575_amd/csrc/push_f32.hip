@@ -675,6 +675,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     __shared__ float4 sQ[QN];
     __shared__ unsigned sQn;
     __shared__ unsigned sNfb;  // particles of this tile marked for k_push_fallback
+    __shared__ uint32_t sFbits;  // fault bits raised in this tile
     __shared__ int sG[3][ROWS];
     __shared__ int sPad[3][ROWS];
 
@@ -713,6 +714,7 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     if (tid == 0) {
         sQn = 0u;
         sNfb = 0u;
+        sFbits = 0u;
     }
     if (tid < 3 * ROWS) {
         const int a = tid / ROWS, l = tid % ROWS;
@@ -773,12 +775,11 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
         push_tile<TL, true>(A, T, tile, sparse0, beg0, end0, pre1, sF, sJ, Q, fbits, nfb);
     else
         push_tile<TL, false>(A, T, tile, sparse0, beg0, end0, pre1, sF, sJ, Q, fbits, nfb);
-    if (fbits) atomicOr(A.fault, fbits | (nfb ? EMPIC_FAULT_FALLBACK : 0u));
-    else if (nfb) atomicOr(A.fault, (uint32_t)EMPIC_FAULT_FALLBACK);
-    if (nfb) {
-        atomicAdd(A.fallback, (unsigned long long)nfb);
-        atomicAdd(&sNfb, nfb);
-    }
+    // counts and fault bits gathered per workgroup in LDS: a global atomic per
+    // thread on these single words serialised the whole step once many
+    // particles were out of their windows
+    if (fbits) atomicOr(&sFbits, fbits);
+    if (nfb) atomicAdd(&sNfb, nfb);
     __syncthreads();
     if constexpr (TL::QCAP > 0 && ORDER == 1) {
         // the queued second segments
@@ -831,9 +832,13 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
     }
     // a tile with marked particles lists itself for k_push_fallback (last, so
     // that no wave waits for this returning atomic before its own work)
-    if (tid == 0 && sNfb) {
-        atomicAdd(A.fb_count, sNfb);
-        A.fb_tiles[atomicAdd(A.fb_count + 2, 1u)] = tile;
+    if (tid == 0) {
+        if (sFbits | sNfb) atomicOr(A.fault, sFbits | (sNfb ? EMPIC_FAULT_FALLBACK : 0u));
+        if (sNfb) {
+            atomicAdd(A.fallback, (unsigned long long)sNfb);
+            atomicAdd(A.fb_count, sNfb);
+            A.fb_tiles[atomicAdd(A.fb_count + 2, 1u)] = tile;
+        }
     }
 }
 

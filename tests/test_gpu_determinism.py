@@ -35,7 +35,11 @@ def _same(a, b):
     for (P, U, I), (Q, V, K) in zip(Pa, Pb):
         assert np.array_equal(I, K)
         assert np.array_equal(P, Q) and np.array_equal(U, V)
-    assert da["U_tot"] == db["U_tot"]
+    # the FP64 energy sums visit the particles in slot order, and the counting
+    # sort ranks the particles of one cell by atomics, so the last bits of the
+    # kinetic sum may differ where fields and particles are identical
+    assert da["U_E"] == db["U_E"] and da["U_B"] == db["U_B"]
+    assert abs(da["U_tot"] - db["U_tot"]) <= 1e-13 * abs(da["U_tot"])
 
 
 def _plasma():
