@@ -498,8 +498,10 @@ struct LdsSink2 {
 // LDS field window, Boris, move, and the EZ current into the LDS window.
 // Particles up to MARGIN cells outside their tile, as at first order: the
 // field window (one point longer per axis, TileCube2) holds every gather
-// stencil; the current of a particle whose move takes its stencil past the
-// current window goes to the global fixed-point sums instead.
+// stencil; a particle whose move takes its current stencil past the current
+// window is left as loaded and marked for k_push_fallback, which pushes it
+// through global memory (a second, inlined global deposit here made the
+// kernel spill registers).
 template <class TL, int P>
 __device__ __forceinline__ void push_species2(const FusedArgs &A, const DevSpecies &D,
                                               const SpeciesP &S, const SpeciesP &Wr, int beg,
@@ -572,11 +574,11 @@ __device__ __forceinline__ void push_species2(const FusedArgs &A, const DevSpeci
                 const int m1 = (int)floorf(o[a] + dx[a] + 0.5f);
                 fits = fits && l[a] + min(m0, m1) - 1 >= 0 && l[a] + max(m0, m1) + 1 < JW[a];
             }
-            if (fits) {
+            // a particle whose current leaves the window is pushed again by
+            // k_push_fallback from its loaded state (kept here)
+            if (list_fallback(A, !fits, s, p, nfb)) continue;
+            {
                 LdsSink2<TL> sink{sJ, lx + JWX * (ly + JWY * lz), mult};
-                ez2_move(o, dx, b.w[k], sink);
-            } else {
-                GlobalSink2 sink{g, A.Jf, {cell_i(c), cell_j(c), cell_k(c)}, mult};
                 ez2_move(o, dx, b.w[k], sink);
             }
             float e[3], no[3];
@@ -630,10 +632,12 @@ __device__ __forceinline__ void push_tile2(const FusedArgs &A, const TileCtx &T,
         const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
         const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
         if (beg >= end) continue;
+        // two particles per thread in dense tiles: four made the 27-point
+        // gathers and the EZ deposit spill registers
         if (end - beg <= 2 * PUSH_THREADS)
             push_species2<TL, 1>(A, D, S, Wr, beg, end, T, sF, sJ, s, fbits, nfb);
         else
-            push_species2<TL, PPT>(A, D, S, Wr, beg, end, T, sF, sJ, s, fbits, nfb);
+            push_species2<TL, 2>(A, D, S, Wr, beg, end, T, sF, sJ, s, fbits, nfb);
     }
 }
 
