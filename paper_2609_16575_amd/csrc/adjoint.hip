@@ -822,7 +822,6 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
                                A, S);
         hipLaunchKernelGGL(k_adj_fallback, dim3(1024), dim3(256), 0, s, A, S,
                            (long long)((sp[i].capacity + 31) / 32));
-        launch_fill_i32((int32_t *)fb_count, 1, 0, s);  // the step kernels expect it empty
         if (ti.slab)
             hipLaunchKernelGGL(k_adj_scatter<TileSlab>, dim3(nblocks), dim3(SCAT_THREADS), 0, s,
                                A, S);

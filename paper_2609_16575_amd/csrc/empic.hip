@@ -365,7 +365,7 @@ void one_step(empic_sim *s, const DevSpecies *tbl = nullptr, int rd_mask = -1, i
     // (FP32) zeroed for this step's deposit
     constexpr bool f32 = sizeof(T) == 4;
     launch_faraday<T>(s->g, E, B, Bb, f32 ? nullptr : J, f32 ? s->jfix : nullptr, true,
-                      s->stream);
+                      s->stream, f32 ? s->fb_count : nullptr);
     ev_end(s, t);
     // 2. gather, Boris, move, ZigZag for every species
     if constexpr (sizeof(T) == 4) {

@@ -69,10 +69,15 @@ __global__ void k_faraday(GridP g, const T *__restrict__ Ex, const T *__restrict
                           T *__restrict__ Bbz, T *__restrict__ Jx, T *__restrict__ Jy,
                           T *__restrict__ Jz, unsigned long long *__restrict__ Jfx,
                           unsigned long long *__restrict__ Jfy, unsigned long long *__restrict__ Jfz,
-                          int write_B) {
+                          unsigned *__restrict__ fb_reset, int write_B) {
     Pt q;
     if (!make_point(g, q)) return;
     const long long p = q.p;
+    if (fb_reset && p == 0) {  // the out-of-window counts of the coming push
+        fb_reset[0] = 0u;
+        fb_reset[1] = 0u;
+        fb_reset[2] = 0u;
+    }
     if (Jx) {
         Jx[p] = T(0);
         Jy[p] = T(0);
@@ -434,11 +439,12 @@ dim3 reduction_grid(const GridP &g) {
 
 template <typename T>
 void launch_faraday(const GridP &g, T *const E[3], T *const B[3], T *const Bbar[3],
-                    T *const J[3], unsigned long long *const Jf[3], bool write_B, hipStream_t s) {
+                    T *const J[3], unsigned long long *const Jf[3], bool write_B, hipStream_t s,
+                    unsigned *fb_reset) {
     hipLaunchKernelGGL(k_faraday<T>, point_grid(g), dim3(64, 4), 0, s, g, E[0], E[1], E[2], B[0],
                        B[1], B[2], Bbar[0], Bbar[1], Bbar[2], J ? J[0] : nullptr,
                        J ? J[1] : nullptr, J ? J[2] : nullptr, Jf ? Jf[0] : nullptr,
-                       Jf ? Jf[1] : nullptr, Jf ? Jf[2] : nullptr, write_B ? 1 : 0);
+                       Jf ? Jf[1] : nullptr, Jf ? Jf[2] : nullptr, fb_reset, write_B ? 1 : 0);
 }
 
 template <typename T>
@@ -556,7 +562,7 @@ void launch_field_energy(const GridP &g, T *const E[3], T *const B[3], double *p
 #define EMPIC_INST(T)                                                                          \
     template void launch_faraday<T>(const GridP &, T *const[3], T *const[3], T *const[3],      \
                                     T *const[3], unsigned long long *const[3], bool,           \
-                                    hipStream_t);                                              \
+                                    hipStream_t, unsigned *);                                  \
     template void launch_ampere<T>(const GridP &, T *const[3], T *const[3], T *const[3],       \
                                    const long long *const[3], double, hipStream_t);            \
     template void launch_mur_save<T>(const GridP &, T *const[3], T *, long long, hipStream_t); \

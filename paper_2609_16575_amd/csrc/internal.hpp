@@ -183,7 +183,8 @@ dim3 reduction_grid(const GridP &g);
 // path) when given
 template <typename T>
 void launch_faraday(const GridP &g, T *const E[3], T *const B[3], T *const Bbar[3],
-                    T *const J[3], unsigned long long *const Jf[3], bool write_B, hipStream_t s);
+                    T *const J[3], unsigned long long *const Jf[3], bool write_B, hipStream_t s,
+                    unsigned *fb_reset = nullptr);
 // Ampere-Maxwell; with Jf, J is first set to Jf * jinv (FP32 path)
 template <typename T>
 void launch_ampere(const GridP &g, T *const E[3], T *const B[3], T *const J[3],

@@ -53,8 +53,8 @@ struct FusedArgs {
     uint32_t *fb_mask;             // bit p of species s's words: slot p is out of its window
     long long mask_words;          // words per species in fb_mask
     int *fb_tiles;                 // tiles with marked particles this step
-    unsigned *fb_count;            // [0] particles marked this step, [1] block ticket of
-                                   // k_push_fallback, [2] entries in fb_tiles
+    unsigned *fb_count;            // [0] particles marked this step, [1] unused, [2]
+                                   // entries in fb_tiles (cleared by k_faraday)
     unsigned long long *publish;   // host-visible copy of *fallback (k_push_fallback), or null
 };
 
@@ -849,10 +849,17 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
 // Out-of-window particles of this step, whole particle through global memory
 // (gather from E and Bbar, global atomic deposit): one workgroup per listed
 // tile reads the mask words of the tile's slot range, keeps the bits inside
-// the range (a word can straddle two tiles) and clears them.  The last
-// workgroup to finish resets the counts for the next step.
+// the range (a word can straddle two tiles) and clears them.  The counts and
+// the tile list are cleared by the next step's Faraday kernel (a ticket for
+// the last workgroup, a returning atomic of every workgroup on one word, cost
+// more than the pass itself in most steps).
 template <int ORDER>
 __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
+    if (A.publish && blockIdx.x == 0 && threadIdx.x == 0) {
+        // every tile workgroup of this step has finished: the count is final
+        *(volatile unsigned long long *)A.publish = *(volatile unsigned long long *)A.fallback;
+        __threadfence_system();
+    }
     const unsigned ntl = *(volatile unsigned *)(A.fb_count + 2);
     uint32_t fbits = 0;
     for (unsigned e = blockIdx.x; e < ntl; e += gridDim.x)
@@ -892,22 +899,6 @@ __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
         }
     }
     if (fbits) atomicOr(A.fault, fbits);
-    // reset the counts once every workgroup has read them
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned ticket = atomicAdd(A.fb_count + 1, 1u);
-        if (ticket == gridDim.x - 1) {
-            atomicExch(A.fb_count, 0u);
-            atomicExch(A.fb_count + 1, 0u);
-            atomicExch(A.fb_count + 2, 0u);
-            if (A.publish) {
-                // every tile workgroup of this step has finished: the count is final
-                *(volatile unsigned long long *)A.publish = *(volatile unsigned long long *)A.fallback;
-                __threadfence_system();
-            }
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
