@@ -18,7 +18,7 @@ J written) per launch over its HIP-event-timed average duration.  The
 "adjoint" entry times a 50-step forward + adjoint on a 128^3 anisotropic
 plasma (see adjoint_leg); "shape_order_2" the same plasma stepped with
 second-order shapes (b_2 weighting, EZ current).  cpu_baseline: the FP64
-oracle on one core, 2 steps of a 64^3 box of the same plasma.
+oracle on one core, 5 steps of a 64^3 box of the same plasma.
 """
 from __future__ import annotations
 
@@ -84,9 +84,9 @@ def traffic_from_counters(nbytes_alg):
             c["write_kib_per_dispatch"] * c["copy_scale_write"]) * 1024.0
 
 
-def cpu_baseline(n=(64, 64, 64), steps=2):
+def cpu_baseline(n=(64, 64, 64), steps=5):
     """The FP64 oracle (single thread) on a 64^3 box of the same plasma (same
-    density, temperatures and cell size), 2 steps: 10-20 s of CPU work.
+    density, temperatures and cell size), 5 steps: about 15 s of CPU work.
     One step of the whole 128^3 box takes about a minute on one core."""
     from oracle import oracle as O
     from paper_2609_16575_amd import workloads as W
