@@ -12,7 +12,7 @@ from paper_2609_16575_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = 2e-5  # the FP32 step's per-step bar; the runs differ only in the order of float atomics
+TOL = 2e-5  # the FP32 step's per-step bar (the step itself is deterministic; the bar is the contract)
 
 
 def _rel(a, b):
