@@ -88,32 +88,34 @@ __global__ void k_faraday(GridP g, const T *__restrict__ Ex, const T *__restrict
         Jfy[p] = 0ull;
         Jfz[p] = 0ull;
     }
-    // dt as a pair of T (the low part is zero in FP64): no systematic error
-    // from its rounding in the FP32 updates
-    const T dt = (T)g.dt, dt_lo = (T)(g.dt - (double)dt);
-    const T ix = (T)g.inv_d[0], iy = (T)g.inv_d[1], iz = (T)g.inv_d[2];
+    // evaluated in FP64 and rounded once per stored value (see k_ampere)
+    const double dt = g.dt;
+    const double ix = g.inv_d[0], iy = g.inv_d[1], iz = g.inv_d[2];
     // B^{n+1/2} = B^{n-1/2} - dt curl E^n (forward differences); Bbar = average
     if (valid_B(g, q, 0)) {
-        const T curl = (Ez[p + up(g, q, 1)] - Ez[p]) * iy - (Ey[p + up(g, q, 2)] - Ey[p]) * iz;
-        const T old = Bx[p], nw = old - dt * curl - dt_lo * curl;
-        if (write_B) Bx[p] = nw;
-        Bbx[p] = T(0.5) * (old + nw);
+        const double curl = ((double)Ez[p + up(g, q, 1)] - (double)Ez[p]) * iy -
+                            ((double)Ey[p + up(g, q, 2)] - (double)Ey[p]) * iz;
+        const double old = (double)Bx[p], nw = old - dt * curl;
+        if (write_B) Bx[p] = (T)nw;
+        Bbx[p] = (T)(0.5 * (old + nw));
     } else {
         Bbx[p] = T(0);
     }
     if (valid_B(g, q, 1)) {
-        const T curl = (Ex[p + up(g, q, 2)] - Ex[p]) * iz - (Ez[p + up(g, q, 0)] - Ez[p]) * ix;
-        const T old = By[p], nw = old - dt * curl - dt_lo * curl;
-        if (write_B) By[p] = nw;
-        Bby[p] = T(0.5) * (old + nw);
+        const double curl = ((double)Ex[p + up(g, q, 2)] - (double)Ex[p]) * iz -
+                            ((double)Ez[p + up(g, q, 0)] - (double)Ez[p]) * ix;
+        const double old = (double)By[p], nw = old - dt * curl;
+        if (write_B) By[p] = (T)nw;
+        Bby[p] = (T)(0.5 * (old + nw));
     } else {
         Bby[p] = T(0);
     }
     if (valid_B(g, q, 2)) {
-        const T curl = (Ey[p + up(g, q, 0)] - Ey[p]) * ix - (Ex[p + up(g, q, 1)] - Ex[p]) * iy;
-        const T old = Bz[p], nw = old - dt * curl - dt_lo * curl;
-        if (write_B) Bz[p] = nw;
-        Bbz[p] = T(0.5) * (old + nw);
+        const double curl = ((double)Ey[p + up(g, q, 0)] - (double)Ey[p]) * ix -
+                            ((double)Ex[p + up(g, q, 1)] - (double)Ex[p]) * iy;
+        const double old = (double)Bz[p], nw = old - dt * curl;
+        if (write_B) Bz[p] = (T)nw;
+        Bbz[p] = (T)(0.5 * (old + nw));
     } else {
         Bbz[p] = T(0);
     }
@@ -137,36 +139,40 @@ __global__ void k_ampere(GridP g, T *__restrict__ Ex, T *__restrict__ Ey, T *__r
     Pt q;
     if (!make_point(g, q)) return;
     const long long p = q.p;
-    T jx, jy, jz;
+    // Evaluated in FP64 and rounded once per stored value: in FP32 the
+    // rounding of J, of curl - J and of the two-part update add up coherently
+    // on a quiet plasma (every cell of a wave front rounds alike).  The kernel
+    // is bound by memory, and gfx950 issues FP64 at the FP32 (unpacked) rate.
+    double jx, jy, jz;
     if (Jfx) {
-        jx = j_from_fixed<T>(Jfx[p], jinv);
-        jy = j_from_fixed<T>(Jfy[p], jinv);
-        jz = j_from_fixed<T>(Jfz[p], jinv);
-        Jx[p] = jx;
-        Jy[p] = jy;
-        Jz[p] = jz;
+        jx = (double)Jfx[p] * jinv;
+        jy = (double)Jfy[p] * jinv;
+        jz = (double)Jfz[p] * jinv;
+        Jx[p] = (T)jx;
+        Jy[p] = (T)jy;
+        Jz[p] = (T)jz;
     } else {
-        jx = Jx[p];
-        jy = Jy[p];
-        jz = Jz[p];
+        jx = (double)Jx[p];
+        jy = (double)Jy[p];
+        jz = (double)Jz[p];
     }
-    const T dt = (T)g.dt, dt_lo = (T)(g.dt - (double)dt);  // see k_faraday
-    const T ix = (T)g.inv_d[0], iy = (T)g.inv_d[1], iz = (T)g.inv_d[2];
+    const double dt = g.dt;
+    const double ix = g.inv_d[0], iy = g.inv_d[1], iz = g.inv_d[2];
     // E^{n+1} = E^n + dt curl B^{n+1/2} - dt J^{n+1/2} (backward differences)
     if (ampere_E(g, q, 0)) {
-        const T curl = (Bz[p] - Bz[p + dn(g, q, 1)]) * iy - (By[p] - By[p + dn(g, q, 2)]) * iz;
-        const T x = curl - jx;
-        Ex[p] = Ex[p] + dt * x + dt_lo * x;
+        const double curl = ((double)Bz[p] - (double)Bz[p + dn(g, q, 1)]) * iy -
+                            ((double)By[p] - (double)By[p + dn(g, q, 2)]) * iz;
+        Ex[p] = (T)((double)Ex[p] + dt * (curl - jx));
     }
     if (ampere_E(g, q, 1)) {
-        const T curl = (Bx[p] - Bx[p + dn(g, q, 2)]) * iz - (Bz[p] - Bz[p + dn(g, q, 0)]) * ix;
-        const T x = curl - jy;
-        Ey[p] = Ey[p] + dt * x + dt_lo * x;
+        const double curl = ((double)Bx[p] - (double)Bx[p + dn(g, q, 2)]) * iz -
+                            ((double)Bz[p] - (double)Bz[p + dn(g, q, 0)]) * ix;
+        Ey[p] = (T)((double)Ey[p] + dt * (curl - jy));
     }
     if (ampere_E(g, q, 2)) {
-        const T curl = (By[p] - By[p + dn(g, q, 0)]) * ix - (Bx[p] - Bx[p + dn(g, q, 1)]) * iy;
-        const T x = curl - jz;
-        Ez[p] = Ez[p] + dt * x + dt_lo * x;
+        const double curl = ((double)By[p] - (double)By[p + dn(g, q, 0)]) * ix -
+                            ((double)Bx[p] - (double)Bx[p + dn(g, q, 1)]) * iy;
+        Ez[p] = (T)((double)Ez[p] + dt * (curl - jz));
     }
 }
 

@@ -240,20 +240,19 @@ def test_differentiable_workload_gradients_500_steps():
     """The differentiable workload as stated: 32^3, 16 per cell, eps = 1e-2,
     500 steps, checkpoints every 50.  The FP32 GPU gradients with respect to
     eps and along the seeded random momentum direction against the FP64
-    oracle's chained adjoint gradient and the oracle's central differences
-    (h = 1e-4) of the same run (tests/golden/langmuir32_gradients.json,
-    written by make_langmuir32_gradients.py from the oracle alone).
+    oracle's central differences (h = 1e-4) and its chained adjoint gradient
+    of the same run (tests/golden/langmuir32_gradients.json, written by
+    make_langmuir32_gradients.py from the oracle alone).
 
-    The stated criterion, 1e-4 relative, is not met at this step (it is at
-    100 steps): the relative errors are 1.0-1.8e-4.  At step 500 the probe
-    energy is about 1/1900 of its peak, a node of the oscillation, where a
-    phase error is amplified ~90-fold into L.  In the oracle, FP32 rounding
-    of the stored arrays to nearest moves L by 2.6e-5, ten times what the
-    same rounding done stochastically does (tests/golden/
-    langmuir32_fp32_noise.json): on the quiet lattice round-to-nearest
-    errors are the same for every particle of a plane and add up instead of
-    averaging, and the push's FP32 arithmetic adds more of them.  2.5e-4
-    is asserted as a regression bound."""
+    The criterion, 1e-4 relative to the central differences, is asserted as
+    stated.  Against the oracle's own adjoint the bound is 1e-4 plus the
+    distance between the oracle's two references (4.8e-5 for eps, 3.9e-6
+    for the direction).  At step 500 the probe energy is about 1/1900 of its
+    peak, a node of the oscillation, where a phase error is amplified
+    ~90-fold into L; the FP32 Yee updates evaluate in FP64 and round once
+    per stored value, since their intermediate FP32 roundings (of J, of
+    curl - J, of the two-part update) add up coherently on the quiet
+    lattice and made L miss by 1.2e-4 and the gradients by 1.0-1.8e-4."""
     ref = json.load(open(GOLDEN_32))
     steps, K, eps = ref["steps"], ref["checkpoint_every"], ref["eps"]
     w = W.cold_langmuir_lattice(eps=eps, steps=steps)
@@ -266,8 +265,12 @@ def test_differentiable_workload_gradients_500_steps():
             "dir_vs_adjoint": abs(gdir - ref["adjoint_dL_ddir"]) / abs(ref["adjoint_dL_ddir"]),
             "dir_vs_fd": abs(gdir - ref["fd_dL_ddir"]) / abs(ref["fd_dL_ddir"])}
     print("config-4 gradients at 500 steps:", json.dumps(errs), flush=True)
-    for k in ("L", "eps_vs_adjoint", "eps_vs_fd", "dir_vs_adjoint", "dir_vs_fd"):
-        assert errs[k] <= 2.5e-4, (k, errs, Lv, geps, gdir)
+    spread = {"eps": abs(ref["adjoint_dL_deps"] - ref["fd_dL_deps"]) / abs(ref["fd_dL_deps"]),
+              "dir": abs(ref["adjoint_dL_ddir"] - ref["fd_dL_ddir"]) / abs(ref["fd_dL_ddir"])}
+    assert errs["L"] <= 1e-4, (errs, Lv)
+    for g in ("eps", "dir"):
+        assert errs[g + "_vs_fd"] <= 1e-4, (g, errs, geps, gdir)
+        assert errs[g + "_vs_adjoint"] <= 1e-4 + spread[g], (g, errs, spread, geps, gdir)
 
 
 def test_gradient_matches_fp64_oracle_adjoint():
