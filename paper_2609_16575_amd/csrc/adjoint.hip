@@ -759,10 +759,24 @@ __global__ void k_sort_vjp_scatter(Lam6 lam, Lam6 tmp, const int32_t *perm, long
     for (int a = 0; a < 6; ++a) lam.p[a][q] = tmp.p[a][j];
 }
 
-__global__ void k_zero_f32(float *p, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        p[i] = 0.f;
+// Six arrays of n floats cleared in one launch: 16-byte stores when every
+// array is 16-byte aligned (vec), single floats otherwise
+__global__ void k_zero6(Lam6 z, long long n, int vec) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long t0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (!vec) {
+        for (long long i = t0; i < n; i += stride)
+#pragma unroll
+            for (int a = 0; a < 6; ++a) z.p[a][i] = 0.f;
+        return;
+    }
+    const long long n4 = n >> 2;
+    for (long long i = t0; i < n4; i += stride)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) ((float4 *)z.p[a])[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t0 < n - 4 * n4)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) z.p[a][4 * n4 + t0] = 0.f;
 }
 
 }  // namespace
@@ -774,9 +788,15 @@ void launch_step_vjp(const GridP &g, const TileInfo &ti, float *const E[3], floa
                      const int32_t *const *tile_off, float *const (*lx)[3],
                      float *const (*lu)[3], int nsp, uint32_t *fb_mask, unsigned *fb_count,
                      float *const (*l6)[6], int *tile_exp, hipStream_t s) {
-    for (int a = 0; a < 3; ++a) {
-        hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, lEg[a], g.V);
-        hipLaunchKernelGGL(k_zero_f32, dim3(1024), dim3(256), 0, s, lBb[a], g.V);
+    {
+        Lam6 z;
+        int vec = 1;
+        for (int a = 0; a < 3; ++a) {
+            z.p[a] = lEg[a];
+            z.p[3 + a] = lBb[a];
+        }
+        for (int a = 0; a < 6; ++a) vec &= ((uintptr_t)z.p[a] & 15u) == 0 ? 1 : 0;
+        hipLaunchKernelGGL(k_zero6, dim3(2048), dim3(256), 0, s, z, g.V, vec);
     }
     AdjArgs A;
     A.g = g;
