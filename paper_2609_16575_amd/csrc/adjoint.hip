@@ -122,28 +122,38 @@ template <class Acc>
 __device__ __forceinline__ void segment_vjp(const Acc &a, const int cell[3], const float W[3],
                                             const float D[3], const float ampc[3],
                                             const float ampc_lo[3], float ls[3], float le[3]) {
+    // per component c, from its four edge adjoints lam_q (q = o1 + 2 o2, o1
+    // along b1, o2 along b2) with weights w(0) = 1 - W, w(1) = W:
+    //   d/dD_c:   sum_q lam_q w1 w2 + D_b1 D_b2 / 12 sum_q s_q lam_q
+    //   d/dW_b1:  D_c sum_q lam_q (2 o1 - 1) w2,  d/dW_b2 likewise
+    //   d/dD_b1:  D_c D_b2 / 12 sum_q s_q lam_q,  d/dD_b2 likewise
+    // with s_q = +1 where o1 = o2, else -1
     float lD[3] = {0.f, 0.f, 0.f}, lW[3] = {0.f, 0.f, 0.f};
+    const float d12[3] = {D[0] * (1.f / 12.f), D[1] * (1.f / 12.f), D[2] * (1.f / 12.f)};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int b1 = (c + 1) % 3, b2 = (c + 2) % 3;
+        float lam[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int o1 = q & 1, o2 = q >> 1;
             int p[3] = {cell[0], cell[1], cell[2]};
-            p[b1] += o1;
-            p[b2] += o2;
+            p[b1] += q & 1;
+            p[b2] += q >> 1;
             const float Lc = a.L(c, p[0], p[1], p[2]);
-            const float lam = fmaf(Lc, ampc_lo[c], Lc * ampc[c]);
-            const float w1 = o1 ? W[b1] : 1.f - W[b1];
-            const float w2 = o2 ? W[b2] : 1.f - W[b2];
-            const float sg = (o1 == o2) ? 1.f : -1.f;
-            lD[c] += lam * (w1 * w2 + sg * D[b1] * D[b2] * (1.f / 12.f));
-            const float k = lam * D[c];
-            lW[b1] += k * (o1 ? 1.f : -1.f) * w2;
-            lW[b2] += k * w1 * (o2 ? 1.f : -1.f);
-            lD[b1] += k * sg * D[b2] * (1.f / 12.f);
-            lD[b2] += k * sg * D[b1] * (1.f / 12.f);
+            lam[q] = fmaf(Lc, ampc_lo[c], Lc * ampc[c]);
         }
+        const float u1 = W[b1], u2 = W[b2];
+        const float e10 = lam[1] - lam[0], e32 = lam[3] - lam[2];
+        const float e20 = lam[2] - lam[0], e31 = lam[3] - lam[1];
+        const float a0 = fmaf(u1, e10, lam[0]), a1 = fmaf(u1, e32, lam[2]);
+        const float bil = fmaf(u2, a1 - a0, a0);
+        const float cross = e32 - e10;  // lam0 - lam1 - lam2 + lam3
+        lD[c] += fmaf(D[b1] * d12[b2], cross, bil);
+        lW[b1] += D[c] * fmaf(u2, e32 - e10, e10);
+        lW[b2] += D[c] * fmaf(u1, e31 - e20, e20);
+        const float kc = D[c] * cross;
+        lD[b1] = fmaf(kc, d12[b2], lD[b1]);
+        lD[b2] = fmaf(kc, d12[b1], lD[b2]);
     }
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
