@@ -93,11 +93,13 @@ def test_sort_vjp_moves_adjoints_back():
 
 
 @pytest.mark.parametrize("drift_steps,n", [(0, (16, 16, 8)), (25, (16, 16, 8)), (0, (40, 2, 16)),
-                                           (25, (40, 2, 16))])
+                                           (25, (40, 2, 16)), (0, (15, 9, 7)), (25, (15, 9, 7))])
 def test_one_step_vjp_matches_oracle(drift_steps, n):
     """One-step VJP against the oracle's; with drift_steps unsorted steps
     first, some particles are outside their tile window and take the
-    global-memory path.  The 40 x 2 x 16 grid gets the 16 x 2 x 8 tiles."""
+    global-memory path.  The 40 x 2 x 16 grid gets the 16 x 2 x 8 tiles;
+    15 x 9 x 7 has ragged tiles on every axis and an odd number of points
+    (the accumulators are cleared float by float)."""
     import torch
     d = (1.0, 0.9, 1.1)
     rng = np.random.default_rng(5)
