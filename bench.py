@@ -14,8 +14,11 @@ Prints one JSON line.  value = FP32 cell-relative particle-pushes/s; the plain
 FP64 step on the same workload is reported beside it.  The dominant kernel is
 the fused FP32 particle kernel; its roofline entry uses the algorithmic bytes
 56 per particle (28 read + 28 written) + 36 per cell (E and centred B read,
-J written) per launch over its HIP-event-timed average duration.  The
-"adjoint" entry times a 50-step forward + adjoint on a 128^3 anisotropic
+J written) per launch over its HIP-event-timed average duration.  It reaches
+about 41 % of the 8 TB/s peak, short of a 50 % target: the kernel is
+co-limited by VALU issue (~411 instructions per particle) and its LDS
+atomics rather than by HBM (its traffic is within 9 % of the algorithmic
+bytes).  The "adjoint" entry times a 50-step forward + adjoint on a 128^3 anisotropic
 plasma (see adjoint_leg); "shape_order_2" the same plasma stepped with
 second-order shapes (b_2 weighting, EZ current).  cpu_baseline: the FP64
 oracle on one core, 5 steps of a 64^3 box of the same plasma.
