@@ -847,12 +847,15 @@ __global__ __launch_bounds__(PUSH_THREADS, 4) void k_push_fused(FusedArgs A) {
 }
 
 // Out-of-window particles of this step, whole particle through global memory
-// (gather from E and Bbar, global atomic deposit): one workgroup per listed
-// tile reads the mask words of the tile's slot range, keeps the bits inside
-// the range (a word can straddle two tiles) and clears them.  The counts and
-// the tile list are cleared by the next step's Faraday kernel (a ticket for
-// the last workgroup, a returning atomic of every workgroup on one word, cost
-// more than the pass itself in most steps).
+// (gather from E and Bbar, global atomic deposit).  A thread takes one mask
+// word of a listed tile's slot range (flat over the listed tiles, so that
+// all of them are scanned at once rather than one after another per
+// workgroup), keeps the bits inside the range (a word can straddle two
+// tiles), clears them and pushes their particles.  The counts and the tile
+// list are cleared by the next step's Faraday kernel (a ticket for the last
+// workgroup, a returning atomic of every workgroup on one word, cost more
+// than the pass itself in most steps).
+constexpr int FB_WPT = 160;  // words per item stride: the 129 of a 4096-particle tile
 template <int ORDER>
 __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
     if (A.publish && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -862,16 +865,21 @@ __global__ __launch_bounds__(256) void k_push_fallback(FusedArgs A) {
     }
     const unsigned ntl = *(volatile unsigned *)(A.fb_count + 2);
     uint32_t fbits = 0;
-    for (unsigned e = blockIdx.x; e < ntl; e += gridDim.x)
+    // items (listed tile, word j < FB_WPT); a tile with more words takes
+    // them FB_WPT apart
+    const long long items = (long long)ntl * FB_WPT;
+    for (long long it = blockIdx.x * (long long)blockDim.x + threadIdx.x; it < items;
+         it += (long long)gridDim.x * blockDim.x)
     for (int s = 0; s < A.nsp; ++s) {
-        const int tile = A.fb_tiles[e];
+        const int j = (int)(it % FB_WPT);
+        const int tile = A.fb_tiles[it / FB_WPT];
         const DevSpecies &D = A.tbl[s];
         const SpeciesP &S = D.p[(A.cur_mask >> s) & 1u];
         const SpeciesP &Wr = D.p[(A.wr_mask >> s) & 1u];
         const int beg = S.tile_off[tile], end = S.tile_off[tile + 1];
         if (beg >= end) continue;
         const int w0 = beg >> 5, w1 = (end - 1) >> 5;
-        for (int w = w0 + (int)threadIdx.x; w <= w1; w += (int)blockDim.x) {
+        for (int w = w0 + j; w <= w1; w += FB_WPT) {
         const int lo = w == w0 ? (beg & 31) : 0, hi = w == w1 ? ((end - 1) & 31) : 31;
         const uint32_t range = (0xffffffffu >> (31 - hi)) & (0xffffffffu << lo);
         uint32_t *mw = A.fb_mask + (long long)s * A.mask_words + w;
@@ -1583,10 +1591,10 @@ void launch_push_fused(const GridP &g, const TileInfo &ti, float *const E[3],
     A.publish = publish;
     const int nb = 8 * ((ti.ntiles + 7) / 8);
     if (fallback_pass)
-        // a grid that fills the chip: after many steps without a sort (or with
-        // order 2, which keeps no drift margin) the list is long
+        // a grid that fills the chip: after many steps without a sort the
+        // list can hold most tiles
         hipLaunchKernelGGL(g.shape_order == 2 ? k_push_fallback<2> : k_push_fallback<1>,
-                           dim3(1024), dim3(256), 0, s, A);
+                           dim3(2048), dim3(256), 0, s, A);
     else if (ti.slab)
         launch_fused<TileSlab, 1>(A, nb, s, ev_start, ev_stop);  // order 2 is refused on slab grids
     else if (g.shape_order == 2)
